@@ -1,0 +1,296 @@
+"""Pins of the CPU oracle against things other than itself: brute force over
+the lattice points with explicit time-frequency shift operators, full-length
+library FFTs, closed forms, the multi-window identity, adjointness, the dense
+frame operator, finite differences and torch autograd."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from dgt_inputs import complex_normal, gaussian_window
+from tests.conftest import feasible_lattices
+
+RNG = np.random.default_rng(20240611)
+
+
+def rand_c(*shape):
+    return (RNG.standard_normal(shape) + 1j * RNG.standard_normal(shape)) / math.sqrt(2)
+
+
+def rel(x, y):
+    return float(np.linalg.norm(np.ravel(x - y)) / max(np.linalg.norm(np.ravel(y)), 1e-300))
+
+
+# ---------------------------------------------------------------------------
+# Brute force: enumerate the lattice A Z_L^2 with A = [[a, 0], [s, b]]
+# (Prop. 1), build each atom M_omega T_x g from the operator definitions
+# (Section 2.1) and index the frequencies of each time position upward from
+# the lowest non-negative one (eq. (DGT)).
+# ---------------------------------------------------------------------------
+
+def lattice_points(L, a, M, lam1, lam2):
+    b = L // M
+    s = b * lam1 // lam2
+    pts = set()
+    for k1 in range(L):
+        for k2 in range(L // b + 1):
+            pts.add(((a * k1) % L, (s * k1 + b * k2) % L))
+    return pts
+
+
+def brute_force_atoms(g, L, a, M, lam1, lam2):
+    """Matrix whose column (n, m) is the atom M_omega T_{na} g, with omega the
+    m-th smallest lattice frequency above time position n a."""
+    pts = lattice_points(L, a, M, lam1, lam2)
+    N = L // a
+    assert len(pts) == L * L // (a * (L // M))  # |Lambda| = L^2/(ab)
+    l = np.arange(L)
+    T = lambda x: np.eye(L)[(l - x) % L]               # (T_x f)(l) = f(l - x)
+    Mo = lambda w: np.diag(np.exp(2j * np.pi * l * w / L))
+    atoms = np.zeros((L, N, M), dtype=np.complex128)
+    for n in range(N):
+        freqs = sorted(w for (x, w) in pts if x == (n * a) % L)
+        assert len(freqs) == M
+        for m, w in enumerate(freqs):
+            atoms[:, n, m] = Mo(w) @ (T(n * a) @ g)
+    return atoms
+
+
+FIG1 = [(36, 6, 6, 0, 1), (36, 6, 6, 1, 2), (36, 6, 6, 1, 3), (36, 6, 6, 2, 3)]
+SMALL_LATTICES = FIG1 + [(16, 4, 8, 1, 2), (60, 5, 6, 1, 2), (72, 6, 4, 1, 3),
+                         (64, 4, 8, 1, 4), (24, 2, 6, 1, 2), (144, 6, 12, 1, 2)]
+
+
+@pytest.mark.parametrize("lat", SMALL_LATTICES)
+def test_direct_and_fold_match_brute_force(lat):
+    L, a, M, l1, l2 = lat
+    f, g = rand_c(L), rand_c(L)
+    A = brute_force_atoms(g, L, a, M, l1, l2)
+    c_bf = np.einsum("l,lnm->nm", f, np.conj(A))       # <f, atom>
+    assert rel(oracle.dgt_direct(f, g, a, M, l1, l2), c_bf) < 1e-13
+    assert rel(oracle.dgt_fold(f, g, a, M, l1, l2), c_bf) < 1e-13
+    assert rel(oracle.dgt_multiwindow(f, g, a, M, l1, l2), c_bf) < 1e-13
+
+
+def test_plus_one_reading_is_rejected():
+    """The window argument read literally as l - a n + 1 disagrees with the
+    brute-force STFT samples; the 0-based reading l - a n agrees."""
+    L, a, M, l1, l2 = 36, 6, 6, 1, 2
+    f, g = rand_c(L), rand_c(L)
+    c_bf = np.einsum("l,lnm->nm", f, np.conj(brute_force_atoms(g, L, a, M, l1, l2)))
+    shifted = np.roll(g, -1)  # shifted(x) = g(x + 1), so shifted(l - a n) = g(l - a n + 1)
+    assert rel(oracle.dgt_fold(f, shifted, a, M, l1, l2), c_bf) > 0.1
+
+
+def test_frequency_index_matches_lattice():
+    for (L, a, M, l1, l2) in SMALL_LATTICES:
+        pts = lattice_points(L, a, M, l1, l2)
+        N, b = L // a, L // M
+        fr = oracle.coefficient_frequencies(N, M, b, l1, l2)
+        for n in range(N):
+            assert sorted(w for (x, w) in pts if x == n * a % L) == list(fr[n])
+
+
+@pytest.mark.parametrize("lat", feasible_lattices(max_L=48, max_lam2=4)[::7])
+def test_fold_equals_full_length_fft_samples(lat):
+    """c(m, n) is the STFT sample V_g f(n a, b m + sigma_n); each column of the
+    STFT is a length-L library FFT of the windowed signal."""
+    L, a, M, l1, l2 = lat
+    f, g = rand_c(L), rand_c(L)
+    N, b = L // a, L // M
+    fr = oracle.coefficient_frequencies(N, M, b, l1, l2)
+    ref = np.empty((N, M), dtype=np.complex128)
+    for n in range(N):
+        ref[n] = np.fft.fft(f * np.conj(np.roll(g, n * a)))[fr[n]]
+    assert rel(oracle.dgt_fold(f, g, a, M, l1, l2), ref) < 1e-13
+    assert rel(oracle.dgt_multiwindow(f, g, a, M, l1, l2), ref) < 1e-13
+
+
+def test_separable_is_subsampled_stft():
+    for (L, a, M) in [(48, 4, 12), (60, 6, 10), (64, 1, 64), (30, 5, 6)]:
+        f, g = rand_c(L), rand_c(L)
+        N, b = L // a, L // M
+        ref = np.array([np.fft.fft(f * np.conj(np.roll(g, n * a)))[::b] for n in range(N)])
+        assert rel(oracle.dgt_separable(f, g, a, M), ref) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Closed forms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lat", SMALL_LATTICES)
+def test_closed_forms(lat):
+    L, a, M, l1, l2 = lat
+    N, b = L // a, L // M
+    f = rand_c(L)
+    sig = (b * oracle.offsets(N, l1, l2)) // l2
+    n = np.arange(N)[:, None]
+    m = np.arange(M)[None, :]
+    # g = delta_0: c(m, n) = f(n a) exp(-2 pi i n a (b m + sigma_n) / L)
+    delta = np.zeros(L, complex)
+    delta[0] = 1
+    ref = f[(n * a) % L] * np.exp(-2j * np.pi * (((n * a) * (b * m + sig[:, None])) % L) / L)
+    assert rel(oracle.dgt_fold(f, delta, a, M, l1, l2), ref) < 1e-13
+    # g constant 1/sqrt(L): c(m, n) = fhat(b m + sigma_n) / sqrt(L)
+    const = np.full(L, 1 / math.sqrt(L), complex)
+    ref = np.fft.fft(f)[b * m + sig[:, None]] / math.sqrt(L)
+    assert rel(oracle.dgt_fold(f, const, a, M, l1, l2), ref) < 1e-13
+    # f = delta_{l0}: c(m, n) = conj(g(l0 - n a)) exp(-2 pi i l0 (b m + sigma_n) / L)
+    g = rand_c(L)
+    l0 = L // 3
+    d = np.zeros(L, complex)
+    d[l0] = 1
+    ref = np.conj(g[(l0 - n * a) % L]) * np.exp(-2j * np.pi * ((l0 * (b * m + sig[:, None])) % L) / L)
+    assert rel(oracle.dgt_fold(d, g, a, M, l1, l2), ref) < 1e-13
+
+
+def test_lattice_covariance():
+    """Shifting the signal by a lattice point (a, s) permutes coefficients:
+    c_{M_s T_a f}(m, n) = exp(-2 pi i a (b m' + sigma_{n-1}) / L) c_f(m', n-1)
+    with m' = m + (sigma_n - s - sigma_{n-1}) / b mod M."""
+    for (L, a, M, l1, l2) in SMALL_LATTICES:
+        N, b = L // a, L // M
+        s = b * l1 // l2
+        f, g = rand_c(L), rand_c(L)
+        l = np.arange(L)
+        fs = np.exp(2j * np.pi * (l * s % L) / L) * np.roll(f, a)
+        c0 = oracle.dgt_fold(f, g, a, M, l1, l2)
+        c1 = oracle.dgt_fold(fs, g, a, M, l1, l2)
+        sig = (b * oracle.offsets(N, l1, l2)) // l2
+        for n in range(N):
+            nm = (n - 1) % N
+            dm = sig[n] - s - sig[nm]
+            assert dm % b == 0
+            mp = (np.arange(M) + dm // b) % M
+            ph = np.exp(-2j * np.pi * ((a * (b * mp + sig[nm])) % L) / L)
+            assert rel(c1[n], ph * c0[nm, mp]) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Adjoint, frame operator, dual window
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lat", SMALL_LATTICES)
+def test_adjoint(lat):
+    L, a, M, l1, l2 = lat
+    N = L // a
+    g = rand_c(L)
+    A = brute_force_atoms(g, L, a, M, l1, l2)
+    c = rand_c(N, M)
+    ref = np.einsum("lnm,nm->l", A, c)          # synthesis = sum c(m,n) atom
+    assert rel(oracle.idgt_adjoint(c, g, a, M, l1, l2), ref) < 1e-13
+    f = rand_c(L)
+    lhs = np.vdot(c, oracle.dgt_fold(f, g, a, M, l1, l2))       # <Cf, c>^*
+    rhs = np.vdot(oracle.idgt_adjoint(c, g, a, M, l1, l2), f)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("lat", SMALL_LATTICES)
+def test_frame_operator_and_dual(lat):
+    L, a, M, l1, l2 = lat
+    g = gaussian_window(L, a, M)
+    A = brute_force_atoms(g, L, a, M, l1, l2).reshape(L, -1)
+    S = A @ A.conj().T                          # dense frame operator
+    b = L // M
+    blocks = oracle.frame_blocks(g, a, M, l1, l2)
+    i = np.arange(b)
+    for r in range(M):
+        assert np.allclose(blocks[r], S[np.ix_(r + i * M, r + i * M)], atol=1e-13)
+    x = rand_c(L)
+    assert rel(oracle.frame_operator_apply(x, g, a, M, l1, l2), S @ x) < 1e-13
+    ev = np.linalg.eigvalsh(S)
+    lo, hi = oracle.frame_bounds(g, a, M, l1, l2)
+    assert abs(lo - ev.min()) < 1e-10 * ev.max() and abs(hi - ev.max()) < 1e-10 * ev.max()
+    if lo < 1e-8 * hi:
+        return  # not a frame (redundancy 1 lattices can be singular)
+    gd = oracle.dual_window(g, a, M, l1, l2)
+    assert rel(S @ gd, g) < 1e-12
+    f = rand_c(L)
+    rec = oracle.idgt_adjoint(oracle.dgt_fold(f, g, a, M, l1, l2), gd, a, M, l1, l2)
+    assert rel(rec, f) < 1e-11
+    # ||C f||^2 = <S f, f>
+    c = oracle.dgt_fold(f, g, a, M, l1, l2)
+    assert abs(np.vdot(c, c).real - np.vdot(f, S @ f).real) < 1e-11 * np.vdot(c, c).real
+
+
+def test_painless_dual_closed_form():
+    """Separable lattice and a window supported in [0, M): S is diagonal with
+    entries M sum_n |g(l - n a)|^2, so the dual is g / that diagonal."""
+    L, a, M = 48, 4, 12
+    g = np.zeros(L, complex)
+    g[:M] = RNG.uniform(0.5, 1.5, M) + 0.3j * RNG.uniform(-1, 1, M)
+    diag = M * sum(np.abs(np.roll(g, n * a)) ** 2 for n in range(L // a))
+    assert rel(oracle.dual_window(g, a, M, 0, 1), g / diag) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Gradients
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lat", [(36, 6, 6, 1, 2), (72, 6, 4, 1, 3), (64, 4, 8, 1, 4)])
+def test_gradients_finite_differences(lat):
+    L, a, M, l1, l2 = lat
+    f, g = rand_c(L), rand_c(L)
+    T = np.abs(oracle.dgt_fold(rand_c(L), g, a, M, l1, l2)) ** 2
+    loss0, gf, gg = oracle.loss_and_grads(f, g, T, a, M, l1, l2)
+    h = 1e-6
+    for _ in range(4):
+        d = rand_c(L)
+        lp = oracle.loss_and_grads(f + h * d, g, T, a, M, l1, l2)[0]
+        lm = oracle.loss_and_grads(f - h * d, g, T, a, M, l1, l2)[0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - np.vdot(gf, d).real) < 1e-6 * max(1.0, abs(fd))
+        lp = oracle.loss_and_grads(f, g + h * d, T, a, M, l1, l2)[0]
+        lm = oracle.loss_and_grads(f, g - h * d, T, a, M, l1, l2)[0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - np.vdot(gg, d).real) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_gradients_match_torch_autograd_on_dense_atoms():
+    torch = pytest.importorskip("torch")
+    L, a, M, l1, l2 = 36, 6, 6, 1, 3
+    f, g = rand_c(L), rand_c(L)
+    T = np.abs(oracle.dgt_fold(rand_c(L), g, a, M, l1, l2)) ** 2
+    _, gf, gg = oracle.loss_and_grads(f, g, T, a, M, l1, l2)
+    # coefficients as an explicit sum over lattice points: c = sum_l f(l) conj(atom(l))
+    pts = sorted(lattice_points(L, a, M, l1, l2))
+    ft = torch.tensor(f, requires_grad=True)
+    gt = torch.tensor(g, requires_grad=True)
+    l = torch.arange(L)
+    Tt = torch.tensor(T)
+    loss = 0
+    N = L // a
+    for n in range(N):
+        freqs = sorted(w for (x, w) in pts if x == n * a)
+        shifted = gt[(l - n * a) % L]
+        for m, w in enumerate(freqs):
+            mod = torch.exp(2j * math.pi * ((l * w) % L).double() / L)
+            c = torch.sum(ft * torch.conj(mod * shifted))
+            loss = loss + (c.abs() ** 2 - Tt[n, m]) ** 2
+    loss.backward()
+    assert rel(ft.grad.numpy(), gf) < 1e-12
+    assert rel(gt.grad.numpy(), gg) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Sweep: the three evaluation orders agree on every feasible small lattice
+# ---------------------------------------------------------------------------
+
+def test_sweep_orders_agree():
+    lats = feasible_lattices(max_L=40, max_lam2=4)
+    assert len(lats) > 200
+    for (L, a, M, l1, l2) in lats[::3]:
+        f, g = rand_c(L), rand_c(L)
+        c1 = oracle.dgt_direct(f, g, a, M, l1, l2)
+        assert rel(oracle.dgt_fold(f, g, a, M, l1, l2), c1) < 1e-12
+        assert rel(oracle.dgt_multiwindow(f, g, a, M, l1, l2), c1) < 1e-12
+
+
+def test_small_workload_shape():
+    from dgt_inputs import SMALL
+    f = complex_normal(SMALL.L, 1)
+    g = gaussian_window(SMALL.L, SMALL.a, SMALL.M)
+    c = oracle.dgt_fold(f, g, SMALL.a, SMALL.M, SMALL.lam1, SMALL.lam2)
+    assert c.shape == (24, 12)
+    assert abs(np.linalg.norm(g) - 1) < 1e-14
