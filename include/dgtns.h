@@ -1,0 +1,200 @@
+/*
+ * dgtns.h -- C-ABI of libdgtns: the discrete Gabor transform on a
+ * nonseparable lattice by the shear method, on AMD Instinct MI355X (gfx950).
+ *
+ * Transform (eq. (DGT), Section 2.1).  For a signal f and a window g of
+ * length L, time step a, M channels (frequency step b = L/M) and lattice
+ * offset lambda = lambda1/lambda2, the coefficients are
+ *
+ *     c(m, n) = sum_{l in Z_L} f(l) conj(g(l - n a)) exp(-2 pi i l (m + w(n)) / M),
+ *     w(n)    = (n lambda1 mod lambda2) / lambda2,   m in Z_M, n in Z_N, N = L/a.
+ *
+ * (The paper's window argument "l - an + 1" is read as the 0-based l - n a.)
+ * The library computes this with the shear algorithm (Alg. 1): a time shear
+ * and, when needed, a frequency shear (Thm. 2) applied as chirp
+ * multiplications (Lemma 1), a separable DGT by window factorisation
+ * (the full-window algorithm of Section 4), and a phase/index correction
+ * (Prop. 7).
+ *
+ * Conventions for every call:
+ *   - Complex data is interleaved (re, im).  DGTNS_C64 plans use float,
+ *     DGTNS_C128 plans double, for signals, coefficients and windows given to
+ *     the hot-path calls; windows given to dgtns_set_window and
+ *     dgtns_dual_window are always complex128.
+ *   - Signal layout f[B][L] (contiguous), coefficient layout c[B][N][M]:
+ *     coefficient (m, n) of signal k at c[(k N + n) M + m] (channel fastest).
+ *   - All pointers named *_dev are device pointers on the current HIP device.
+ *     The caller owns all memory: the library never allocates device memory.
+ *     Persistent plan memory is handed over once with dgtns_plan_bind, and
+ *     each call takes a caller-provided workspace whose size is given by
+ *     dgtns_workspace_bytes.
+ *   - Device work is enqueued asynchronously on `stream` (a hipStream_t; NULL
+ *     means the default stream).  Calls return after enqueueing.
+ *   - Argument and state errors are detected synchronously before any work is
+ *     enqueued; outputs are then left untouched.  Launch failures return
+ *     DGTNS_EDEVICE.  No call throws across the ABI.  A message for the last
+ *     error of the calling thread is available from dgtns_last_error().
+ *   - A plan is immutable once its window is set; calls on one plan may run
+ *     concurrently on different streams if each uses its own workspace.
+ */
+#ifndef DGTNS_H
+#define DGTNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dgtns_plan_s* dgtns_plan;
+
+enum dgtns_status {
+  DGTNS_OK = 0,
+  DGTNS_EINVAL = 1,       /* bad argument (null pointer, non-positive size, bad dtype, ...) */
+  DGTNS_ELATTICE = 2,     /* (L, a, M, lambda) is not a lattice of Z_L^2 (Prop. 1, Prop. 8) */
+  DGTNS_ENOTFRAME = 3,    /* the frame operator is singular (dual window does not exist) */
+  DGTNS_EUNSUPPORTED = 4, /* valid lattice outside the implemented sizes (see message) */
+  DGTNS_EDEVICE = 5,      /* a HIP call or kernel launch failed */
+  DGTNS_EWORKSPACE = 6,   /* workspace too small, or persistent memory too small */
+  DGTNS_ESTATE = 7        /* plan not bound, or window not set */
+};
+
+enum dgtns_dtype { DGTNS_C64 = 0, DGTNS_C128 = 1 };
+
+enum dgtns_branch {
+  DGTNS_SEPARABLE = 0,  /* lambda = 0: no shear */
+  DGTNS_TIME_SHEAR = 1, /* s0 = 0: time shear only (Alg. 1, first branch) */
+  DGTNS_FREQ_SHEAR = 2  /* s0 != 0: frequency and time shear (Alg. 1, second branch) */
+};
+
+enum dgtns_op {
+  DGTNS_OP_FORWARD = 0,
+  DGTNS_OP_ADJOINT = 1,
+  DGTNS_OP_WINDOW_GRAD = 2,
+  DGTNS_OP_SET_WINDOW = 3,
+  DGTNS_OP_DUAL = 4
+};
+
+typedef struct {
+  int64_t L, a, M, lambda1, lambda2;
+  int64_t b;        /* frequency step L/M */
+  int64_t N;        /* number of time positions L/a */
+  int64_t s;        /* absolute shear of the normal form, b lambda1 / lambda2 (Section 2.1) */
+  int64_t s0, s1;   /* frequency shear and time shear, A = U_{s0,s1} D V (Thm. 2) */
+  int64_t b_r;      /* frequency step of the sheared separable lattice (Alg. 1) */
+  int32_t branch;   /* enum dgtns_branch */
+  int32_t dtype;    /* enum dgtns_dtype */
+  /* separable lattice the factorised DGT runs on, and its constants c, d, p, q
+     (eq. (cd), eq. (pq)): time step inner_a, inner_M channels */
+  int64_t inner_a, inner_M, c, d, p, q;
+  int64_t max_batch;
+  size_t persistent_bytes; /* device bytes dgtns_plan_bind needs */
+} dgtns_plan_info_t;
+
+/* Human-readable name of a status code (static storage). */
+const char* dgtns_status_string(int status);
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char* dgtns_last_error(void);
+
+/*
+ * Create a plan (host only; no device work).  Validates the lattice (a | L,
+ * M | L, 0 <= lambda1 < lambda2 coprime, lambda = 0 written 0/1, and L a
+ * multiple of lambda2 lcm(a, M), Prop. 8), finds the shear factorisation
+ * (Thm. 2; a time shear alone when a | s + k b, Prop. 9) and builds all
+ * tables on the host.  dtype is enum dgtns_dtype; max_batch bounds B in later
+ * calls.  Errors: DGTNS_EINVAL, DGTNS_ELATTICE, DGTNS_EUNSUPPORTED (transform
+ * lengths that are not 7-smooth or exceed the in-LDS limit, L > 2^30).
+ * On success *plan owns host memory released by dgtns_plan_destroy.
+ */
+int dgtns_plan_create(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1,
+                      int64_t lambda2, int dtype, int64_t max_batch);
+
+/* Fill *info (host only). */
+int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info);
+
+/*
+ * Hand the plan its persistent device memory (persistent_bytes from
+ * dgtns_plan_info, 256-byte aligned) and upload the tables on `stream`.
+ * Blocks until the upload has finished.  The memory stays owned by the
+ * caller and must outlive every call on the plan.  Errors: DGTNS_EINVAL,
+ * DGTNS_EWORKSPACE (bytes too small), DGTNS_EDEVICE.
+ */
+int dgtns_plan_bind(dgtns_plan plan, void* persistent_dev, size_t bytes, void* stream);
+
+/* Workspace bytes needed by operation `op` (enum dgtns_op) for a batch of B. */
+int dgtns_workspace_bytes(dgtns_plan plan, int op, int64_t B, size_t* bytes);
+
+/*
+ * Set the analysis window g_dev (complex128, length L) on `stream`: applies
+ * the time-shear chirp, the frequency shear when s0 != 0 (Alg. 1: chirp,
+ * length-L DFT, second chirp, division by L) and the factorisation (Zak)
+ * transform, all in FP64, and stores the result in the plan's precision.
+ * Needs the plan bound.  Workspace: dgtns_workspace_bytes(DGTNS_OP_SET_WINDOW).
+ */
+int dgtns_set_window(dgtns_plan plan, const void* g_dev, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Forward transform (Alg. 1): c_dev[B][N][M] = DGT of f_dev[B][L].  If
+ * real_input != 0, f_dev holds real samples (float or double by the plan
+ * dtype) and is read as complex with zero imaginary part.  Needs the window
+ * set.  Workspace: dgtns_workspace_bytes(DGTNS_OP_FORWARD, B).
+ */
+int dgtns_forward(dgtns_plan plan, const void* f_dev, int real_input, void* c_dev, int64_t B,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Adjoint (synthesis) transform, the adjoint of eq. (DGT):
+ * f_dev[B][L](l) = sum_{m,n} c(m, n) g(l - n a) exp(2 pi i l (m + w(n)) / M).
+ * Computed as the adjoint of every stage of Alg. 1 in reverse order.
+ * Workspace: dgtns_workspace_bytes(DGTNS_OP_ADJOINT, B).
+ */
+int dgtns_adjoint(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/*
+ * Gradient of a real loss with respect to the window, summed over the batch.
+ * Given signals f_dev[B][L] and the loss gradient gc_dev[B][N][M] with
+ * respect to the coefficients (convention dLoss/dRe + i dLoss/dIm), writes
+ * gg_dev[L] (plan dtype) with gg(j) = sum_k sum_n f_k(j + n a) conj(y_{k,n}(j + n a)),
+ * y_{k,n}(l) = sum_m gc_k(m, n) exp(2 pi i l (m + w(n)) / M).
+ * Deterministic (no atomics).  Workspace: DGTNS_OP_WINDOW_GRAD.
+ */
+int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, void* gg_dev,
+                      int64_t B, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Canonical dual window S^{-1} g of the Gabor frame of g_dev (complex128,
+ * length L) on the plan's lattice (Section 2.1, eq. (frameop); computed by
+ * shearing as in Alg. 2, with the time shear undone at the end), in FP64.
+ * gd_dev: complex128[L].  bounds_dev: 2 doubles on the device receiving the
+ * optimal frame bounds (A, B); A == 0 means the system is not a frame and
+ * gd_dev is then undefined (asynchronous calls cannot report
+ * DGTNS_ENOTFRAME; callers check A).  Implemented for p = 1 of the sheared
+ * lattice (DGTNS_EUNSUPPORTED otherwise).  Does not change the plan's window.
+ * Workspace: DGTNS_OP_DUAL.
+ */
+int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* bounds_dev,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Release host memory of the plan (device memory stays with the caller). */
+int dgtns_plan_destroy(dgtns_plan plan);
+
+/*
+ * Host-only planner queries used by tests: the shear factorisation for a
+ * lattice without creating a plan.  out[0..2] = s0, s1, b_r.
+ */
+int dgtns_shearfind(int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2, int64_t* out);
+
+/*
+ * Smallest multiplier of L_min = lambda2 lcm(a, M) for which a time shear
+ * alone suffices, L = n L_min c / c1 (Prop. 9): returns c / c1 in *out.
+ */
+int dgtns_noshear_factor(int64_t a, int64_t M, int64_t lambda1, int64_t lambda2, int64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGTNS_H */

@@ -1,0 +1,195 @@
+"""Torch-facing API over the C-ABI: PyTorch provides device memory and
+streams, libdgtns does all the computation.
+
+    plan = Plan(L, a, M, lam1, lam2, dtype=torch.complex64, max_batch=64)
+    plan.set_window(g)            # any complex/real tensor of length L
+    c = plan.forward(f)           # f: (B, L) -> c: (B, N, M), c[k, n, m] = c_k(m, n)
+    f2 = plan.adjoint(c)          # synthesis (adjoint) operator
+    gd, (A, B) = plan.dual(g)     # canonical dual window (FP64) and frame bounds
+"""
+from __future__ import annotations
+
+from typing import Dict, Optional, Tuple
+
+import torch
+
+from . import _binding as B
+
+_DT = {torch.complex64: B.DGTNS_C64, torch.complex128: B.DGTNS_C128}
+_REAL = {torch.complex64: torch.float32, torch.complex128: torch.float64}
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Plan:
+    """A lattice plan with its tables and window resident in device memory."""
+
+    def __init__(self, L: int, a: int, M: int, lam1: int = 0, lam2: int = 1,
+                 dtype: torch.dtype = torch.complex64, max_batch: int = 64, device=None):
+        if dtype not in _DT:
+            raise ValueError("dtype must be torch.complex64 or torch.complex128")
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdgtns needs a HIP device")
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.dtype = dtype
+        self._h = B.dgtns_plan_create(L, a, M, lam1, lam2, _DT[dtype], max_batch)
+        self.info = B.dgtns_plan_info(self._h)
+        self.L, self.a, self.M, self.lam1, self.lam2 = L, a, M, lam1, lam2
+        self.N = self.info.N
+        self.max_batch = max_batch
+        nbytes = self.info.persistent_bytes
+        # 256-byte alignment: allocate with slack and offset
+        self._persist = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._persist.data_ptr()
+        self._pptr = base + ((-base) % 256)
+        with torch.cuda.device(self.device):
+            B.dgtns_plan_bind(self._h, self._pptr, nbytes, _stream_handle(self.device))
+        self._ws: Dict[Tuple[int, int], torch.Tensor] = {}
+        self.window: Optional[torch.Tensor] = None
+
+    # ------------------------------------------------------------------
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                B.dgtns_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def branch(self) -> int:
+        return self.info.branch
+
+    @property
+    def shear(self) -> Tuple[int, int, int]:
+        return self.info.s0, self.info.s1, self.info.b_r
+
+    def workspace(self, op: int, batch: int, stream: Optional[int] = None) -> Tuple[int, int]:
+        """Workspace pointer and size for op, cached per (op, stream)."""
+        need = B.dgtns_workspace_bytes(self._h, op, batch)
+        key = (op, stream if stream is not None else _stream_handle(self.device))
+        buf = self._ws.get(key)
+        if buf is None or buf.numel() < need:
+            buf = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws[key] = buf
+        return buf.data_ptr(), buf.numel()
+
+    # ------------------------------------------------------------------
+    def set_window(self, g: torch.Tensor) -> None:
+        g64 = g.detach().to(device=self.device, dtype=torch.complex128).contiguous()
+        if g64.shape != (self.L,):
+            raise ValueError(f"window must have shape ({self.L},)")
+        st = _stream_handle(self.device)
+        ws, wsb = self.workspace(B.DGTNS_OP_SET_WINDOW, 1, st)
+        B.dgtns_set_window(self._h, g64.data_ptr(), ws, wsb, st)
+        self.window = g64
+
+    def _signals(self, f: torch.Tensor):
+        if f.dim() == 1:
+            f = f.unsqueeze(0)
+        if f.dim() != 2 or f.shape[1] != self.L:
+            raise ValueError(f"signals must have shape (B, {self.L})")
+        if f.is_complex():
+            f = f.to(device=self.device, dtype=self.dtype).contiguous()
+            return f, 0
+        f = f.to(device=self.device, dtype=_REAL[self.dtype]).contiguous()
+        return f, 1
+
+    def forward(self, f: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Coefficients c[k, n, m] = c_k(m, n) of eq. (DGT) for signals f (B, L)
+        (real or complex)."""
+        squeeze = f.dim() == 1
+        f, real = self._signals(f)
+        nb = f.shape[0]
+        if out is None:
+            out = torch.empty((nb, self.N, self.M), dtype=self.dtype, device=self.device)
+        st = _stream_handle(self.device)
+        ws, wsb = self.workspace(B.DGTNS_OP_FORWARD, nb, st)
+        B.dgtns_forward(self._h, f.data_ptr(), real, out.data_ptr(), nb, ws, wsb, st)
+        return out[0] if squeeze else out
+
+    def adjoint(self, c: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Synthesis f(l) = sum_{m,n} c(m, n) g(l - n a) exp(2 pi i l (m + w(n))/M)."""
+        squeeze = c.dim() == 2
+        if squeeze:
+            c = c.unsqueeze(0)
+        if c.shape[1:] != (self.N, self.M):
+            raise ValueError(f"coefficients must have shape (B, {self.N}, {self.M})")
+        c = c.to(device=self.device, dtype=self.dtype).contiguous()
+        nb = c.shape[0]
+        if out is None:
+            out = torch.empty((nb, self.L), dtype=self.dtype, device=self.device)
+        st = _stream_handle(self.device)
+        ws, wsb = self.workspace(B.DGTNS_OP_ADJOINT, nb, st)
+        B.dgtns_adjoint(self._h, c.data_ptr(), out.data_ptr(), nb, ws, wsb, st)
+        return out[0] if squeeze else out
+
+    def window_grad(self, f: torch.Tensor, gc: torch.Tensor) -> torch.Tensor:
+        """Gradient of a real loss with respect to the window, summed over the
+        batch, given the coefficient gradient gc (B, N, M)."""
+        if f.dim() == 1:
+            f = f.unsqueeze(0)
+            gc = gc.unsqueeze(0)
+        f = f.to(device=self.device, dtype=self.dtype).contiguous()
+        gc = gc.to(device=self.device, dtype=self.dtype).contiguous()
+        nb = f.shape[0]
+        out = torch.empty(self.L, dtype=self.dtype, device=self.device)
+        st = _stream_handle(self.device)
+        ws, wsb = self.workspace(B.DGTNS_OP_WINDOW_GRAD, nb, st)
+        B.dgtns_window_grad(self._h, f.data_ptr(), gc.data_ptr(), out.data_ptr(), nb, ws, wsb, st)
+        return out
+
+    def dual(self, g: Optional[torch.Tensor] = None):
+        """Canonical dual window (complex128) and the frame bounds (A, B)."""
+        g64 = (self.window if g is None else g).detach().to(device=self.device, dtype=torch.complex128).contiguous()
+        gd = torch.empty(self.L, dtype=torch.complex128, device=self.device)
+        bounds = torch.empty(2, dtype=torch.float64, device=self.device)
+        st = _stream_handle(self.device)
+        ws, wsb = self.workspace(B.DGTNS_OP_DUAL, 1, st)
+        B.dgtns_dual_window(self._h, g64.data_ptr(), gd.data_ptr(), bounds.data_ptr(), ws, wsb, st)
+        return gd, bounds
+
+
+def dgt(f: torch.Tensor, plan: Plan) -> torch.Tensor:
+    return plan.forward(f)
+
+
+def idgt(c: torch.Tensor, plan: Plan) -> torch.Tensor:
+    return plan.adjoint(c)
+
+
+class DGTFunction(torch.autograd.Function):
+    """c = DGT_g(f) with gradients for both the signal and the window.
+
+    Backward: grad_f = C_g^* grad_c (the synthesis operator) and
+    grad_g(j) = sum_k sum_n f_k(j + n a) conj(y_{k,n}(j + n a)), both computed
+    by libdgtns."""
+
+    @staticmethod
+    def forward(ctx, f, g, plan: Plan):
+        plan.set_window(g)
+        c = plan.forward(f)
+        ctx.plan = plan
+        ctx.save_for_backward(f, g)
+        return c
+
+    @staticmethod
+    def backward(ctx, gc):
+        f, g = ctx.saved_tensors
+        plan = ctx.plan
+        plan.set_window(g)
+        gf = gg = None
+        if ctx.needs_input_grad[0]:
+            gf = plan.adjoint(gc)
+            if f.dim() == 1:
+                gf = gf.reshape(-1)
+            gf = gf.to(f.dtype)
+        if ctx.needs_input_grad[1]:
+            fc = f if f.is_complex() else f.to(plan.dtype)
+            gg = plan.window_grad(fc, gc).to(g.dtype)
+        return gf, gg, None

@@ -1,0 +1,63 @@
+"""Build libdgtns.so in-tree for gfx950 (hipcc for the HIP sources, g++ for
+the host planner).  Run as ``python -m paper_1307_4569_amd.build``."""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+LIB = os.path.join(HERE, "libdgtns.so")
+ARCH = os.environ.get("DGTNS_OFFLOAD_ARCH", "gfx950")
+
+HIPCC_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
+    # keep hipcc from forming packed FP32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    f"-I{INCLUDE}",
+]
+
+
+def _run(cmd):
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops' is not a recognized" not in l)
+    if p.returncode != 0:
+        raise RuntimeError(f"command failed ({p.returncode}): {' '.join(cmd)}\n{out}")
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    with tempfile.TemporaryDirectory(prefix="dgtns_build_") as tmp:
+        objs = []
+        plan_o = os.path.join(tmp, "plan.o")
+        _run(["g++", "-std=c++17", "-O2", "-fPIC", "-c", os.path.join(CSRC, "plan.cpp"), "-o", plan_o])
+        objs.append(plan_o)
+        procs = []
+        for src in sorted(os.listdir(CSRC)):
+            if src.endswith(".hip"):
+                o = os.path.join(tmp, src[:-4] + ".o")
+                cmd = [hipcc] + HIPCC_FLAGS + ["-c", os.path.join(CSRC, src), "-o", o]
+                procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                                    text=True)))
+                objs.append(o)
+        for cmd, pr in procs:
+            out, _ = pr.communicate()
+            if pr.returncode != 0:
+                out = "\n".join(l for l in out.splitlines() if "packed-fp32-ops' is not a recognized" not in l)
+                raise RuntimeError(f"command failed: {' '.join(cmd)}\n{out}")
+            if verbose and out.strip():
+                print(out)
+        tmp_lib = LIB + ".tmp"
+        _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib] + objs
+             + ["-Wl,-rpath,/opt/rocm/lib"])
+        os.replace(tmp_lib, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,727 @@
+// HIP kernels of the shear DGT (gfx950).
+//
+// Notation: the factorised separable DGT runs on the lattice with time step
+// ai and Mi channels (Alg. 1: (a, M) when s0 = 0, (b_r, N_r) when s0 != 0),
+// L = Mi * bi, c = gcd(ai, Mi), p = ai / c, q = Mi / c, d = bi / p, Ni = d q.
+//
+// Factorisation (the full-window algorithm of Section 4, derived from
+// eq. (DGT) with lambda = 0).  Column r in Z_Mi of the signal is split into p
+// polyphase sub-columns x(r + Mi (j0 + p t)), t in Z_d.  With X_{r,j0} their
+// length-d DFTs and Zg_{u,j0} those of the window,
+//   h_{n0 + q t'}(r) = sum_nu exp(2 pi i nu t'/d) sum_{j0} X_{r,j0}(nu)
+//                       conj(Zg_{u,j0'}(nu)) exp(-2 pi i nu delta/d) / d,
+// where r - n0 ai + Mi j0 = u + Mi (j0' + p delta), u in Z_Mi, j0' in Z_p,
+// and c_r(m, n) = sum_r h_n(r) exp(-2 pi i r m / Mi).  The plan stores
+// Zc = conj(Zg) / d.  Kernel "cols" computes h (all q time offsets n0 of one
+// block of W adjacent columns per work-group, the DFT of the signal columns
+// kept in registers), kernel "rows" the channel DFT of each time position and
+// the post-processing of Alg. 1.
+#pragma once
+#include "fft_core.hpp"
+
+namespace dgtns {
+
+template <typename C> struct ChirpSrc {
+  const C* tab;   // pchirp values per sample (plan precision), or null
+  long long K;    // s (L+1) mod 2L for exact on-the-fly FP64 evaluation when tab is null
+  long long L;    // K == 0 and tab == null: identity
+  int conj;       // multiply by the conjugate chirp
+};
+
+template <typename C> __device__ __forceinline__ C chirp_val(const ChirpSrc<C>& cs, long long l) {
+  using T = decltype(C::x);
+  if (cs.tab) return cs.tab[l];
+  // exp(pi i r / L), r = K (l^2 mod 2L) mod 2L (Lemma 1), exact in integers
+  const long long twoL = 2 * cs.L;
+  const long long l2 = (l * l) % twoL;
+  const long long r = (long long)(((unsigned long long)cs.K * (unsigned long long)l2) % (unsigned long long)twoL);
+  return phase_pi(r, cs.L, T());
+}
+
+template <typename C> __device__ __forceinline__ C apply_chirp(const ChirpSrc<C>& cs, C v, long long l) {
+  if (!cs.tab && cs.K == 0) return v;
+  C p = chirp_val(cs, l);
+  if (cs.conj) p = cconj(p);
+  return cmul_comp(v, p);
+}
+
+template <typename C> __device__ __forceinline__ C load_sig(const void* x, int real_in, long long idx) {
+  using T = decltype(C::x);
+  if (real_in) return mk<C>(reinterpret_cast<const T*>(x)[idx], T(0));
+  return reinterpret_cast<const C*>(x)[idx];
+}
+
+// exp(-2 pi i e / n) (sign = -1) or its conjugate, from a table or on the fly
+template <typename C> __device__ __forceinline__ C root_at(const C* tab, long long e, long long n, int inv) {
+  using T = decltype(C::x);
+  C w;
+  if (tab) {
+    w = tab[e];
+  } else {
+    w = cconj(phase_pi(2 * e, n, T()));  // exp(-2 pi i e / n)
+  }
+  return inv ? cconj(w) : w;
+}
+
+// Window-Zak coefficient used by the factorisation for output column r, time
+// offset n0 and polyphase index j0: Zc_{u,j0'}(nu) exp(-2 pi i nu delta / d).
+template <typename C>
+__device__ __forceinline__ C zc_coef(const C* zc, const C* tw, int r, int n0, int j0, int nu, int ai, int Mi,
+                                     int p, int d) {
+  const int v = r - n0 * ai + Mi * j0;  // in (-Mi p, Mi p)
+  int u = v % Mi;
+  if (u < 0) u += Mi;
+  const int j1 = (v - u) / Mi;          // in [-p, p)
+  int j0p = j1 % p;
+  if (j0p < 0) j0p += p;
+  C z = zc[((long long)u * p + j0p) * d + nu];
+  if (j1 < 0) z = cmulc(z, tw[nu]);     // delta = -1: multiply by exp(+2 pi i nu / d)
+  return z;
+}
+
+// ----------------------------------------------------------------------------
+// Forward factorisation kernel ("cols").  grid (ceil(Mi/W), B), 512 threads.
+// ----------------------------------------------------------------------------
+template <typename C> struct ColArgs {
+  const void* x;
+  long long xs;
+  int real_in;
+  ChirpSrc<C> chirp;
+  const C* zc;
+  C* H;
+  long long hs;
+  const C* twd;
+  int Mi, ai, d, p, q, W, Sd;
+  FftSched fd;
+};
+
+template <typename C, bool GENP>
+__global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  const int d = A.d, p = GENP ? A.p : 1, W = A.W, Sd = A.Sd, Mi = A.Mi;
+  C* xb = tw + d;
+  C* yb = GENP ? xb + W * p * Sd : xb;
+  for (int e = threadIdx.x; e < d; e += kThreads) tw[e] = A.twd[e];
+  const int r0 = blockIdx.x * W;
+  const long long bo = blockIdx.y;
+  const int b = p * d;
+  for (int e = threadIdx.x; e < W * b; e += kThreads) {
+    const int j = e / W, cc = e - j * W, r = r0 + cc;
+    C v = czero<C>();
+    if (r < Mi) {
+      const long long l = r + (long long)j * Mi;
+      v = apply_chirp(A.chirp, load_sig<C>(A.x, A.real_in, bo * A.xs + l), l);
+    }
+    const int j0 = GENP ? j % p : 0, t = GENP ? j / p : j;
+    xb[(cc * p + j0) * Sd + t] = v;
+  }
+  __syncthreads();
+  fft_lds<C, false>(xb, Sd, A.fd, W * p, tw);
+  const int WD = W * d;
+  constexpr int KX = GENP ? 1 : MaxE<C>::value;
+  C X[KX];
+  if (!GENP) {
+#pragma unroll
+    for (int i = 0; i < KX; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < WD) {
+        const int cc = e / d, nu = e - cc * d;
+        X[i] = xb[cc * Sd + nu];
+      }
+    }
+  }
+  for (int n0 = 0; n0 < A.q; ++n0) {
+    __syncthreads();
+    if (!GENP) {
+#pragma unroll
+      for (int i = 0; i < KX; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        if (e < WD) {
+          const int cc = e / d, nu = e - cc * d, r = r0 + cc;
+          C y = czero<C>();
+          if (r < Mi) {
+            const int v = r - n0 * A.ai;
+            C z;
+            if (v >= 0) {
+              z = A.zc[(long long)v * d + nu];
+            } else {
+              z = cmulc(A.zc[(long long)(v + Mi) * d + nu], tw[nu]);
+            }
+            y = cmul(X[i], z);
+          }
+          yb[cc * Sd + nu] = y;
+        }
+      }
+    } else {
+      for (int e = threadIdx.x; e < WD; e += kThreads) {
+        const int cc = e / d, nu = e - cc * d, r = r0 + cc;
+        C y = czero<C>();
+        if (r < Mi) {
+          for (int j0 = 0; j0 < p; ++j0)
+            y = cadd(y, cmul(xb[(cc * p + j0) * Sd + nu], zc_coef(A.zc, tw, r, n0, j0, nu, A.ai, Mi, p, d)));
+        }
+        yb[cc * Sd + nu] = y;
+      }
+    }
+    __syncthreads();
+    fft_lds<C, true>(yb, Sd, A.fd, W, tw);
+    for (int e = threadIdx.x; e < WD; e += kThreads) {
+      const int t = e / W, cc = e - t * W, r = r0 + cc;
+      if (r < Mi) A.H[bo * A.hs + (long long)(n0 + A.q * t) * Mi + r] = yb[cc * Sd + t];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint factorisation kernel: h*[Ni][Mi] -> signal domain.  Reverse of
+// k_fwd_cols: per n0 a forward DFT over t' of the h* column, multiplied by
+// conj of the window coefficient and accumulated per sub-column, then one
+// unnormalised inverse DFT per sub-column and the conjugate chirp.
+// ----------------------------------------------------------------------------
+template <typename C> struct ColAdjArgs {
+  const C* H;
+  long long hs;
+  const C* zc;
+  const C* twd;
+  ChirpSrc<C> chirp;
+  C* y;
+  long long ys;
+  int Mi, ai, d, p, q, W, Sd;
+  FftSched fd;
+};
+
+template <typename C, bool GENP>
+__global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  const int d = A.d, p = GENP ? A.p : 1, W = A.W, Sd = A.Sd, Mi = A.Mi;
+  C* xb = tw + d;
+  C* yb = xb + W * p * Sd;
+  for (int e = threadIdx.x; e < d; e += kThreads) tw[e] = A.twd[e];
+  const int r0 = blockIdx.x * W;
+  const long long bo = blockIdx.y;
+  const int WD = W * d;
+  constexpr int KX = GENP ? 1 : MaxE<C>::value;
+  C acc[KX];
+#pragma unroll
+  for (int i = 0; i < KX; ++i) acc[i] = czero<C>();
+  if (GENP)
+    for (int e = threadIdx.x; e < W * p * Sd; e += kThreads) xb[e] = czero<C>();
+  for (int n0 = 0; n0 < A.q; ++n0) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < WD; e += kThreads) {
+      const int t = e / W, cc = e - t * W, r = r0 + cc;
+      yb[cc * Sd + t] = r < Mi ? A.H[bo * A.hs + (long long)(n0 + A.q * t) * Mi + r] : czero<C>();
+    }
+    __syncthreads();
+    fft_lds<C, false>(yb, Sd, A.fd, W, tw);
+    if (!GENP) {
+#pragma unroll
+      for (int i = 0; i < KX; ++i) {
+        const int e = threadIdx.x + i * kThreads;
+        if (e < WD) {
+          const int cc = e / d, nu = e - cc * d, r = r0 + cc;
+          if (r < Mi) {
+            const int v = r - n0 * A.ai;
+            C z;
+            if (v >= 0) {
+              z = A.zc[(long long)v * d + nu];
+            } else {
+              z = cmulc(A.zc[(long long)(v + Mi) * d + nu], tw[nu]);
+            }
+            acc[i] = cadd(acc[i], cmulc(yb[cc * Sd + nu], z));
+          }
+        }
+      }
+    } else {
+      for (int e = threadIdx.x; e < WD; e += kThreads) {
+        const int cc = e / d, nu = e - cc * d, r = r0 + cc;
+        if (r < Mi) {
+          const C yv = yb[cc * Sd + nu];
+          for (int j0 = 0; j0 < p; ++j0) {
+            C& a = xb[(cc * p + j0) * Sd + nu];
+            a = cadd(a, cmulc(yv, zc_coef(A.zc, tw, r, n0, j0, nu, A.ai, Mi, p, d)));
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (!GENP) {
+#pragma unroll
+    for (int i = 0; i < KX; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < WD) {
+        const int cc = e / d, nu = e - cc * d;
+        xb[cc * Sd + nu] = acc[i];
+      }
+    }
+    __syncthreads();
+  }
+  fft_lds<C, true>(xb, Sd, A.fd, W * p, tw);
+  const int b = p * d;
+  for (int e = threadIdx.x; e < W * b; e += kThreads) {
+    const int j = e / W, cc = e - j * W, r = r0 + cc;
+    if (r < Mi) {
+      const long long l = r + (long long)j * Mi;
+      const int j0 = GENP ? j % p : 0, t = GENP ? j / p : j;
+      A.y[bo * A.ys + l] = apply_chirp(A.chirp, xb[(cc * p + j0) * Sd + t], l);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Row kernels: channel DFT per time position plus the post-processing of
+// Alg. 1, and the adjoint.  grid (ceil(Ni/R), B), 512 threads.
+//   MODE 0 (s0 = 0): c((m + rho_n) mod M, n) = E_n c_r(m, n), tables E, rho.
+//   MODE 1 (s0 != 0): row = inner position m in Z_{M_r}, FFT over the N_r
+//     inner channels k'; with k = -k' mod N_r,
+//       sq = C1 k + C2 m mod 2N,
+//       E  = exp(pi i ((C3 sq^2 - m (C4 m + C5 k)) mod 2N) / N),
+//       m~ = C1 k + C2 m mod N (time position of c),
+//       k~ = floor(((-s1 a_r k + C6 m) mod L) / b) (channel of c),
+//     and c(k~, m~) = E c_r(k', m).
+// ----------------------------------------------------------------------------
+template <typename C> struct RowArgs {
+  const C* H;
+  long long hs;
+  C* c;
+  long long cs;
+  const C* twm;
+  const C* postE;
+  const int* rho;
+  int Mi, Ni, R, Sm;
+  FftSched fm;
+  long long N, L, b, M, K1, K2, K3, K4, K5, C1n, C2n, Kt1, Kt6;
+};
+
+template <typename C>
+__device__ __forceinline__ void shear_map(const RowArgs<C>& A, long long m, long long k, long long* dst, C* E) {
+  using T = decltype(C::x);
+  const long long twoN = 2 * A.N;
+  const long long sq = (A.K1 * k + A.K2 * m) % twoN;
+  const long long sq2 = (sq * sq) % twoN;
+  long long e = (A.K3 * sq2) % twoN;
+  const long long inner = (A.K4 * m + A.K5 * k) % twoN;
+  e = (e - (m * inner) % twoN) % twoN;
+  if (e < 0) e += twoN;
+  *E = phase_pi(e, A.N, T());
+  const long long mt = (A.C1n * k + A.C2n * m) % A.N;
+  const long long kt = ((A.Kt1 * k + A.Kt6 * m) % A.L) / A.b;
+  *dst = mt * A.M + kt;
+}
+
+template <typename C, int MODE>
+__global__ void __launch_bounds__(kThreads) k_fwd_rows(RowArgs<C> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  const int Mi = A.Mi, R = A.R, Sm = A.Sm;
+  C* buf = tw + Mi;
+  for (int e = threadIdx.x; e < Mi; e += kThreads) tw[e] = A.twm[e];
+  const int n_0 = blockIdx.x * R;
+  const long long bo = blockIdx.y;
+  const C* Hb = A.H + bo * A.hs;
+  for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
+    const int row = e / Mi, m = e - row * Mi, n = n_0 + row;
+    buf[row * Sm + m] = n < A.Ni ? Hb[(long long)n * Mi + m] : czero<C>();
+  }
+  __syncthreads();
+  fft_lds<C, false>(buf, Sm, A.fm, R, tw);
+  C* cb = A.c + bo * A.cs;
+  for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
+    const int row = e / Mi, mo = e - row * Mi, n = n_0 + row;
+    if (n >= A.Ni) continue;
+    if (MODE == 0) {
+      int mi = mo - A.rho[n];
+      if (mi < 0) mi += Mi;
+      cb[(long long)n * Mi + mo] = cmul(A.postE[n], buf[row * Sm + mi]);
+    } else {
+      const long long k = mo == 0 ? 0 : Mi - mo;
+      long long dst;
+      C E;
+      shear_map(A, n, k, &dst, &E);
+      cb[dst] = cmul(E, buf[row * Sm + mo]);
+    }
+  }
+}
+
+template <typename C, int MODE>
+__global__ void __launch_bounds__(kThreads) k_adj_rows(RowArgs<C> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  const int Mi = A.Mi, R = A.R, Sm = A.Sm;
+  C* buf = tw + Mi;
+  for (int e = threadIdx.x; e < Mi; e += kThreads) tw[e] = A.twm[e];
+  const int n_0 = blockIdx.x * R;
+  const long long bo = blockIdx.y;
+  const C* cb = A.c + bo * A.cs;
+  for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
+    const int row = e / Mi, m = e - row * Mi, n = n_0 + row;
+    C v = czero<C>();
+    if (n < A.Ni) {
+      if (MODE == 0) {
+        int mo = m + A.rho[n];
+        if (mo >= Mi) mo -= Mi;
+        v = cmulc(cb[(long long)n * Mi + mo], A.postE[n]);
+      } else {
+        const long long k = m == 0 ? 0 : Mi - m;
+        long long src;
+        C E;
+        shear_map(A, n, k, &src, &E);
+        v = cmulc(cb[src], E);
+      }
+    }
+    buf[row * Sm + m] = v;
+  }
+  __syncthreads();
+  fft_lds<C, true>(buf, Sm, A.fm, R, tw);
+  C* Hb = const_cast<C*>(A.H) + bo * A.hs;
+  for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
+    const int row = e / Mi, m = e - row * Mi, n = n_0 + row;
+    if (n < A.Ni) Hb[(long long)n * Mi + m] = buf[row * Sm + m];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Two-pass transform of length L = L1 L2 (frequency shear).  Column pass:
+// transform along the row index of an [n][ncols] array, W adjacent columns per
+// work-group, with a pre-multiplication (chirp) and the inter-pass twiddle
+// exp(-+ 2 pi i k col / L).  Row pass: transform along contiguous rows of an
+// [nrows][n] array and store transposed, out[k nrows + row], with a
+// post-multiplication and a scale.
+// ----------------------------------------------------------------------------
+template <typename C> struct ColFftArgs {
+  const void* x;
+  long long xs;
+  int real_in;
+  C* y;
+  long long ys;
+  ChirpSrc<C> pre;
+  const C* twL;   // length-L table exp(-2 pi i e / L) or null (on the fly)
+  long long L;
+  const C* tws;   // length-n stage twiddles
+  int n, ncols, W, Sn;
+  FftSched fs;
+};
+
+template <typename C, bool INV>
+__global__ void __launch_bounds__(kThreads) k_col_fft(ColFftArgs<C> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  const int n = A.n, W = A.W, Sn = A.Sn, nc = A.ncols;
+  C* buf = tw + n;
+  for (int e = threadIdx.x; e < n; e += kThreads) tw[e] = A.tws[e];
+  const int c0 = blockIdx.x * W;
+  const long long bo = blockIdx.y;
+  for (int e = threadIdx.x; e < W * n; e += kThreads) {
+    const int j = e / W, cc = e - j * W, col = c0 + cc;
+    C v = czero<C>();
+    if (col < nc) {
+      const long long idx = (long long)j * nc + col;
+      v = apply_chirp(A.pre, load_sig<C>(A.x, A.real_in, bo * A.xs + idx), idx);
+    }
+    buf[cc * Sn + j] = v;
+  }
+  __syncthreads();
+  fft_lds<C, INV>(buf, Sn, A.fs, W, tw);
+  for (int e = threadIdx.x; e < W * n; e += kThreads) {
+    const int k = e / W, cc = e - k * W, col = c0 + cc;
+    if (col < nc) {
+      const long long ex = ((long long)k * col) % A.L;
+      A.y[bo * A.ys + (long long)k * nc + col] = cmul(buf[cc * Sn + k], root_at(A.twL, ex, A.L, INV ? 1 : 0));
+    }
+  }
+}
+
+template <typename C> struct RowFftArgs {
+  const C* x;
+  long long xs;
+  C* y;
+  long long ys;
+  ChirpSrc<C> post;
+  decltype(C::x) scale;
+  const C* tws;
+  int n, nrows, R, Sn;
+  FftSched fs;
+};
+
+template <typename C, bool INV>
+__global__ void __launch_bounds__(kThreads) k_row_fft(RowFftArgs<C> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  const int n = A.n, R = A.R, Sn = A.Sn, nr = A.nrows;
+  C* buf = tw + n;
+  for (int e = threadIdx.x; e < n; e += kThreads) tw[e] = A.tws[e];
+  const int row0 = blockIdx.x * R;
+  const long long bo = blockIdx.y;
+  for (int e = threadIdx.x; e < R * n; e += kThreads) {
+    const int rr = e / n, j = e - rr * n, row = row0 + rr;
+    buf[rr * Sn + j] = row < nr ? A.x[bo * A.xs + (long long)row * n + j] : czero<C>();
+  }
+  __syncthreads();
+  fft_lds<C, INV>(buf, Sn, A.fs, R, tw);
+  for (int e = threadIdx.x; e < R * n; e += kThreads) {
+    const int k = e / R, rr = e - k * R, row = row0 + rr;
+    if (row < nr) {
+      const long long idx = (long long)k * nr + row;
+      A.y[bo * A.ys + idx] = cscale(apply_chirp(A.post, buf[rr * Sn + k], idx), A.scale);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Window Zak transform (FP64 in; plan precision conj(Z)/d and/or FP64 Z out).
+// ----------------------------------------------------------------------------
+template <typename CO> struct ZakArgs {
+  const double2* x;
+  ChirpSrc<double2> chirp;
+  CO* zc;
+  double2* z64;
+  const double2* twd;
+  int Mi, d, p, W, Sd;
+  FftSched fd;
+};
+
+template <typename CO>
+__global__ void __launch_bounds__(kThreads) k_zak_fwd(ZakArgs<CO> A) {
+  using TO = decltype(CO::x);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* tw = reinterpret_cast<double2*>(smem_raw);
+  const int d = A.d, p = A.p, W = A.W, Sd = A.Sd, Mi = A.Mi;
+  double2* xb = tw + d;
+  for (int e = threadIdx.x; e < d; e += kThreads) tw[e] = A.twd[e];
+  const int r0 = blockIdx.x * W;
+  const int b = p * d;
+  for (int e = threadIdx.x; e < W * b; e += kThreads) {
+    const int j = e / W, cc = e - j * W, r = r0 + cc;
+    double2 v = make_double2(0, 0);
+    if (r < Mi) {
+      const long long l = r + (long long)j * Mi;
+      v = apply_chirp(A.chirp, A.x[l], l);
+    }
+    xb[(cc * p + j % p) * Sd + j / p] = v;
+  }
+  __syncthreads();
+  fft_lds<double2, false>(xb, Sd, A.fd, W * p, tw);
+  const double inv_d = 1.0 / d;
+  for (int e = threadIdx.x; e < W * b; e += kThreads) {
+    const int cc = e / b, rem = e - cc * b, j0 = rem / d, nu = rem - j0 * d, r = r0 + cc;
+    if (r < Mi) {
+      const double2 z = xb[(cc * p + j0) * Sd + nu];
+      const long long o = ((long long)r * p + j0) * d + nu;
+      if (A.zc) A.zc[o] = mk<CO>(TO(z.x * inv_d), TO(-z.y * inv_d));
+      if (A.z64) A.z64[o] = z;
+    }
+  }
+}
+
+// Inverse window Zak (FP64): x(r + Mi (j0 + p t)) = (1/d) sum_nu Z_{r,j0}(nu) exp(2 pi i nu t / d),
+// followed by a chirp multiplication.
+struct ZakInvArgs {
+  const double2* z;
+  ChirpSrc<double2> chirp;
+  double2* x;
+  const double2* twd;
+  int Mi, d, p, W, Sd;
+  FftSched fd;
+};
+
+__global__ void __launch_bounds__(kThreads) k_zak_inv(ZakInvArgs A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* tw = reinterpret_cast<double2*>(smem_raw);
+  const int d = A.d, p = A.p, W = A.W, Sd = A.Sd, Mi = A.Mi;
+  double2* xb = tw + d;
+  for (int e = threadIdx.x; e < d; e += kThreads) tw[e] = A.twd[e];
+  const int r0 = blockIdx.x * W;
+  const int b = p * d;
+  for (int e = threadIdx.x; e < W * b; e += kThreads) {
+    const int cc = e / b, rem = e - cc * b, j0 = rem / d, nu = rem - j0 * d, r = r0 + cc;
+    xb[(cc * p + j0) * Sd + nu] = r < Mi ? A.z[((long long)r * p + j0) * d + nu] : make_double2(0, 0);
+  }
+  __syncthreads();
+  fft_lds<double2, true>(xb, Sd, A.fd, W * p, tw);
+  const double inv_d = 1.0 / d;
+  for (int e = threadIdx.x; e < W * b; e += kThreads) {
+    const int j = e / W, cc = e - j * W, r = r0 + cc;
+    if (r < Mi) {
+      const long long l = r + (long long)j * Mi;
+      A.x[l] = apply_chirp(A.chirp, cscale(xb[(cc * p + j % p) * Sd + j / p], inv_d), l);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Canonical dual in the Zak domain (p = 1): the frame operator of the
+// separable system is diagonal there with entries
+//   D(u, nu) = Mi sum_{n0 in Z_q} |Zg_{(u - n0 ai) mod Mi}(nu)|^2,
+// so Zd = Zg / D.  Each block also writes its min and max of D.
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_dual_div(const double2* z, double2* zd, double* part, int Mi, int d,
+                                                      int ai, int q, double scale_bounds) {
+  __shared__ double smin[kThreads], smax[kThreads];
+  const long long tot = (long long)Mi * d;
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  double mn = 1e308, mx = 0;
+  if (i < tot) {
+    const int u = int(i / d), nu = int(i - (long long)u * d);
+    double D = 0;
+    for (int n0 = 0; n0 < q; ++n0) {
+      int uu = u - n0 * ai;
+      uu %= Mi;
+      if (uu < 0) uu += Mi;
+      const double2 v = z[(long long)uu * d + nu];
+      D += v.x * v.x + v.y * v.y;
+    }
+    D *= Mi;
+    const double2 v = z[i];
+    zd[i] = D > 0 ? make_double2(v.x / D, v.y / D) : make_double2(0, 0);
+    mn = D * scale_bounds;
+    mx = D * scale_bounds;
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = smin[0];
+    part[2 * blockIdx.x + 1] = smax[0];
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_minmax_final(const double* part, int nparts, double* out) {
+  __shared__ double smin[kThreads], smax[kThreads];
+  double mn = 1e308, mx = 0;
+  for (int i = threadIdx.x; i < nparts; i += kThreads) {
+    mn = fmin(mn, part[2 * i]);
+    mx = fmax(mx, part[2 * i + 1]);
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = smin[0];
+    out[1] = smax[0];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Window gradient (p = 1).  For output window column u and time offset n0 the
+// contributing signal column is r = (u + n0 ai) mod Mi; in the Zak domain
+//   grad Zg_u(nu) += X_r(nu) conj(Hhat_{n0,r}(nu)) exp(-2 pi i nu delta/d) / d,
+// with Hhat the DFT over t' of h*_{n0 + q t'}(r) and delta = -1 when the
+// column index wrapped.  The window gradient is the unnormalised inverse DFT
+// of grad Zg.  grid (ceil(Mi/W), B): one partial per signal, summed by
+// k_batch_sum (deterministic, no atomics).
+// ----------------------------------------------------------------------------
+template <typename C> struct GradArgs {
+  const void* x;
+  long long xs;
+  int real_in;
+  ChirpSrc<C> chirp;
+  const C* H;
+  long long hs;
+  C* part;
+  long long ps;
+  const C* twd;
+  int Mi, ai, d, q, W, Sd;
+  FftSched fd;
+};
+
+template <typename C>
+__global__ void __launch_bounds__(kThreads) k_grad_cols(GradArgs<C> A) {
+  using T = decltype(C::x);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  const int d = A.d, W = A.W, Sd = A.Sd, Mi = A.Mi;
+  C* xb = tw + d;       // W transforms of the signal columns, then W of h*
+  C* yb = xb + W * Sd;
+  for (int e = threadIdx.x; e < d; e += kThreads) tw[e] = A.twd[e];
+  const int u0 = blockIdx.x * W;
+  const long long bo = blockIdx.y;
+  const int WD = W * d;
+  constexpr int KX = MaxE<C>::value;
+  C acc[KX];
+#pragma unroll
+  for (int i = 0; i < KX; ++i) acc[i] = czero<C>();
+  for (int n0 = 0; n0 < A.q; ++n0) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < WD; e += kThreads) {
+      const int t = e / W, cc = e - t * W, u = u0 + cc;
+      C v = czero<C>(), h = czero<C>();
+      if (u < Mi) {
+        int r = u + n0 * A.ai;
+        if (r >= Mi) r -= Mi;
+        const long long l = r + (long long)t * Mi;
+        v = apply_chirp(A.chirp, load_sig<C>(A.x, A.real_in, bo * A.xs + l), l);
+        h = A.H[bo * A.hs + (long long)(n0 + A.q * t) * Mi + r];
+      }
+      xb[cc * Sd + t] = v;
+      yb[cc * Sd + t] = h;
+    }
+    __syncthreads();
+    fft_lds<C, false>(xb, Sd, A.fd, 2 * W, tw);
+#pragma unroll
+    for (int i = 0; i < KX; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < WD) {
+        const int cc = e / d, nu = e - cc * d, u = u0 + cc;
+        if (u < Mi) {
+          C pr = cmulc(xb[cc * Sd + nu], yb[cc * Sd + nu]);
+          if (u + n0 * A.ai >= Mi) pr = cmulc(pr, tw[nu]);
+          acc[i] = cadd(acc[i], pr);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const T inv_d = T(1) / T(d);
+#pragma unroll
+  for (int i = 0; i < KX; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < WD) {
+      const int cc = e / d, nu = e - cc * d;
+      xb[cc * Sd + nu] = cscale(acc[i], inv_d);
+    }
+  }
+  __syncthreads();
+  fft_lds<C, true>(xb, Sd, A.fd, W, tw);
+  for (int e = threadIdx.x; e < WD; e += kThreads) {
+    const int t = e / W, cc = e - t * W, u = u0 + cc;
+    if (u < Mi) A.part[bo * A.ps + u + (long long)t * Mi] = xb[cc * Sd + t];
+  }
+}
+
+// out[l] = chirp(l) * sum_k part[k][l]  (fixed summation order)
+template <typename C>
+__global__ void __launch_bounds__(kThreads) k_batch_sum(const C* part, long long ps, int B, long long L,
+                                                       ChirpSrc<C> chirp, C* out) {
+  const long long l = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (l >= L) return;
+  C s = czero<C>();
+  for (int k = 0; k < B; ++k) s = cadd(s, part[k * ps + l]);
+  out[l] = apply_chirp(chirp, s, l);
+}
+
+// precision conversion of a complex vector
+template <typename CI, typename CO>
+__global__ void __launch_bounds__(kThreads) k_convert(const CI* x, CO* y, long long n) {
+  using TO = decltype(CO::x);
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) y[i] = mk<CO>(TO(x[i].x), TO(x[i].y));
+}
+
+}  // namespace dgtns

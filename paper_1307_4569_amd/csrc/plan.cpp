@@ -1,0 +1,380 @@
+// Lattice planner: normal form checks, shear factorisation and tables.
+#include "plan.hpp"
+
+#include <cmath>
+#include <map>
+
+namespace dgtns {
+
+int64_t gcd64(int64_t a, int64_t b) {
+  if (a < 0) a = -a;
+  if (b < 0) b = -b;
+  while (b) {
+    int64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+int64_t lcm64(int64_t a, int64_t b) { return a / gcd64(a, b) * b; }
+
+// Extended Euclid: returns g = gcd(|x|, |y|) >= 0 and u, v with u x + v y = g.
+static int64_t egcd(int64_t x, int64_t y, int64_t* u, int64_t* v) {
+  int64_t r0 = x, r1 = y, s0 = 1, s1 = 0, t0 = 0, t1 = 1;
+  while (r1 != 0) {
+    int64_t qq = r0 / r1;
+    int64_t t;
+    t = r0 - qq * r1; r0 = r1; r1 = t;
+    t = s0 - qq * s1; s0 = s1; s1 = t;
+    t = t0 - qq * t1; t0 = t1; t1 = t;
+  }
+  if (r0 < 0) { r0 = -r0; s0 = -s0; t0 = -t0; }
+  *u = s0;
+  *v = t0;
+  return r0;
+}
+
+static std::map<int64_t, int> factorize(int64_t n) {
+  std::map<int64_t, int> f;
+  for (int64_t p = 2; p * p <= n; ++p)
+    while (n % p == 0) { f[p]++; n /= p; }
+  if (n > 1) f[n]++;
+  return f;
+}
+
+// Exponent of prime p in x (x != 0).
+static int vexp(int64_t x, int64_t p) {
+  if (x < 0) x = -x;
+  int e = 0;
+  while (x != 0 && x % p == 0) { x /= p; ++e; }
+  return e;
+}
+
+static int64_t ipow(int64_t p, int e) {
+  int64_t r = 1;
+  while (e-- > 0) r *= p;
+  return r;
+}
+
+// Shear factorisation of the lattice [[a, 0], [s, b]] (Thm. 2 and Prop. 9).
+Shear shearfind(int64_t L, int64_t a, int64_t M, int64_t s, int64_t b, std::string* err) {
+  (void)M;
+  Shear r;
+  if (s == 0) {           // separable lattice: no shear at all
+    r.br = b;
+    return r;
+  }
+  // A time shear alone suffices iff a | s + k b for some k (Prop. 9); then
+  // s1 = -(s + k b) / a makes [[1,0],[s1,1]] A = [[a,0],[-k b, b]] separable.
+  // Residues of s + k b mod a repeat with period a / gcd(a, b).
+  for (int64_t k = 0; k <= a; ++k) {
+    if ((s + k * b) % a == 0) {
+      r.s0 = 0;
+      r.s1 = -((s + k * b) / a);
+      r.br = b;
+      return r;
+    }
+  }
+  // Constructive proof of Thm. 2.
+  auto primes = factorize(L);
+  int64_t s1 = 1;
+  for (auto& pe : primes)
+    if (vexp(a, pe.first) == vexp(s, pe.first)) s1 *= pe.first;
+  int64_t k1, k2;
+  int64_t X = egcd(s1 * a + s, b, &k1, &k2);
+  const int64_t modulus = a * b / X;
+  int64_t s0 = 0;
+  bool ok = false;
+  if (k1 != 0) {
+    int64_t lrest = k1;
+    int64_t t1 = 1, t2 = 1;
+    bool overflow = false;
+    for (auto& pe : primes) {
+      int64_t p = pe.first;
+      int kap = 0;
+      while (lrest % p == 0) { lrest /= p; ++kap; }
+      int al = vexp(a, p), be = vexp(b, p), ga = vexp(X, p);
+      int e1 = be - ga - kap;
+      if (e1 < 0) e1 = 0;
+      int e2 = al + kap - ga;
+      if (e2 < 0 || e1 > 62 || e2 > 62) { overflow = true; break; }
+      t1 *= ipow(p, e1);
+      t2 *= ipow(p, e2);
+    }
+    if (!overflow) {
+      __int128 cand = (__int128)(t1 - lrest) * t2;
+      // reduce the candidate mod the period of the chirp, 2L, keeping its class
+      int64_t c = int64_t(cand % (__int128)(2 * L));
+      __int128 chk = (__int128)c * X + (__int128)a * k1;
+      if (chk % modulus == 0) {
+        s0 = c;
+        ok = true;
+      }
+    }
+  }
+  if (!ok) {
+    // Fallback: solve s0 X = -a k1 (mod a b / X) directly.
+    int64_t u, v;
+    int64_t gX = egcd(X % modulus, modulus, &u, &v);
+    int64_t rhs = fmod64(-mulmod(a % modulus, fmod64(k1, modulus), modulus), modulus);
+    if (rhs % gX != 0) {
+      if (err) *err = "shear factorisation failed (eq. modcond has no solution)";
+      r.br = 0;
+      return r;
+    }
+    int64_t m2 = modulus / gX;
+    s0 = fmod64(mulmod(fmod64(u, m2), (rhs / gX) % m2, m2), m2);
+  }
+  // keep s0 in (-L, L]: the chirps depend on s0 mod 2L only, and the
+  // post-processing constants are reduced with the same representative
+  s0 = fmod64(s0, 2 * L);
+  if (s0 > L) s0 -= 2 * L;
+  if (s0 == 0) {
+    // s0 = 0 would mean a time shear alone works, which was ruled out above
+    if (err) *err = "internal: frequency shear reduced to zero";
+    r.br = 0;
+    return r;
+  }
+  r.s0 = s0;
+  r.s1 = s1;
+  r.br = X;
+  r.constructed = true;
+  return r;
+}
+
+bool fft_schedule(int64_t n, FftSchedule* out) {
+  FftSchedule fs;
+  fs.n = int(n);
+  if (n < 1 || n > kMaxFft) return false;
+  int64_t m = n;
+  int e2 = 0, e3 = 0, e5 = 0, e7 = 0;
+  while (m % 2 == 0) { m /= 2; ++e2; }
+  while (m % 3 == 0) { m /= 3; ++e3; }
+  while (m % 5 == 0) { m /= 5; ++e5; }
+  while (m % 7 == 0) { m /= 7; ++e7; }
+  if (m != 1) return false;
+  int r8 = e2 / 3, rem = e2 % 3;
+  auto push = [&](int r) { fs.rad[fs.nst++] = int8_t(r); };
+  if (rem == 1 && r8 > 0) {
+    for (int i = 0; i < r8 - 1; ++i) push(8);
+    push(4);
+    push(4);
+  } else {
+    for (int i = 0; i < r8; ++i) push(8);
+    if (rem == 1) push(2);
+    if (rem == 2) push(4);
+  }
+  for (int i = 0; i < e7; ++i) push(7);
+  for (int i = 0; i < e5; ++i) push(5);
+  for (int i = 0; i < e3; ++i) push(3);
+  if (fs.nst > kMaxStages) return false;
+  *out = fs;
+  return true;
+}
+
+void unit_root(int64_t num, int64_t den, double* re, double* im) {
+  num = fmod64(num, den);
+  // reduce to the first octant with exact integer comparisons
+  const long double twopi = 6.283185307179586476925286766559005768L;
+  long double x = (long double)num / (long double)den;
+  long double s = sinl(twopi * x), c = cosl(twopi * x);
+  // exact values on the axes
+  if (4 * num == 0) { s = 0; c = 1; }
+  else if (4 * num == den) { s = 1; c = 0; }
+  else if (2 * num == den) { s = 0; c = -1; }
+  else if (4 * num == 3 * den) { s = -1; c = 0; }
+  *re = double(c);
+  *im = double(s);
+}
+
+static void fill_twiddles(int64_t n, std::vector<double>* v) {
+  v->resize(2 * n);
+  for (int64_t e = 0; e < n; ++e) unit_root(-e, n, &(*v)[2 * e], &(*v)[2 * e + 1]);
+}
+
+// pchirp(L, s)(l) = exp(pi i s (L+1) l^2 / L) = exp(2 pi i r / (2L)),
+// r = s (L+1) l^2 mod 2L, reduced exactly factor by factor (Lemma 1).
+static void fill_chirp(int64_t L, int64_t s, std::vector<double>* v) {
+  const int64_t twoL = 2 * L;
+  const int64_t K = mulmod(fmod64(s, twoL), fmod64(L + 1, twoL), twoL);
+  v->resize(2 * L);
+  for (int64_t l = 0; l < L; ++l) {
+    int64_t l2 = mulmod(l, l, twoL);
+    int64_t r = mulmod(K, l2, twoL);
+    unit_root(r, twoL, &(*v)[2 * l], &(*v)[2 * l + 1]);
+  }
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int dtype,
+              int64_t max_batch, Plan* P, std::string* err) {
+  // status codes mirror include/dgtns.h
+  const int kEInval = 1, kELattice = 2, kEUnsupported = 4;
+  if (dtype != 0 && dtype != 1) { *err = "dtype must be DGTNS_C64 or DGTNS_C128"; return kEInval; }
+  if (L < 1 || a < 1 || M < 1 || max_batch < 1) { *err = "L, a, M and max_batch must be positive"; return kEInval; }
+  if (L > kMaxL) { *err = "L above 2^30 is not supported"; return kEUnsupported; }
+  if (L % a || L % M) { *err = "a and M must divide L"; return kELattice; }
+  if (lam2 < 1 || lam1 < 0 || lam1 >= lam2 || gcd64(lam1, lam2) != 1) {
+    *err = "lattice offset must be lambda1/lambda2 with 0 <= lambda1 < lambda2 and gcd 1 (0/1 for separable)";
+    return kELattice;
+  }
+  // feasible lengths are the multiples of lambda2 lcm(a, M) (Prop. 8)
+  if (L % (lam2 * lcm64(a, M)) != 0) {
+    *err = "L is not a multiple of lambda2 * lcm(a, M) (minimal feasible length)";
+    return kELattice;
+  }
+  Plan& p = *P;
+  p = Plan();
+  p.L = L; p.a = a; p.M = M; p.lam1 = lam1; p.lam2 = lam2;
+  p.b = L / M; p.N = L / a;
+  p.s = p.b * lam1 / lam2;   // absolute shear in normal form (Section 2.1)
+  p.dtype = dtype;
+  p.max_batch = max_batch;
+  p.sh = shearfind(L, a, M, p.s, p.b, err);
+  if (p.sh.br == 0) return kELattice;
+  if (p.s == 0) p.branch = kSeparable;
+  else if (p.sh.s0 == 0) p.branch = kTimeShear;
+  else p.branch = kFreqShear;
+
+  const int64_t N = p.N, b = p.b;
+  if (p.branch != kFreqShear) {
+    p.ai = a; p.Mi = M;
+  } else {
+    // Alg. 1, frequency-shear branch: separable DGT with time step b_r and
+    // N_r channels on the Fourier transform of the chirped signal
+    p.ar = a * b / p.sh.br;
+    p.Mr = L / p.sh.br;
+    p.Nr = L / p.ar;
+    p.ai = p.sh.br; p.Mi = p.Nr;
+    const int64_t twoN = 2 * N;
+    int64_t C1 = p.ar / a;
+    if (((__int128)p.sh.s0 * p.sh.br) % a != 0) {
+      *err = "internal: s0 b_r not divisible by a";
+      return kELattice;
+    }
+    __int128 C2 = -(__int128)p.sh.s0 * p.sh.br / a;
+    __int128 C3 = (__int128)a * p.sh.s1 * (L + 1);
+    __int128 C4 = C2 * p.sh.br * (L + 1);
+    __int128 C5 = (__int128)2 * C1 * p.sh.br;
+    __int128 C6 = ((__int128)p.sh.s0 * p.sh.s1 + 1) * p.sh.br;
+    auto red = [](__int128 x, int64_t m) { __int128 r = x % m; if (r < 0) r += m; return int64_t(r); };
+    p.K1 = red(C1, twoN); p.K2 = red(C2, twoN); p.K3 = red(C3, twoN);
+    p.K4 = red(C4, twoN); p.K5 = red(C5, twoN);
+    p.C1n = red(C1, N); p.C2n = red(C2, N);
+    p.Kt1 = red(-(__int128)p.sh.s1 * p.ar, L);
+    p.Kt6 = red(C6, L);
+  }
+  p.bi = L / p.Mi;
+  p.Ni = L / p.ai;
+  p.ci = gcd64(p.ai, p.Mi);
+  p.pi = p.ai / p.ci;
+  p.qi = p.Mi / p.ci;
+  p.di = p.bi / p.pi;
+
+  if (!fft_schedule(p.di, &p.fd) || !fft_schedule(p.Mi, &p.fm)) {
+    *err = "transform lengths d = " + std::to_string(p.di) + " and M = " + std::to_string(p.Mi) +
+           " must be 7-smooth and at most 4096";
+    return kEUnsupported;
+  }
+  // LDS element budget per work-group: 8192 complex elements (FP32) or 4096 (FP64)
+  const int64_t budget = dtype == 0 ? 8192 : 4096;
+  const int64_t Sd = p.di | 1;
+  int64_t W = 16;
+  while (W > 1 && (W * p.pi * p.di > budget || W * (p.pi * Sd + (p.pi > 1 ? Sd : 0)) > budget + 64 * W))
+    --W;
+  if (W * p.pi * p.di > budget) {
+    *err = "column length b = " + std::to_string(p.bi) + " exceeds the in-LDS limit";
+    return kEUnsupported;
+  }
+  if (p.Mi > budget) {
+    *err = "channel count exceeds the in-LDS limit";
+    return kEUnsupported;
+  }
+  p.W = int(W);
+  if (p.branch == kFreqShear) {
+    // L = L1 * L2 for the two-pass transform of length L
+    int64_t best = 0;
+    for (int64_t d1 = 1; d1 * d1 <= L; ++d1) {
+      if (L % d1) continue;
+      int64_t d2 = L / d1;
+      FftSchedule t1, t2;
+      if (d2 <= budget && d1 <= kMaxFft && d2 <= kMaxFft && fft_schedule(d1, &t1) && fft_schedule(d2, &t2))
+        best = d1;
+    }
+    if (best == 0) {
+      *err = "signal length cannot be split into two in-LDS transform lengths";
+      return kEUnsupported;
+    }
+    p.L1 = best;
+    p.L2 = L / best;
+    fft_schedule(p.L1, &p.f1);
+    fft_schedule(p.L2, &p.f2);
+  }
+
+  // ---- host tables (FP64) ----
+  fill_twiddles(p.di, &p.tw_d);
+  fill_twiddles(p.Mi, &p.tw_m);
+  if (p.branch != kSeparable) fill_chirp(L, p.sh.s1, &p.chirp1);
+  if (p.branch == kFreqShear) {
+    fill_twiddles(p.L1, &p.tw_1);
+    fill_twiddles(p.L2, &p.tw_2);
+    fill_twiddles(L, &p.tw_L);
+    fill_chirp(L, -p.sh.s0, &p.chirp0);
+  } else {
+    // Alg. 1, time-shear branch: c((m + rho_n) mod M, n) = E_n c_r(m, n) with
+    // E_n = exp(pi i (C1 n^2 mod 2N) / N), C1 = s1 a (L+1) mod 2N,
+    // rho_n = floor(((-s1 n a) mod L) / b)
+    const int64_t twoN = 2 * N;
+    int64_t C1 = int64_t(((__int128)p.sh.s1 * a % twoN * ((L + 1) % twoN)) % twoN);
+    C1 = fmod64(C1, twoN);
+    p.post_E.resize(2 * N);
+    p.post_rho.resize(N);
+    const int64_t ms1a = fmod64(-(int64_t)((__int128)p.sh.s1 * a % L), L);
+    for (int64_t n = 0; n < N; ++n) {
+      int64_t e = mulmod(C1, mulmod(n, n, twoN), twoN);
+      unit_root(e, twoN, &p.post_E[2 * n], &p.post_E[2 * n + 1]);
+      p.post_rho[n] = int32_t(mulmod(ms1a, n, L) / b);
+    }
+  }
+
+  // ---- device memory map ----
+  const size_t es = dtype == 0 ? 8 : 16;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+  p.off.tw_d = take(es * p.di);
+  p.off.tw_m = take(es * p.Mi);
+  p.off.chirp1 = p.chirp1.empty() ? 0 : take(es * L);
+  p.off.tw_1 = p.off.tw_2 = p.off.tw_L = p.off.chirp0 = 0;
+  p.off.tw_1_64 = p.off.tw_2_64 = p.off.tw_L64 = 0;
+  if (p.branch == kFreqShear) {
+    p.off.tw_1 = take(es * p.L1);
+    p.off.tw_2 = take(es * p.L2);
+    p.off.tw_L = take(es * L);
+    p.off.chirp0 = take(es * L);
+  }
+  p.off.post_E = p.post_E.empty() ? 0 : take(es * N);
+  p.off.post_rho = p.post_rho.empty() ? 0 : take(4 * N);
+  p.off.zc = take(es * L);
+  if (dtype == 0) {
+    p.off.tw_d64 = take(16 * p.di);
+    p.off.tw_m64 = take(16 * p.Mi);
+    if (p.branch == kFreqShear) {
+      p.off.tw_1_64 = take(16 * p.L1);
+      p.off.tw_2_64 = take(16 * p.L2);
+      p.off.tw_L64 = take(16 * L);
+    }
+  } else {
+    p.off.tw_d64 = p.off.tw_d;
+    p.off.tw_m64 = p.off.tw_m;
+    p.off.tw_1_64 = p.off.tw_1;
+    p.off.tw_2_64 = p.off.tw_2;
+    p.off.tw_L64 = p.off.tw_L;
+  }
+  p.off.bounds = take(16);
+  p.off.total = o;
+  return 0;
+}
+
+}  // namespace dgtns

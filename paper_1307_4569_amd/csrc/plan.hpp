@@ -1,0 +1,95 @@
+// Host-side lattice planner for the shear DGT (exact int64 arithmetic).
+//
+// Given (L, a, M, lambda1, lambda2) the planner
+//   * validates the lattice (Prop. 1 normal form; feasible lengths, Prop. 8),
+//   * finds the shear factorisation A = U_{s0,s1} D V (Thm. 2): first a time
+//     shear alone (a | s + k b for some k, Prop. 9), otherwise the
+//     constructive proof of Thm. 2 (choice of s1 from prime exponents,
+//     Bezout for k1, s0 from the exponents of k1, check of eq. (modcond)),
+//   * derives the separable lattice the factorised DGT runs on and the
+//     constants of Alg. 1 (C1 ... C6),
+//   * builds the FFT radix schedules and all twiddle/chirp/phase tables in
+//     FP64 (rounded to FP32 for single-precision plans).
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dgtns {
+
+constexpr int kMaxStages = 20;
+constexpr int64_t kMaxFft = 4096;     // largest in-LDS transform length
+constexpr int64_t kMaxL = int64_t(1) << 30;
+
+struct FftSchedule {
+  int n = 1;
+  int nst = 0;
+  int8_t rad[kMaxStages] = {0};
+};
+
+// Floor modulus for possibly negative values.
+inline int64_t fmod64(int64_t x, int64_t m) {
+  int64_t r = x % m;
+  return r < 0 ? r + m : r;
+}
+
+// (x * y) mod m without overflow for 0 <= x, y < m < 2^62.
+inline int64_t mulmod(int64_t x, int64_t y, int64_t m) {
+  return int64_t((__int128)x * y % m);
+}
+
+struct Shear {
+  int64_t s0 = 0, s1 = 0, br = 0;   // frequency shear, time shear, b_r
+  bool constructed = false;          // true if the Thm. 2 construction was used
+};
+
+// Number theory helpers (exposed for tests through the C-ABI).
+int64_t gcd64(int64_t a, int64_t b);
+int64_t lcm64(int64_t a, int64_t b);
+bool fft_schedule(int64_t n, FftSchedule* out);
+Shear shearfind(int64_t L, int64_t a, int64_t M, int64_t s, int64_t b, std::string* err);
+
+enum Branch { kSeparable = 0, kTimeShear = 1, kFreqShear = 2 };
+
+struct Plan {
+  // lattice
+  int64_t L, a, M, lam1, lam2, b, N, s;
+  Shear sh;
+  int branch;
+  int dtype;           // 0 = complex64, 1 = complex128
+  int64_t max_batch;
+  // separable lattice the factorised DGT runs on (time step ai, channels Mi)
+  int64_t ai, Mi, bi, Ni, ci, pi, qi, di;
+  // frequency-shear branch constants of Alg. 1 (reduced mod 2N or mod L)
+  int64_t ar, Mr, Nr;
+  int64_t K1, K2, K3, K4, K5;     // C1, C2, C3, C4, C5 mod 2N
+  int64_t Kt1, Kt6;               // (-s1 a_r) mod L and C6 mod L
+  int64_t C1n, C2n;               // C1, C2 mod N
+  // FFT schedules
+  FftSchedule fd, fm, f1, f2;     // length di, Mi, and L = L1 * L2 (freq shear)
+  int64_t L1, L2;
+  // column-block width of the factorisation kernels
+  int W;
+  // host tables (FP64, interleaved re/im); uploaded by bind
+  std::vector<double> tw_d, tw_m, tw_1, tw_2, tw_L, chirp1, chirp0, post_E;
+  std::vector<int32_t> post_rho;
+  // device memory map (byte offsets into the persistent block)
+  struct Off {
+    size_t tw_d, tw_m, tw_1, tw_2, tw_L, chirp1, chirp0, post_E, post_rho, zc;   // plan dtype
+    size_t tw_d64, tw_m64, tw_1_64, tw_2_64, tw_L64;                             // FP64 copies
+    size_t bounds;  // 2 doubles
+    size_t total;
+  } off;
+  void* dev = nullptr;       // bound persistent memory
+  bool window_set = false;
+};
+
+// Returns 0 on success, else an error status with a message in *err.
+int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int dtype,
+              int64_t max_batch, Plan* p, std::string* err);
+
+// exp(2 pi i num / den), accurate to about one ulp (num reduced exactly first).
+void unit_root(int64_t num, int64_t den, double* re, double* im);
+
+}  // namespace dgtns

@@ -1,0 +1,222 @@
+"""GPU parity of libdgtns against the FP64 oracle, element by element on the
+same seeded inputs.  Bar: relative l2 error per signal <= 1e-12 (FP64) and
+<= 1e-5 (FP32)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from dgt_inputs import (GRADIENT, LARGE, PRECISION, SMALL, chirp_mixture, complex_normal, complex_normal_batch,
+                        gaussian_window, hann_window, round_to)
+from tests.conftest import feasible_lattices
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex64: 1e-5, torch.complex128: 1e-12}
+
+
+def rel(x, y):
+    x = np.asarray(x)
+    y = np.asarray(y)
+    return float(np.linalg.norm((x - y).ravel()) / np.linalg.norm(y.ravel()))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1307_4569_amd import _binding
+    _binding.lib()   # fail loudly if the library is missing
+    return torch.device("cuda", 0)
+
+
+def make_plan(L, a, M, l1, l2, dtype, B=4):
+    from paper_1307_4569_amd import Plan
+    return Plan(L, a, M, l1, l2, dtype=dtype, max_batch=B)
+
+
+def inputs(L, a, M, B, single, seed=0):
+    f = np.stack([complex_normal(L, 1000 + seed + i) for i in range(B)])
+    g = gaussian_window(L, a, M)
+    return round_to(f, single), round_to(g, single)
+
+
+def run_forward(lat, dtype, B=2, g=None, seed=0):
+    L, a, M, l1, l2 = lat
+    single = dtype == torch.complex64
+    f, g0 = inputs(L, a, M, B, single, seed)
+    g = g0 if g is None else round_to(g, single)
+    plan = make_plan(L, a, M, l1, l2, dtype, B)
+    plan.set_window(torch.tensor(g))
+    c = plan.forward(torch.tensor(f)).cpu().numpy()
+    return plan, f, g, c
+
+
+# ---------------------------------------------------------------------------
+# Small workload and random lattices
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_small_workload(dtype):
+    lat = (SMALL.L, SMALL.a, SMALL.M, SMALL.lam1, SMALL.lam2)
+    plan, f, g, c = run_forward(lat, dtype, B=1)
+    assert c.shape == (1, 24, 12)
+    ref = oracle.dgt_direct(f[0], g, *lat[1:])
+    print("small workload", dtype, rel(c[0], ref))
+    assert rel(c[0], ref) < TOL[dtype]
+
+
+def sample_lattices(p1_only):
+    lats = [l for l in feasible_lattices(max_L=240, max_lam2=4) if l[0] >= 24]
+    rng = np.random.default_rng(7)
+    idx = rng.choice(len(lats), 400, replace=False)
+    out = []
+    from paper_1307_4569_amd import _binding as B
+    for i in idx:
+        L, a, M, l1, l2 = lats[i]
+        try:
+            h = B.dgtns_plan_create(L, a, M, l1, l2, 1, 2)
+        except B.DgtnsError:
+            continue
+        info = B.dgtns_plan_info(h)
+        B.dgtns_plan_destroy(h)
+        if p1_only and info.p != 1:
+            continue
+        out.append((lats[i], info.branch, info.p))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_random_lattices_forward_and_adjoint(dtype):
+    lats = sample_lattices(False)
+    seen = {"fs": 0, "ts": 0, "sep": 0, "p>1": 0}
+    worst_f = worst_a = 0.0
+    for (lat, branch, p) in lats[:120]:
+        L, a, M, l1, l2 = lat
+        plan, f, g, c = run_forward(lat, dtype, B=2, g=complex_normal(L, 77))
+        for k in range(2):
+            e = rel(c[k], oracle.dgt_fold(f[k], g, a, M, l1, l2))
+            worst_f = max(worst_f, e)
+            assert e < TOL[dtype], (lat, branch, p, e)
+        cin = np.stack([complex_normal(L // a * M, 500 + k).reshape(L // a, M) for k in range(2)])
+        cin = round_to(cin, dtype == torch.complex64)
+        fa = plan.adjoint(torch.tensor(cin)).cpu().numpy()
+        for k in range(2):
+            e = rel(fa[k], oracle.idgt_adjoint(cin[k], g, a, M, l1, l2))
+            worst_a = max(worst_a, e)
+            assert e < TOL[dtype], ("adjoint", lat, branch, p, e)
+        seen[["sep", "ts", "fs"][branch]] += 1
+        seen["p>1"] += p > 1
+    print("random lattices", dtype, seen, "worst forward", worst_f, "worst adjoint", worst_a)
+    assert seen["fs"] >= 5 and seen["ts"] >= 20 and seen["p>1"] >= 5
+
+
+def test_ragged_blocks_and_batch_sizes():
+    """Column blocks that do not divide M, batch 1 and the maximal batch."""
+    lat = (5 * 7 * 8, 5, 70, 0, 1)      # M = 70 channels: 70 = 4 * 16 + 6 columns
+    dt = torch.complex128
+    L, a, M, l1, l2 = lat
+    plan = make_plan(L, a, M, l1, l2, dt, B=5)
+    g = complex_normal(L, 3)
+    plan.set_window(torch.tensor(g))
+    f = np.stack([complex_normal(L, 10 + i) for i in range(5)])
+    c5 = plan.forward(torch.tensor(f)).cpu().numpy()
+    c1 = plan.forward(torch.tensor(f[3])).cpu().numpy()
+    assert np.array_equal(c5[3], c1)           # batch position does not change the result
+    for k in range(5):
+        assert rel(c5[k], oracle.dgt_fold(f[k], g, a, M, l1, l2)) < 1e-12
+
+
+def test_real_input_matches_complex():
+    lat = (240, 6, 12, 1, 2)
+    L, a, M, l1, l2 = lat
+    dt = torch.complex128
+    plan = make_plan(*lat, dt, B=2)
+    g = gaussian_window(L, a, M)
+    plan.set_window(torch.tensor(g))
+    x = np.stack([chirp_mixture(L, 5), chirp_mixture(L, 6)])
+    cr = plan.forward(torch.tensor(x)).cpu().numpy()
+    cc = plan.forward(torch.tensor(x.astype(np.complex128))).cpu().numpy()
+    assert np.array_equal(cr, cc)
+    assert rel(cr[1], oracle.dgt_fold(x[1], g, a, M, l1, l2)) < 1e-12
+
+
+def test_errors_are_reported():
+    from paper_1307_4569_amd import _binding as B
+    plan = make_plan(144, 6, 12, 1, 2, torch.complex64, B=2)
+    f = torch.zeros(2, 144, dtype=torch.complex64, device="cuda")
+    with pytest.raises(B.DgtnsError) as e:
+        plan.forward(f)                           # window not set
+    assert e.value.status == B.DGTNS_ESTATE
+    plan.set_window(torch.tensor(gaussian_window(144, 6, 12)))
+    c = torch.empty(3, 24, 12, dtype=torch.complex64, device="cuda")
+    with pytest.raises(B.DgtnsError) as e:
+        B.dgtns_forward(plan._h, f.data_ptr(), 0, c.data_ptr(), 3, c.data_ptr(), 10 ** 9, 0)   # B > max_batch
+    assert e.value.status == B.DGTNS_EINVAL
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.DgtnsError) as e:
+        B.dgtns_forward(plan._h, f.data_ptr(), 0, c.data_ptr(), 2, ws.data_ptr(), 16, 0)
+    assert e.value.status == B.DGTNS_EWORKSPACE
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads: all signals transformed, sampled time positions
+# compared with the oracle, plus invariants that hold at any size.
+# ---------------------------------------------------------------------------
+
+def full_size(w, dtype, B, columns, real=False, window=None):
+    single = dtype == torch.complex64
+    if real:
+        f = np.stack([chirp_mixture(w.L, 13074569 + 3000 + i) for i in range(B)])
+    else:
+        f = complex_normal_batch(B, w.L, 2)
+    f = round_to(f, single)
+    g = round_to(gaussian_window(w.L, w.a, w.M) if window is None else window, single)
+    plan = make_plan(w.L, w.a, w.M, w.lam1, w.lam2, dtype, B)
+    plan.set_window(torch.tensor(g))
+    ft = torch.tensor(f).cuda()
+    c = plan.forward(ft)
+    torch.cuda.synchronize()
+    errs = []
+    for k in sorted({0, B - 1}):
+        ref = oracle.dgt_fold(f[k], g, w.a, w.M, w.lam1, w.lam2, columns=columns)
+        got = c[k, columns].cpu().numpy()
+        errs.append(rel(got, ref))
+    return plan, ft, c, errs
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_large_workload_sampled(dtype):
+    w = LARGE
+    B = w.batch if dtype == torch.complex64 else 8
+    cols = list(range(0, w.N, 97)) + [w.N - 1]
+    plan, f, c, errs = full_size(w, dtype, B, cols)
+    print("large workload", dtype, "B", B, "errors", errs)
+    assert max(errs) < TOL[dtype]
+    # every signal: Parseval-type invariant ||c||^2 = <S f, f> is not cheap; check
+    # adjointness <C f, c'> = <f, C* c'> on the whole batch instead
+    cp = torch.randn_like(c)
+    fa = plan.adjoint(cp)
+    lhs = torch.vdot(c.flatten().to(torch.complex128), cp.flatten().to(torch.complex128)).item()
+    rhs = torch.vdot(f.flatten().to(torch.complex128), fa.flatten().to(torch.complex128)).item()
+    print("adjointness", abs(lhs - rhs) / abs(lhs))
+    assert abs(lhs - rhs) <= (1e-4 if dtype == torch.complex64 else 1e-11) * abs(lhs)
+
+
+def test_precision_workload_real_signals():
+    w = PRECISION
+    cols = list(range(0, w.N, 331)) + [w.N - 1]
+    for name, win in (("gaussian", None), ("hann", hann_window(w.L, 2048))):
+        plan, f, c, errs = full_size(w, torch.complex64, w.batch, cols, real=True, window=win)
+        print("precision workload", name, errs)
+        assert max(errs) < 1e-5
+
+
+def test_gradient_workload_sampled():
+    w = GRADIENT
+    cols = list(range(0, w.N, 53))
+    plan, f, c, errs = full_size(w, torch.complex64, w.batch, cols)
+    print("gradient workload forward", errs)
+    assert max(errs) < 1e-5

@@ -1,0 +1,175 @@
+"""Host-side checks of libdgtns that need no GPU: exported symbols, the
+lattice planner against brute force and the paper's number-theory results,
+and the synchronous error paths of the C-ABI."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT, feasible_lattices
+
+B = pytest.importorskip("paper_1307_4569_amd._binding")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libdgtns.so not built")
+    return B.lib()
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "dgtns.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dgtns_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_header_symbol(lib):
+    syms = header_symbols()
+    assert len(syms) >= 14
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert sorted(n for n, _, _ in B.SIGNATURES) == syms
+
+
+def test_status_strings(lib):
+    for code, name in B.STATUS_NAMES.items():
+        assert B.dgtns_status_string(code) == name
+
+
+# ---------------------------------------------------------------------------
+# Planner
+# ---------------------------------------------------------------------------
+
+def lattice(L, a, M, l1, l2):
+    b = L // M
+    s = b * l1 // l2
+    return {((a * k1) % L, (s * k1 + b * k2) % L) for k1 in range(L // a) for k2 in range(L // b)}
+
+
+def is_closed_lattice(L, a, M, l1, l2):
+    """Brute-force lattice condition (proof of Prop. 1): s = b l1/l2 is an
+    integer and N steps of (a, s) land in {0} x bZ."""
+    b = L // M
+    if (b * l1) % l2:
+        return False
+    s = b * l1 // l2
+    return ((L // a) * s) % b == 0
+
+
+def test_prop8_feasible_lengths(lib):
+    """The planner accepts exactly the lengths that form a lattice, which
+    are the multiples of lambda2 * lcm(a, M) (Prop. 8)."""
+    n = 0
+    for L in range(2, 97):
+        divs = [d for d in range(1, L + 1) if L % d == 0]
+        for a in divs:
+            for M in divs:
+                for l2 in range(1, 5):
+                    for l1 in range(l2):
+                        if math.gcd(l1, l2) != 1:
+                            continue
+                        ok = is_closed_lattice(L, a, M, l1, l2)
+                        assert ok == (L % (l2 * (a * M // math.gcd(a, M))) == 0)
+                        h = ctypes.c_void_p()
+                        st = lib.dgtns_plan_create(ctypes.byref(h), L, a, M, l1, l2, 0, 1)
+                        if ok:
+                            assert st in (B.DGTNS_OK, B.DGTNS_EUNSUPPORTED), (L, a, M, l1, l2)
+                        else:
+                            assert st == B.DGTNS_ELATTICE, (L, a, M, l1, l2)
+                        if st == B.DGTNS_OK:
+                            lib.dgtns_plan_destroy(h)
+                        n += 1
+    assert n > 5000
+
+
+@pytest.mark.parametrize("chunk", range(4))
+def test_shearfind_makes_lattice_separable(lib, chunk):
+    """U^{-1} A Z_L^2 is the separable lattice (ab/b_r) Z x b_r Z, where
+    U^{-1} = [[1 + s0 s1, s0], [s1, 1]] (proof of Thm. 2)."""
+    lats = feasible_lattices(max_L=90, max_lam2=4)[chunk::4]
+    nfs = 0
+    for (L, a, M, l1, l2) in lats:
+        s0, s1, br = B.dgtns_shearfind(L, a, M, l1, l2)
+        b = L // M
+        ar = a * b // br
+        assert (a * b) % br == 0 and L % br == 0 and L % ar == 0
+        img = {(((1 + s0 * s1) * x + s0 * w) % L, (s1 * x + w) % L) for (x, w) in lattice(L, a, M, l1, l2)}
+        sep = {((ar * i) % L, (br * j) % L) for i in range(L // ar) for j in range(L // br)}
+        assert img == sep, (L, a, M, l1, l2, s0, s1, br)
+        # a time shear alone is used exactly when a | s + k b for some k (Prop. 9)
+        s = b * l1 // l2
+        time_only = any((s + k * b) % a == 0 for k in range(a + 1))
+        assert (s0 == 0) == time_only
+        nfs += s0 != 0
+    assert nfs > 20
+
+
+def test_remark_values(lib):
+    path = os.path.join(ROOT, "tests", "golden", "remark_quincunx.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 2
+    for a, M, l1, l2, expect in (map(int, r) for r in rows):
+        lmin = l2 * (a * M // math.gcd(a, M))
+        assert lmin * B.dgtns_noshear_factor(a, M, l1, l2) == expect
+        # at that length the planner needs no frequency shear ...
+        assert B.dgtns_shearfind(expect, a, M, l1, l2)[0] == 0
+        # ... and shorter feasible lengths do need one
+        for L in range(lmin, expect, lmin):
+            assert B.dgtns_shearfind(L, a, M, l1, l2)[0] != 0
+
+
+def test_prop9_lengths_need_no_frequency_shear(lib):
+    for (L, a, M, l1, l2) in feasible_lattices(max_L=120, max_lam2=4):
+        lmin = l2 * (a * M // math.gcd(a, M))
+        if L % (lmin * B.dgtns_noshear_factor(a, M, l1, l2)) == 0:
+            assert B.dgtns_shearfind(L, a, M, l1, l2)[0] == 0
+
+
+SERVING_FREQ_SHEAR = {(36864, 32, 256), (73728, 32, 256), (36864, 64, 512), (73728, 64, 512),
+                      (147456, 64, 512), (294912, 64, 512)}
+
+
+def test_workload_plans(lib):
+    from dgt_inputs import GRADIENT, LARGE, PRECISION, SMALL, serving_plans
+    for w in (SMALL, LARGE, PRECISION, GRADIENT):
+        h = B.dgtns_plan_create(w.L, w.a, w.M, w.lam1, w.lam2, 0, 1)
+        i = B.dgtns_plan_info(h)
+        assert i.branch == B.DGTNS_TIME_SHEAR and i.s0 == 0 and i.p == 1 and i.q == 8 or w is SMALL
+        B.dgtns_plan_destroy(h)
+    nfs = 0
+    for (L, a, M, l1, l2) in serving_plans():
+        h = B.dgtns_plan_create(L, a, M, l1, l2, 0, 8)
+        i = B.dgtns_plan_info(h)
+        fs = i.branch == B.DGTNS_FREQ_SHEAR
+        assert fs == ((L, a, M) in SERVING_FREQ_SHEAR and (l1, l2) == (1, 2))
+        nfs += fs
+        B.dgtns_plan_destroy(h)
+    assert nfs == 6
+
+
+def test_error_paths_without_device(lib):
+    with pytest.raises(B.DgtnsError) as e:
+        B.dgtns_plan_create(100, 6, 12, 1, 2, 0, 1)
+    assert e.value.status == B.DGTNS_ELATTICE
+    with pytest.raises(B.DgtnsError) as e:
+        B.dgtns_plan_create(144, 6, 12, 2, 4, 0, 1)        # not coprime
+    assert e.value.status == B.DGTNS_ELATTICE
+    with pytest.raises(B.DgtnsError) as e:
+        B.dgtns_plan_create(144, 6, 12, 1, 2, 7, 1)        # bad dtype
+    assert e.value.status == B.DGTNS_EINVAL
+    with pytest.raises(B.DgtnsError) as e:
+        B.dgtns_plan_create(242, 2, 2, 0, 1, 0, 1)         # d = 121 is not 7-smooth
+    assert e.value.status == B.DGTNS_EUNSUPPORTED
+    h = B.dgtns_plan_create(144, 6, 12, 1, 2, 1, 4)
+    dummy = ctypes.c_void_p(4096)
+    # not bound: every device call is refused before touching the device
+    assert lib.dgtns_forward(h, dummy, 0, dummy, 1, dummy, 1 << 20, None) == B.DGTNS_ESTATE
+    assert lib.dgtns_set_window(h, dummy, dummy, 1 << 20, None) == B.DGTNS_ESTATE
+    assert lib.dgtns_plan_bind(h, None, 0, None) == B.DGTNS_EINVAL
+    assert B.dgtns_workspace_bytes(h, B.DGTNS_OP_FORWARD, 4) >= 16 * 144 * 4 * 2
+    with pytest.raises(B.DgtnsError):
+        B.dgtns_workspace_bytes(h, 99, 1)
+    B.dgtns_plan_destroy(h)
