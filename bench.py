@@ -1,0 +1,231 @@
+"""Throughput benchmark of the shear DGT on one MI355X.
+
+One step = the forward transform of one batch of the quincunx workload
+(64 complex signals, L = 2^18, a = 64, M = 512, lambda = 1/2, redundancy 8) in
+FP32 with plan tables and window resident in HBM: chirp (time shear),
+factorisation kernel, channel DFT + phase correction.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1307_4569_amd/csrc/kernels.hpp", "paper_1307_4569_amd/csrc/fft_core.hpp",
+                  "paper_1307_4569_amd/csrc/dgtns.hip", "paper_1307_4569_amd/csrc/plan.cpp"]
+
+
+def sources_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel: str, es: int, L: int, MN: int, B: int) -> int:
+    """Bytes a kernel must move per launch: its inputs and outputs once.
+    factorisation kernel: read the signal (L) and write h (M N); channel DFT:
+    read h and write the coefficients (2 M N)."""
+    if kernel.startswith("factorisation"):
+        return es * (L + MN) * B
+    if kernel.startswith("channel DFT"):
+        return 2 * es * MN * B
+    return 0
+
+
+def time_forward(plan, f, c, steps, warmup, torch, B_mod):
+    for _ in range(warmup):
+        plan.forward(f, out=c)
+    torch.cuda.synchronize()
+    B_mod.dgtns_timing_reset()
+    B_mod.dgtns_timing_enable(1)
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        plan.forward(f, out=c)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    B_mod.dgtns_timing_enable(0)
+    kt = B_mod.kernel_times()
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3, kt
+
+
+def cpu_baseline(w, f_host, g_host, c_gpu_fn, budget_s=12.0):
+    """Time the FP64 oracle (per-column fold form) on a bounded sample of the
+    workload: the first columns of signal 0 until the time budget is used."""
+    import numpy as np
+
+    import oracle
+    cols, n = [], 0
+    t0 = time.perf_counter()
+    chunk = 64
+    ref_parts = []
+    while time.perf_counter() - t0 < budget_s and n < w.N:
+        cs = list(range(n, min(n + chunk, w.N)))
+        ref_parts.append(oracle.dgt_fold(f_host, g_host, w.a, w.M, w.lam1, w.lam2, columns=cs))
+        cols += cs
+        n += len(cs)
+    el = time.perf_counter() - t0
+    ref = np.concatenate(ref_parts)
+    got = c_gpu_fn(cols)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return {"value": len(cols) * w.M / el, "unit": "coeffs/s", "cores": 1, "kind": "oracle",
+            "sample": f"signal 0 of the batch, time positions 0..{len(cols) - 1} of {w.N} "
+                      f"({len(cols) * w.M} coefficients, {el:.1f} s, single-threaded NumPy FP64 fold form)"}, err
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run only the FP32 forward loop (for rocprofv3)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy (reference for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copied 3 x 1 GiB")
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from dgt_inputs import LARGE, complex_normal_batch, gaussian_window
+    from paper_1307_4569_amd import Plan
+    from paper_1307_4569_amd import _binding as Bm
+
+    w = LARGE
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"inputs: {w.name}")
+    f64 = complex_normal_batch(w.batch, w.L, 2)
+    g = gaussian_window(w.L, w.a, w.M)
+    f32 = torch.tensor(f64.astype(np.complex64), device=dev)
+    g32 = g.astype(np.complex64).astype(np.complex128)
+
+    plan = Plan(w.L, w.a, w.M, w.lam1, w.lam2, dtype=torch.complex64, max_batch=w.batch, device=dev)
+    plan.set_window(torch.tensor(g32))
+    c = torch.empty((w.batch, w.N, w.M), dtype=torch.complex64, device=dev)
+    MN = w.M * w.N
+    coeffs = w.batch * MN
+    log("fp32 forward timing")
+    ms, wall_ms, kt = time_forward(plan, f32, c, args.steps, args.warmup, torch, Bm)
+    if args.profile_only:
+        log(f"fp32 forward {ms:.3f} ms/step")
+        return
+    value = coeffs / (ms * 1e-3)
+
+    # dominant kernel and its roofline
+    dom = max(kt.items(), key=lambda kv: kv[1][1])
+    dname, (dn, dms) = dom
+    avg_ms = dms / dn
+    abytes = algorithmic_bytes(dname, 8, w.L, MN, w.batch)
+    achieved = abytes / (avg_ms * 1e-3) / 1e9
+    kernels = {k: {"launches": n, "avg_ms": round(t / n, 4),
+                   "algorithmic_GBps": round(algorithmic_bytes(k, 8, w.L, MN, w.batch) / (t / n * 1e-3) / 1e9, 1)}
+               for k, (n, t) in kt.items()}
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        tr = json.load(open(tpath))
+        ent = tr.get("kernels", {}).get(dname)
+        if ent and tr.get("sources") == sources_hash():
+            traffic = ent["bytes_per_launch"]
+
+    out = {
+        "metric": "nonsep DGT coeffs/s FP32 vs FP64 (rel err <=1e-5); serve p50/p99 latency",
+        "value": value,
+        "unit": "coeffs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic (seeded complex normal signals, unit-norm periodic Gaussian window)",
+        "config": {"workload": w.name, "L": w.L, "a": w.a, "M": w.M, "lambda": f"{w.lam1}/{w.lam2}",
+                   "batch": w.batch, "coeffs_per_step": coeffs, "branch": "time shear (s0=0, s1=-4)"},
+        "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+        "kernels": kernels,
+        "wall_ms_per_step": wall_ms,
+        "whole_path": {"compulsory_bytes_per_coeff": 9.0,
+                       "compulsory_GBps": round(9.0 * value / 1e9, 1),
+                       "frac_of_compulsory_bound": round(9.0 * value / 1e9 / HBM_PEAK_GBS, 4)},
+    }
+
+    # adjoint (synthesis) on the same batch, FP32
+    log("fp32 adjoint timing")
+    fa = torch.empty_like(f32)
+    for _ in range(3):
+        plan.adjoint(c, out=fa)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(max(5, args.steps // 5)):
+        plan.adjoint(c, out=fa)
+    e1.record()
+    torch.cuda.synchronize()
+    ams = e0.elapsed_time(e1) / max(5, args.steps // 5)
+    out["adjoint"] = {"ms_per_step": ams, "coeffs_per_s": coeffs / (ams * 1e-3)}
+
+    if not args.no_fp64:
+        log("fp64 forward timing")
+        plan64 = Plan(w.L, w.a, w.M, w.lam1, w.lam2, dtype=torch.complex128, max_batch=w.batch, device=dev)
+        plan64.set_window(torch.tensor(g))
+        f64d = torch.tensor(f64, device=dev)
+        c64 = torch.empty((w.batch, w.N, w.M), dtype=torch.complex128, device=dev)
+        ms64, _, _ = time_forward(plan64, f64d, c64, max(5, args.steps // 5), 2, torch, Bm)
+        out["fp64"] = {"ms_per_step": ms64, "value": coeffs / (ms64 * 1e-3),
+                       "fp32_speedup": ms64 / ms}
+        del c64, f64d, plan64
+        torch.cuda.synchronize()
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        f0 = f32[0].cpu().numpy().astype(np.complex128)
+
+        def gpu_cols(cols):
+            return c[0, cols].cpu().numpy().astype(np.complex128)
+
+        cb, err = cpu_baseline(w, f0, g32, gpu_cols)
+        out["cpu_baseline"] = cb
+        out["rel_err_fp32_vs_oracle"] = err
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

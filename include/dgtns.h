@@ -178,6 +178,19 @@ int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, vo
 int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* bounds_dev,
                       void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Kernel timing for profiling and benchmarks.  While enabled (process-wide),
+ * every kernel the library launches is bracketed by two HIP events recorded
+ * on its launch stream.  dgtns_timing_collect() waits for all recorded events,
+ * adds their durations to per-kernel totals and returns the number of
+ * distinct kernels; dgtns_timing_entry(i, ...) reads entry i (name, number of
+ * launches, total milliseconds); dgtns_timing_reset() clears the totals.
+ */
+int dgtns_timing_enable(int on);
+int dgtns_timing_collect(void);
+int dgtns_timing_entry(int i, char* name, size_t name_bytes, int64_t* launches, double* total_ms);
+int dgtns_timing_reset(void);
+
 /* Release host memory of the plan (device memory stays with the caller). */
 int dgtns_plan_destroy(dgtns_plan plan);
 

@@ -71,6 +71,11 @@ SIGNATURES = [
     ("dgtns_plan_destroy", ctypes.c_int, [c_vp]),
     ("dgtns_shearfind", ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.POINTER(c_i64)]),
     ("dgtns_noshear_factor", ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, ctypes.POINTER(c_i64)]),
+    ("dgtns_timing_enable", ctypes.c_int, [ctypes.c_int]),
+    ("dgtns_timing_collect", ctypes.c_int, []),
+    ("dgtns_timing_entry", ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(c_i64),
+                                          ctypes.POINTER(ctypes.c_double)]),
+    ("dgtns_timing_reset", ctypes.c_int, []),
 ]
 
 _lib = None
@@ -156,6 +161,36 @@ def dgtns_noshear_factor(a, M, lambda1, lambda2):
     out = c_i64()
     _call("dgtns_noshear_factor", a, M, lambda1, lambda2, ctypes.byref(out))
     return int(out.value)
+
+
+def dgtns_timing_enable(on):
+    _call("dgtns_timing_enable", int(on))
+
+
+def dgtns_timing_collect():
+    n = lib().dgtns_timing_collect()
+    if n < 0 or n > 1000:
+        check(n, "dgtns_timing_collect")
+    return n
+
+
+def dgtns_timing_entry(i):
+    name = ctypes.create_string_buffer(128)
+    cnt = c_i64()
+    ms = ctypes.c_double()
+    _call("dgtns_timing_entry", i, name, 128, ctypes.byref(cnt), ctypes.byref(ms))
+    return name.value.decode(), int(cnt.value), float(ms.value)
+
+
+def dgtns_timing_reset():
+    _call("dgtns_timing_reset")
+
+
+def kernel_times():
+    """{kernel name: (launches, total ms)} of the launches timed since the
+    last reset."""
+    n = dgtns_timing_collect()
+    return {name: (cnt, ms) for name, cnt, ms in (dgtns_timing_entry(i) for i in range(n))}
 
 
 def dgtns_status_string(status):

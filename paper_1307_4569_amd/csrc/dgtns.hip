@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,6 +35,48 @@ int check_hip(hipError_t e, const char* what) {
   return DGTNS_OK;
 }
 
+// Optional per-kernel timing: every launch bracketed by two HIP events on
+// the launch stream; dgtns_timing_collect() waits for them and aggregates.
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  struct Rec { std::string name; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  struct Agg { long long n = 0; double ms = 0; };
+  std::vector<std::pair<std::string, Agg>> agg;
+};
+Timing& timing() {
+  static Timing t;
+  return t;
+}
+hipEvent_t take_event(Timing& t) {
+  if (!t.pool.empty()) { hipEvent_t e = t.pool.back(); t.pool.pop_back(); return e; }
+  hipEvent_t e = nullptr;
+  hipEventCreate(&e);
+  return e;
+}
+
+template <typename K, typename... A>
+int launch_raw(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, const char* name, A... args) {
+  Timing& t = timing();
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (t.on) {
+    std::lock_guard<std::mutex> g(t.mu);
+    ea = take_event(t);
+    eb = take_event(t);
+  }
+  if (ea) hipEventRecord(ea, st);
+  hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+  int rc = check_hip(hipGetLastError(), name);
+  if (eb) {
+    hipEventRecord(eb, st);
+    std::lock_guard<std::mutex> g(t.mu);
+    t.recs.push_back({name, ea, eb});
+  }
+  return rc;
+}
+
 template <typename K, typename A>
 int launch(K kernel, dim3 grid, size_t lds, hipStream_t st, const A& args, const char* name) {
   if (grid.x == 0 || grid.y == 0) return DGTNS_OK;
@@ -42,8 +86,7 @@ int launch(K kernel, dim3 grid, size_t lds, hipStream_t st, const A& args, const
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return check_hip(e, name);
   }
-  hipLaunchKernelGGL(kernel, grid, dim3(kThreads), lds, st, args);
-  return check_hip(hipGetLastError(), name);
+  return launch_raw(kernel, grid, dim3(kThreads), lds, st, name, args);
 }
 
 inline unsigned cdiv(long long a, long long b) { return unsigned((a + b - 1) / b); }
@@ -319,14 +362,12 @@ int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* 
   rc = launch(k_grad_cols<C>, dim3(cdiv(P.Mi, A.W), unsigned(B)), lds, st, A, "window gradient");
   if (rc) return rc;
   if (!fs) {
-    hipLaunchKernelGGL(k_batch_sum<C>, dim3(cdiv(P.L, kThreads)), dim3(kThreads), 0, st, part, (long long)P.L,
-                       int(B), (long long)P.L, chirp_tab<C>(P, P.off.chirp1, 1), gg);
-    return check_hip(hipGetLastError(), "batch sum");
+    return launch_raw(k_batch_sum<C>, dim3(cdiv(P.L, kThreads)), dim3(kThreads), 0, st, "batch sum", part,
+                      (long long)P.L, int(B), (long long)P.L, chirp_tab<C>(P, P.off.chirp1, 1), gg);
   }
   C* G = reinterpret_cast<C*>(ws + l.G);
-  hipLaunchKernelGGL(k_batch_sum<C>, dim3(cdiv(P.L, kThreads)), dim3(kThreads), 0, st, part, (long long)P.L,
-                     int(B), (long long)P.L, no_chirp<C>(P), G);
-  rc = check_hip(hipGetLastError(), "batch sum");
+  rc = launch_raw(k_batch_sum<C>, dim3(cdiv(P.L, kThreads)), dim3(kThreads), 0, st, "batch sum", part,
+                  (long long)P.L, int(B), (long long)P.L, no_chirp<C>(P), G);
   if (rc) return rc;
   // the frequency-domain window is p0 FFT(p1 g) / L: its adjoint is
   // conj(p1) IFFT_unnormalised(conj(p0) .) / L
@@ -554,12 +595,11 @@ int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* 
   const long long tot = P.Mi * P.di;
   const unsigned nb = cdiv(tot, kThreads);
   const double sb = P.branch == kFreqShear ? double(P.L) : 1.0;
-  hipLaunchKernelGGL(k_dual_div, dim3(nb), dim3(kThreads), 0, st, Z, Zd, part, int(P.Mi), int(P.di), int(P.ai),
-                     int(P.qi), sb);
-  rc = check_hip(hipGetLastError(), "dual division");
+  rc = launch_raw(k_dual_div, dim3(nb), dim3(kThreads), 0, st, "dual division", Z, Zd, part, int(P.Mi),
+                  int(P.di), int(P.ai), int(P.qi), sb);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(kThreads), 0, st, part, int(nb), bounds_dev);
-  rc = check_hip(hipGetLastError(), "frame bounds");
+  rc = launch_raw(k_minmax_final, dim3(1), dim3(kThreads), 0, st, "frame bounds", (const double*)part, int(nb),
+                  bounds_dev);
   if (rc) return rc;
   ZakInvArgs Zi;
   Zi.z = Zd;
@@ -582,6 +622,56 @@ int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* 
   return run_four_step<double2>(P, Gd, 0, Y, static_cast<double2*>(gd_dev), 1, true, chirp_fly(P, -P.sh.s0, 1),
                                 chirp_fly(P, P.sh.s1, 1), 1.0 / double(P.L), nullptr,
                                 tab<double2>(P, P.off.tw_1_64), tab<double2>(P, P.off.tw_2_64), st);
+}
+
+int dgtns_timing_enable(int on) {
+  Timing& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.on = on != 0;
+  return DGTNS_OK;
+}
+
+int dgtns_timing_collect(void) {
+  Timing& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  for (auto& r : t.recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return fail(DGTNS_EDEVICE, std::string("timing: ") + hipGetErrorString(e));
+    auto it = t.agg.begin();
+    for (; it != t.agg.end(); ++it)
+      if (it->first == r.name) break;
+    if (it == t.agg.end()) {
+      t.agg.push_back({r.name, Timing::Agg()});
+      it = t.agg.end() - 1;
+    }
+    it->second.n += 1;
+    it->second.ms += ms;
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.recs.clear();
+  return int(t.agg.size());
+}
+
+int dgtns_timing_entry(int i, char* name, size_t name_bytes, int64_t* launches, double* total_ms) {
+  Timing& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (i < 0 || size_t(i) >= t.agg.size() || !name || name_bytes == 0 || !launches || !total_ms)
+    return fail(DGTNS_EINVAL, "bad timing entry request");
+  std::strncpy(name, t.agg[i].first.c_str(), name_bytes - 1);
+  name[name_bytes - 1] = 0;
+  *launches = t.agg[i].second.n;
+  *total_ms = t.agg[i].second.ms;
+  return DGTNS_OK;
+}
+
+int dgtns_timing_reset(void) {
+  Timing& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.agg.clear();
+  return DGTNS_OK;
 }
 
 int dgtns_plan_destroy(dgtns_plan plan) {
