@@ -10,155 +10,31 @@
 #include <vector>
 
 #include "../../include/dgtns.h"
-#include "kernels.hpp"
-#include "plan.hpp"
+#include "launch.hpp"
 
 using namespace dgtns;
+using namespace dgtns::host;
 
 struct dgtns_plan_s {
   Plan p;
 };
 
-namespace {
+namespace dgtns {
+namespace host {
 
 thread_local std::string g_err;
 
-int fail(int status, const std::string& msg) {
-  g_err = msg;
-  return status;
-}
+void set_last_error(const std::string& msg) { g_err = msg; }
 
-size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
-
-int check_hip(hipError_t e, const char* what) {
-  if (e != hipSuccess) return fail(DGTNS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
-  return DGTNS_OK;
-}
-
-// Optional per-kernel timing: every launch bracketed by two HIP events on
-// the launch stream; dgtns_timing_collect() waits for them and aggregates.
-struct Timing {
-  std::mutex mu;
-  bool on = false;
-  struct Rec { std::string name; hipEvent_t a, b; };
-  std::vector<Rec> recs;
-  std::vector<hipEvent_t> pool;
-  struct Agg { long long n = 0; double ms = 0; };
-  std::vector<std::pair<std::string, Agg>> agg;
-};
 Timing& timing() {
   static Timing t;
   return t;
 }
-hipEvent_t take_event(Timing& t) {
-  if (!t.pool.empty()) { hipEvent_t e = t.pool.back(); t.pool.pop_back(); return e; }
-  hipEvent_t e = nullptr;
-  hipEventCreate(&e);
-  return e;
-}
 
-template <typename K, typename... A>
-int launch_raw(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, const char* name, A... args) {
-  Timing& t = timing();
-  hipEvent_t ea = nullptr, eb = nullptr;
-  if (t.on) {
-    std::lock_guard<std::mutex> g(t.mu);
-    ea = take_event(t);
-    eb = take_event(t);
-  }
-  if (ea) hipEventRecord(ea, st);
-  hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
-  int rc = check_hip(hipGetLastError(), name);
-  if (eb) {
-    hipEventRecord(eb, st);
-    std::lock_guard<std::mutex> g(t.mu);
-    t.recs.push_back({name, ea, eb});
-  }
-  return rc;
-}
+}  // namespace host
+}  // namespace dgtns
 
-template <typename K, typename A>
-int launch(K kernel, dim3 grid, size_t lds, hipStream_t st, const A& args, const char* name) {
-  if (grid.x == 0 || grid.y == 0) return DGTNS_OK;
-  if (lds > 160 * 1024) return fail(DGTNS_EUNSUPPORTED, std::string(name) + ": LDS request above 160 KiB");
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return check_hip(e, name);
-  }
-  return launch_raw(kernel, grid, dim3(kThreads), lds, st, name, args);
-}
-
-inline unsigned cdiv(long long a, long long b) { return unsigned((a + b - 1) / b); }
-
-template <typename C> const C* tab(const Plan& P, size_t off) {
-  return reinterpret_cast<const C*>(static_cast<const char*>(P.dev) + off);
-}
-template <typename C> C* mtab(const Plan& P, size_t off) {
-  return reinterpret_cast<C*>(static_cast<char*>(P.dev) + off);
-}
-
-FftSched sched(const FftSchedule& s) {
-  FftSched f;
-  f.n = s.n;
-  f.nst = s.nst;
-  for (int i = 0; i < 20; ++i) f.rad[i] = s.rad[i];
-  return f;
-}
-
-long long chirpK(const Plan& P, long long s) {
-  const long long twoL = 2 * P.L;
-  return mulmod(fmod64(s, twoL), fmod64(P.L + 1, twoL), twoL);
-}
-
-// elements per work-group for column/row transforms of length n
-int block_width(long long n, int es, int maxw = 16) {
-  const long long budget = es == 8 ? 8192 : 4096;
-  long long w = budget / n;
-  if (w > maxw) w = maxw;
-  if (w < 1) w = 1;
-  return int(w);
-}
-
-struct Layout {
-  size_t H = 0, F = 0, Y = 0, part = 0, G = 0, total = 0;
-};
-
-Layout ws_layout(const Plan& P, int op, long long B) {
-  const size_t es = P.dtype == 0 ? 8 : 16;
-  const size_t MN = size_t(P.Mi) * size_t(P.Ni);
-  const size_t L = size_t(P.L);
-  Layout l;
-  size_t o = 0;
-  auto take = [&](size_t bytes) { size_t r = o; o = al256(o + bytes); return r; };
-  const bool fs = P.branch == kFreqShear;
-  switch (op) {
-    case DGTNS_OP_FORWARD:
-    case DGTNS_OP_ADJOINT:
-      l.H = take(es * MN * B);
-      if (fs) { l.F = take(es * L * B); l.Y = take(es * L * B); }
-      break;
-    case DGTNS_OP_WINDOW_GRAD:
-      l.H = take(es * MN * B);
-      l.part = take(es * L * B);
-      if (fs) { l.F = take(es * L * B); l.Y = take(es * L * B); l.G = take(es * L); }
-      break;
-    case DGTNS_OP_SET_WINDOW:
-      if (fs) { l.Y = take(16 * L); l.G = take(16 * L); }
-      break;
-    case DGTNS_OP_DUAL:
-      l.H = take(16 * L);   // Zak of the sheared window
-      l.F = take(16 * L);   // divided Zak
-      l.G = take(16 * L);   // separable dual / frequency-domain dual
-      if (fs) l.Y = take(16 * L);
-      l.part = take(16 * (size_t(cdiv((long long)P.Mi * P.di, kThreads)) + 1));
-      break;
-    default:
-      break;
-  }
-  l.total = o < 256 ? 256 : o;
-  return l;
-}
+namespace {
 
 int check_call(dgtns_plan plan, int64_t B, void* ws, size_t ws_bytes, int op, Layout* lay) {
   if (!plan) return fail(DGTNS_EINVAL, "null plan");
@@ -172,238 +48,6 @@ int check_call(dgtns_plan plan, int64_t B, void* ws, size_t ws_bytes, int op, La
   if (ws_bytes < lay->total)
     return fail(DGTNS_EWORKSPACE, "workspace too small: need " + std::to_string(lay->total) + " bytes");
   return DGTNS_OK;
-}
-
-// ---------------------------------------------------------------------------
-// stage launchers (templated on precision)
-// ---------------------------------------------------------------------------
-
-template <typename C>
-int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C> ch, C* H, long long B,
-             hipStream_t st) {
-  ColArgs<C> A;
-  A.x = x; A.xs = xs; A.real_in = real_in; A.chirp = ch;
-  A.zc = tab<C>(P, P.off.zc);
-  A.H = H; A.hs = (long long)P.Mi * P.Ni;
-  A.twd = tab<C>(P, P.off.tw_d);
-  A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.p = int(P.pi); A.q = int(P.qi);
-  A.W = P.W; A.Sd = int(P.di | 1); A.fd = sched(P.fd);
-  const size_t es = sizeof(C);
-  dim3 grid(cdiv(P.Mi, P.W), unsigned(B));
-  if (P.pi == 1) {
-    size_t lds = es * (P.di + size_t(P.W) * A.Sd);
-    return launch(k_fwd_cols<C, false>, grid, lds, st, A, "factorisation kernel");
-  }
-  size_t lds = es * (P.di + size_t(P.W) * A.Sd * (P.pi + 1));
-  return launch(k_fwd_cols<C, true>, grid, lds, st, A, "factorisation kernel (p > 1)");
-}
-
-template <typename C>
-int run_adj_cols(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, hipStream_t st) {
-  ColAdjArgs<C> A;
-  A.H = H; A.hs = (long long)P.Mi * P.Ni;
-  A.zc = tab<C>(P, P.off.zc);
-  A.twd = tab<C>(P, P.off.tw_d);
-  A.chirp = ch; A.y = y; A.ys = P.L;
-  A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.p = int(P.pi); A.q = int(P.qi);
-  A.W = P.W; A.Sd = int(P.di | 1); A.fd = sched(P.fd);
-  const size_t es = sizeof(C);
-  dim3 grid(cdiv(P.Mi, P.W), unsigned(B));
-  size_t lds = es * (P.di + size_t(P.W) * A.Sd * (P.pi + 1));
-  if (P.pi == 1) return launch(k_adj_cols<C, false>, grid, lds, st, A, "adjoint factorisation kernel");
-  return launch(k_adj_cols<C, true>, grid, lds, st, A, "adjoint factorisation kernel (p > 1)");
-}
-
-template <typename C>
-RowArgs<C> row_args(const Plan& P, const C* H, C* c) {
-  RowArgs<C> A;
-  std::memset(&A, 0, sizeof(A));
-  A.H = H; A.hs = (long long)P.Mi * P.Ni;
-  A.c = c; A.cs = (long long)P.M * P.N;
-  A.twm = tab<C>(P, P.off.tw_m);
-  A.Mi = int(P.Mi); A.Ni = int(P.Ni);
-  A.R = block_width(P.Mi | 1, sizeof(C));
-  A.Sm = int(P.Mi | 1);
-  A.fm = sched(P.fm);
-  if (P.branch != kFreqShear) {
-    A.postE = tab<C>(P, P.off.post_E);
-    A.rho = reinterpret_cast<const int*>(tab<C>(P, P.off.post_rho));
-  } else {
-    A.N = P.N; A.L = P.L; A.b = P.b; A.M = P.M;
-    A.K1 = P.K1; A.K2 = P.K2; A.K3 = P.K3; A.K4 = P.K4; A.K5 = P.K5;
-    A.C1n = P.C1n; A.C2n = P.C2n; A.Kt1 = P.Kt1; A.Kt6 = P.Kt6;
-  }
-  return A;
-}
-
-template <typename C>
-int run_rows(const Plan& P, const C* H, C* c, long long B, bool adjoint, hipStream_t st) {
-  RowArgs<C> A = row_args<C>(P, H, c);
-  dim3 grid(cdiv(P.Ni, A.R), unsigned(B));
-  size_t lds = sizeof(C) * (P.Mi + size_t(A.R) * A.Sm);
-  const bool fs = P.branch == kFreqShear;
-  if (!adjoint) {
-    if (fs) return launch(k_fwd_rows<C, 1>, grid, lds, st, A, "channel DFT + shear post-processing");
-    return launch(k_fwd_rows<C, 0>, grid, lds, st, A, "channel DFT + phase correction");
-  }
-  if (fs) return launch(k_adj_rows<C, 1>, grid, lds, st, A, "adjoint channel DFT (shear)");
-  return launch(k_adj_rows<C, 0>, grid, lds, st, A, "adjoint channel DFT");
-}
-
-// Length-L transform as column pass (length n1 over n2 columns) + row pass
-// (length n2 over n1 rows, transposed store).  Forward: n1 = L1, n2 = L2;
-// inverse: n1 = L2, n2 = L1.
-template <typename C>
-int run_four_step(const Plan& P, const void* x, int real_in, C* tmp, C* y, long long B, bool inv,
-                  ChirpSrc<C> pre, ChirpSrc<C> post, decltype(C::x) scale, const C* twL,
-                  const C* tw1, const C* tw2, hipStream_t st) {
-  const long long n1 = inv ? P.L2 : P.L1, n2 = inv ? P.L1 : P.L2;
-  const FftSched s1 = sched(inv ? P.f2 : P.f1), s2 = sched(inv ? P.f1 : P.f2);
-  ColFftArgs<C> A;
-  A.x = x; A.xs = P.L; A.real_in = real_in; A.y = tmp; A.ys = P.L; A.pre = pre;
-  A.twL = twL; A.L = P.L; A.tws = inv ? tw2 : tw1;
-  A.n = int(n1); A.ncols = int(n2); A.Sn = int(n1 | 1); A.W = block_width(A.Sn, sizeof(C)); A.fs = s1;
-  size_t lds = sizeof(C) * (n1 + size_t(A.W) * A.Sn);
-  dim3 g1(cdiv(n2, A.W), unsigned(B));
-  int rc = inv ? launch(k_col_fft<C, true>, g1, lds, st, A, "length-L transform, column pass")
-               : launch(k_col_fft<C, false>, g1, lds, st, A, "length-L transform, column pass");
-  if (rc) return rc;
-  RowFftArgs<C> R;
-  R.x = tmp; R.xs = P.L; R.y = y; R.ys = P.L; R.post = post; R.scale = scale;
-  R.tws = inv ? tw1 : tw2;
-  R.n = int(n2); R.nrows = int(n1); R.Sn = int(n2 | 1); R.R = block_width(R.Sn, sizeof(C)); R.fs = s2;
-  lds = sizeof(C) * (n2 + size_t(R.R) * R.Sn);
-  dim3 g2(cdiv(n1, R.R), unsigned(B));
-  return inv ? launch(k_row_fft<C, true>, g2, lds, st, R, "length-L transform, row pass")
-             : launch(k_row_fft<C, false>, g2, lds, st, R, "length-L transform, row pass");
-}
-
-template <typename C> ChirpSrc<C> no_chirp(const Plan& P) {
-  ChirpSrc<C> c;
-  c.tab = nullptr; c.K = 0; c.L = P.L; c.conj = 0;
-  return c;
-}
-template <typename C> ChirpSrc<C> chirp_tab(const Plan& P, size_t off, int conj) {
-  ChirpSrc<C> c;
-  c.tab = off ? tab<C>(P, off) : nullptr; c.K = 0; c.L = P.L; c.conj = conj;
-  return c;
-}
-ChirpSrc<double2> chirp_fly(const Plan& P, long long s, int conj) {
-  ChirpSrc<double2> c;
-  c.tab = nullptr; c.K = chirpK(P, s); c.L = P.L; c.conj = conj;
-  return c;
-}
-
-template <typename C>
-int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, char* ws, const Layout& l,
-                 hipStream_t st) {
-  C* H = reinterpret_cast<C*>(ws + l.H);
-  int rc;
-  if (P.branch != kFreqShear) {
-    rc = run_cols<C>(P, f, P.L, real_in, chirp_tab<C>(P, P.off.chirp1, 0), H, B, st);
-  } else {
-    C* F = reinterpret_cast<C*>(ws + l.F);
-    C* Y = reinterpret_cast<C*>(ws + l.Y);
-    rc = run_four_step<C>(P, f, real_in, Y, F, B, false, chirp_tab<C>(P, P.off.chirp1, 0),
-                          chirp_tab<C>(P, P.off.chirp0, 0), 1, tab<C>(P, P.off.tw_L), tab<C>(P, P.off.tw_1),
-                          tab<C>(P, P.off.tw_2), st);
-    if (rc) return rc;
-    rc = run_cols<C>(P, F, P.L, 0, no_chirp<C>(P), H, B, st);
-  }
-  if (rc) return rc;
-  return run_rows<C>(P, H, c, B, false, st);
-}
-
-template <typename C>
-int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const Layout& l, hipStream_t st) {
-  C* H = reinterpret_cast<C*>(ws + l.H);
-  int rc = run_rows<C>(P, H, const_cast<C*>(c), B, true, st);
-  if (rc) return rc;
-  if (P.branch != kFreqShear) return run_adj_cols<C>(P, H, chirp_tab<C>(P, P.off.chirp1, 1), f, B, st);
-  C* F = reinterpret_cast<C*>(ws + l.F);
-  C* Y = reinterpret_cast<C*>(ws + l.Y);
-  rc = run_adj_cols<C>(P, H, no_chirp<C>(P), F, B, st);
-  if (rc) return rc;
-  return run_four_step<C>(P, F, 0, Y, f, B, true, chirp_tab<C>(P, P.off.chirp0, 1),
-                          chirp_tab<C>(P, P.off.chirp1, 1), 1, tab<C>(P, P.off.tw_L), tab<C>(P, P.off.tw_1),
-                          tab<C>(P, P.off.tw_2), st);
-}
-
-template <typename C>
-int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* ws, const Layout& l,
-              hipStream_t st) {
-  C* H = reinterpret_cast<C*>(ws + l.H);
-  C* part = reinterpret_cast<C*>(ws + l.part);
-  int rc = run_rows<C>(P, H, const_cast<C*>(gc), B, true, st);
-  if (rc) return rc;
-  const void* x = f;
-  ChirpSrc<C> ch = chirp_tab<C>(P, P.off.chirp1, 0);
-  const bool fs = P.branch == kFreqShear;
-  if (fs) {
-    C* F = reinterpret_cast<C*>(ws + l.F);
-    C* Y = reinterpret_cast<C*>(ws + l.Y);
-    rc = run_four_step<C>(P, f, 0, Y, F, B, false, chirp_tab<C>(P, P.off.chirp1, 0),
-                          chirp_tab<C>(P, P.off.chirp0, 0), 1, tab<C>(P, P.off.tw_L), tab<C>(P, P.off.tw_1),
-                          tab<C>(P, P.off.tw_2), st);
-    if (rc) return rc;
-    x = F;
-    ch = no_chirp<C>(P);
-  }
-  GradArgs<C> A;
-  A.x = x; A.xs = P.L; A.real_in = 0; A.chirp = ch;
-  A.H = H; A.hs = (long long)P.Mi * P.Ni;
-  A.part = part; A.ps = P.L;
-  A.twd = tab<C>(P, P.off.tw_d);
-  A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.q = int(P.qi);
-  A.Sd = int(P.di | 1);
-  A.W = block_width(2 * A.Sd, sizeof(C));
-  A.fd = sched(P.fd);
-  size_t lds = sizeof(C) * (P.di + 2 * size_t(A.W) * A.Sd);
-  rc = launch(k_grad_cols<C>, dim3(cdiv(P.Mi, A.W), unsigned(B)), lds, st, A, "window gradient");
-  if (rc) return rc;
-  if (!fs) {
-    return launch_raw(k_batch_sum<C>, dim3(cdiv(P.L, kThreads)), dim3(kThreads), 0, st, "batch sum", part,
-                      (long long)P.L, int(B), (long long)P.L, chirp_tab<C>(P, P.off.chirp1, 1), gg);
-  }
-  C* G = reinterpret_cast<C*>(ws + l.G);
-  rc = launch_raw(k_batch_sum<C>, dim3(cdiv(P.L, kThreads)), dim3(kThreads), 0, st, "batch sum", part,
-                  (long long)P.L, int(B), (long long)P.L, no_chirp<C>(P), G);
-  if (rc) return rc;
-  // the frequency-domain window is p0 FFT(p1 g) / L: its adjoint is
-  // conj(p1) IFFT_unnormalised(conj(p0) .) / L
-  C* Y = reinterpret_cast<C*>(ws + l.Y);
-  using T = decltype(C::x);
-  return run_four_step<C>(P, G, 0, Y, gg, 1, true, chirp_tab<C>(P, P.off.chirp0, 1),
-                          chirp_tab<C>(P, P.off.chirp1, 1), T(1) / T(P.L), tab<C>(P, P.off.tw_L),
-                          tab<C>(P, P.off.tw_1), tab<C>(P, P.off.tw_2), st);
-}
-
-// FP64 window preparation: Zak of the sheared window; writes the plan-dtype
-// conj(Z)/d table (zc_out) and/or the FP64 Zak (z64_out).
-template <typename CO>
-int window_zak(const Plan& P, const double2* g, CO* zc_out, double2* z64_out, char* ws, const Layout& l,
-               hipStream_t st) {
-  const double2* src = g;
-  ChirpSrc<double2> ch = chirp_fly(P, P.sh.s1, 0);
-  if (P.branch == kSeparable) ch = no_chirp<double2>(P);
-  if (P.branch == kFreqShear) {
-    double2* Y = reinterpret_cast<double2*>(ws + l.Y);
-    double2* G = reinterpret_cast<double2*>(ws + l.G);
-    int rc = run_four_step<double2>(P, g, 0, Y, G, 1, false, chirp_fly(P, P.sh.s1, 0), chirp_fly(P, -P.sh.s0, 0),
-                                    1.0 / double(P.L), nullptr, tab<double2>(P, P.off.tw_1_64),
-                                    tab<double2>(P, P.off.tw_2_64), st);
-    if (rc) return rc;
-    src = G;
-    ch = no_chirp<double2>(P);
-  }
-  ZakArgs<CO> Z;
-  Z.x = src; Z.chirp = ch; Z.zc = zc_out; Z.z64 = z64_out;
-  Z.twd = tab<double2>(P, P.off.tw_d64);
-  Z.Mi = int(P.Mi); Z.d = int(P.di); Z.p = int(P.pi); Z.Sd = int(P.di | 1);
-  Z.W = block_width(P.pi * Z.Sd, 16);
-  Z.fd = sched(P.fd);
-  size_t lds = 16 * (P.di + size_t(Z.W) * P.pi * Z.Sd);
-  return launch(k_zak_fwd<CO>, dim3(cdiv(P.Mi, Z.W), 1), lds, st, Z, "window Zak transform");
 }
 
 void put_tab(std::vector<unsigned char>& img, size_t off, const std::vector<double>& v, int dtype) {
@@ -520,8 +164,7 @@ int dgtns_set_window(dgtns_plan plan, const void* g_dev, void* ws, size_t ws_byt
   hipStream_t st = static_cast<hipStream_t>(stream);
   const double2* g = static_cast<const double2*>(g_dev);
   char* w = static_cast<char*>(ws);
-  if (P.dtype == 0) rc = window_zak<float2>(P, g, mtab<float2>(P, P.off.zc), nullptr, w, l, st);
-  else rc = window_zak<double2>(P, g, mtab<double2>(P, P.off.zc), nullptr, w, l, st);
+  rc = P.dtype == 0 ? set_window_c64(P, g, w, l, st) : set_window_c128(P, g, w, l, st);
   if (rc) return rc;
   P.window_set = true;
   return DGTNS_OK;
@@ -536,8 +179,8 @@ int dgtns_forward(dgtns_plan plan, const void* f_dev, int real_input, void* c_de
   const Plan& P = plan->p;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  if (P.dtype == 0) return forward_impl<float2>(P, f_dev, real_input ? 1 : 0, static_cast<float2*>(c_dev), B, w, l, st);
-  return forward_impl<double2>(P, f_dev, real_input ? 1 : 0, static_cast<double2*>(c_dev), B, w, l, st);
+  if (P.dtype == 0) return forward_c64(P, f_dev, real_input ? 1 : 0, c_dev, B, w, l, st);
+  return forward_c128(P, f_dev, real_input ? 1 : 0, c_dev, B, w, l, st);
 }
 
 int dgtns_adjoint(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, void* ws, size_t ws_bytes,
@@ -549,9 +192,8 @@ int dgtns_adjoint(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, vo
   const Plan& P = plan->p;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  if (P.dtype == 0)
-    return adjoint_impl<float2>(P, static_cast<const float2*>(c_dev), static_cast<float2*>(f_dev), B, w, l, st);
-  return adjoint_impl<double2>(P, static_cast<const double2*>(c_dev), static_cast<double2*>(f_dev), B, w, l, st);
+  if (P.dtype == 0) return adjoint_c64(P, c_dev, f_dev, B, w, l, st);
+  return adjoint_c128(P, c_dev, f_dev, B, w, l, st);
 }
 
 int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, void* gg_dev, int64_t B, void* ws,
@@ -564,11 +206,8 @@ int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, vo
   if (P.pi != 1) return fail(DGTNS_EUNSUPPORTED, "window gradient is implemented for p = 1 of the sheared lattice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  if (P.dtype == 0)
-    return grad_impl<float2>(P, static_cast<const float2*>(f_dev), static_cast<const float2*>(gc_dev),
-                             static_cast<float2*>(gg_dev), B, w, l, st);
-  return grad_impl<double2>(P, static_cast<const double2*>(f_dev), static_cast<const double2*>(gc_dev),
-                            static_cast<double2*>(gg_dev), B, w, l, st);
+  if (P.dtype == 0) return grad_c64(P, f_dev, gc_dev, gg_dev, B, w, l, st);
+  return grad_c128(P, f_dev, gc_dev, gg_dev, B, w, l, st);
 }
 
 int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* bounds_dev, void* ws,
@@ -581,47 +220,7 @@ int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* 
   if (P.pi != 1) return fail(DGTNS_EUNSUPPORTED, "dual window is implemented for p = 1 of the sheared lattice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  double2* Z = reinterpret_cast<double2*>(w + l.H);
-  double2* Zd = reinterpret_cast<double2*>(w + l.F);
-  double2* Gd = reinterpret_cast<double2*>(w + l.G);
-  double* part = reinterpret_cast<double*>(w + l.part);
-  // the Zak of the frequency-sheared window uses the Y/G scratch of set_window:
-  // map it onto this layout (Y = l.Y, G = Gd before it is overwritten)
-  Layout lw;
-  lw.Y = l.Y;
-  lw.G = l.G;
-  rc = window_zak<double2>(P, static_cast<const double2*>(g_dev), nullptr, Z, w, lw, st);
-  if (rc) return rc;
-  const long long tot = P.Mi * P.di;
-  const unsigned nb = cdiv(tot, kThreads);
-  const double sb = P.branch == kFreqShear ? double(P.L) : 1.0;
-  rc = launch_raw(k_dual_div, dim3(nb), dim3(kThreads), 0, st, "dual division", Z, Zd, part, int(P.Mi),
-                  int(P.di), int(P.ai), int(P.qi), sb);
-  if (rc) return rc;
-  rc = launch_raw(k_minmax_final, dim3(1), dim3(kThreads), 0, st, "frame bounds", (const double*)part, int(nb),
-                  bounds_dev);
-  if (rc) return rc;
-  ZakInvArgs Zi;
-  Zi.z = Zd;
-  Zi.twd = tab<double2>(P, P.off.tw_d64);
-  Zi.Mi = int(P.Mi); Zi.d = int(P.di); Zi.p = int(P.pi); Zi.Sd = int(P.di | 1);
-  Zi.W = block_width(Zi.Sd, 16);
-  Zi.fd = sched(P.fd);
-  size_t lds = 16 * (P.di + size_t(Zi.W) * Zi.Sd);
-  if (P.branch != kFreqShear) {
-    Zi.chirp = P.branch == kSeparable ? no_chirp<double2>(P) : chirp_fly(P, P.sh.s1, 1);
-    Zi.x = static_cast<double2*>(gd_dev);
-    return launch(k_zak_inv, dim3(cdiv(P.Mi, Zi.W), 1), lds, st, Zi, "inverse Zak");
-  }
-  Zi.chirp = no_chirp<double2>(P);
-  Zi.x = Gd;
-  rc = launch(k_zak_inv, dim3(cdiv(P.Mi, Zi.W), 1), lds, st, Zi, "inverse Zak");
-  if (rc) return rc;
-  // g_d = conj(p1) IFFT(conj(p0) dual_sep(G))  (Alg. 2 with the time shear undone)
-  double2* Y = reinterpret_cast<double2*>(w + l.Y);
-  return run_four_step<double2>(P, Gd, 0, Y, static_cast<double2*>(gd_dev), 1, true, chirp_fly(P, -P.sh.s0, 1),
-                                chirp_fly(P, P.sh.s1, 1), 1.0 / double(P.L), nullptr,
-                                tab<double2>(P, P.off.tw_1_64), tab<double2>(P, P.off.tw_2_64), st);
+  return dual_c128(P, static_cast<const double2*>(g_dev), static_cast<double2*>(gd_dev), bounds_dev, w, l, st);
 }
 
 int dgtns_timing_enable(int on) {

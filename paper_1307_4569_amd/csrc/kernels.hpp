@@ -11,7 +11,8 @@
 //   h_{n0 + q t'}(r) = sum_nu exp(2 pi i nu t'/d) sum_{j0} X_{r,j0}(nu)
 //                       conj(Zg_{u,j0'}(nu)) exp(-2 pi i nu delta/d) / d,
 // where r - n0 ai + Mi j0 = u + Mi (j0' + p delta), u in Z_Mi, j0' in Z_p,
-// and c_r(m, n) = sum_r h_n(r) exp(-2 pi i r m / Mi).  The plan stores
+// and c_r(m, n) = sum_r h_n(r) exp(-2 pi i r m / Mi).  The intermediate h is
+// stored per signal as h[n0][r][t'] (t' fastest).  The plan stores
 // Zc = conj(Zg) / d.  Kernel "cols" computes h (all q time offsets n0 of one
 // block of W adjacent columns per work-group, the DFT of the signal columns
 // kept in registers), kernel "rows" the channel DFT of each time position and
@@ -167,8 +168,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
     __syncthreads();
     fft_lds<C, true>(yb, Sd, A.fd, W, tw);
     for (int e = threadIdx.x; e < WD; e += kThreads) {
-      const int t = e / W, cc = e - t * W, r = r0 + cc;
-      if (r < Mi) A.H[bo * A.hs + (long long)(n0 + A.q * t) * Mi + r] = yb[cc * Sd + t];
+      const int cc = e / d, t = e - cc * d, r = r0 + cc;
+      if (r < Mi) A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t] = yb[cc * Sd + t];
     }
   }
 }
@@ -211,8 +212,8 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
   for (int n0 = 0; n0 < A.q; ++n0) {
     __syncthreads();
     for (int e = threadIdx.x; e < WD; e += kThreads) {
-      const int t = e / W, cc = e - t * W, r = r0 + cc;
-      yb[cc * Sd + t] = r < Mi ? A.H[bo * A.hs + (long long)(n0 + A.q * t) * Mi + r] : czero<C>();
+      const int cc = e / d, t = e - cc * d, r = r0 + cc;
+      yb[cc * Sd + t] = r < Mi ? A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t] : czero<C>();
     }
     __syncthreads();
     fft_lds<C, false>(yb, Sd, A.fd, W, tw);
@@ -273,7 +274,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
 
 // ----------------------------------------------------------------------------
 // Row kernels: channel DFT per time position plus the post-processing of
-// Alg. 1, and the adjoint.  grid (ceil(Ni/R), B), 512 threads.
+// Alg. 1, and the adjoint.  A work-group handles the R time positions
+// n = n0 + q (t0 + i), i in Z_R (n0 = blockIdx.x mod q), whose intermediate
+// values h[n0][r][t0 + i] are contiguous in i.  grid (q ceil(d/R), B), 512
+// threads.
 //   MODE 0 (s0 = 0): c((m + rho_n) mod M, n) = E_n c_r(m, n), tables E, rho.
 //   MODE 1 (s0 != 0): row = inner position m in Z_{M_r}, FFT over the N_r
 //     inner channels k'; with k = -k' mod N_r,
@@ -291,7 +295,7 @@ template <typename C> struct RowArgs {
   const C* twm;
   const C* postE;
   const int* rho;
-  int Mi, Ni, R, Sm;
+  int Mi, Ni, R, Sm, q, d;
   FftSched fm;
   long long N, L, b, M, K1, K2, K3, K4, K5, C1n, C2n, Kt1, Kt6;
 };
@@ -319,19 +323,20 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows(RowArgs<C> A) {
   const int Mi = A.Mi, R = A.R, Sm = A.Sm;
   C* buf = tw + Mi;
   for (int e = threadIdx.x; e < Mi; e += kThreads) tw[e] = A.twm[e];
-  const int n_0 = blockIdx.x * R;
+  const int q = A.q, d = A.d, n0 = blockIdx.x % q, t0 = (blockIdx.x / q) * R;
   const long long bo = blockIdx.y;
-  const C* Hb = A.H + bo * A.hs;
+  const C* Hb = A.H + bo * A.hs + (long long)n0 * Mi * d + t0;
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
-    const int row = e / Mi, m = e - row * Mi, n = n_0 + row;
-    buf[row * Sm + m] = n < A.Ni ? Hb[(long long)n * Mi + m] : czero<C>();
+    const int m = e / R, i = e - m * R;
+    buf[i * Sm + m] = t0 + i < d ? Hb[(long long)m * d + i] : czero<C>();
   }
   __syncthreads();
   fft_lds<C, false>(buf, Sm, A.fm, R, tw);
   C* cb = A.c + bo * A.cs;
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
-    const int row = e / Mi, mo = e - row * Mi, n = n_0 + row;
-    if (n >= A.Ni) continue;
+    const int row = e / Mi, mo = e - row * Mi;
+    if (t0 + row >= d) continue;
+    const int n = n0 + q * (t0 + row);
     if (MODE == 0) {
       int mi = mo - A.rho[n];
       if (mi < 0) mi += Mi;
@@ -353,13 +358,13 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows(RowArgs<C> A) {
   const int Mi = A.Mi, R = A.R, Sm = A.Sm;
   C* buf = tw + Mi;
   for (int e = threadIdx.x; e < Mi; e += kThreads) tw[e] = A.twm[e];
-  const int n_0 = blockIdx.x * R;
+  const int q = A.q, d = A.d, n0 = blockIdx.x % q, t0 = (blockIdx.x / q) * R;
   const long long bo = blockIdx.y;
   const C* cb = A.c + bo * A.cs;
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
-    const int row = e / Mi, m = e - row * Mi, n = n_0 + row;
+    const int row = e / Mi, m = e - row * Mi, n = n0 + q * (t0 + row);
     C v = czero<C>();
-    if (n < A.Ni) {
+    if (t0 + row < d) {
       if (MODE == 0) {
         int mo = m + A.rho[n];
         if (mo >= Mi) mo -= Mi;
@@ -376,10 +381,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows(RowArgs<C> A) {
   }
   __syncthreads();
   fft_lds<C, true>(buf, Sm, A.fm, R, tw);
-  C* Hb = const_cast<C*>(A.H) + bo * A.hs;
+  C* Hb = const_cast<C*>(A.H) + bo * A.hs + (long long)n0 * Mi * d + t0;
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
-    const int row = e / Mi, m = e - row * Mi, n = n_0 + row;
-    if (n < A.Ni) Hb[(long long)n * Mi + m] = buf[row * Sm + m];
+    const int m = e / R, i = e - m * R;
+    if (t0 + i < d) Hb[(long long)m * d + i] = buf[i * Sm + m];
   }
 }
 
@@ -527,6 +532,7 @@ struct ZakInvArgs {
   FftSched fd;
 };
 
+template <int Unused = 0>
 __global__ void __launch_bounds__(kThreads) k_zak_inv(ZakInvArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double2* tw = reinterpret_cast<double2*>(smem_raw);
@@ -557,6 +563,7 @@ __global__ void __launch_bounds__(kThreads) k_zak_inv(ZakInvArgs A) {
 //   D(u, nu) = Mi sum_{n0 in Z_q} |Zg_{(u - n0 ai) mod Mi}(nu)|^2,
 // so Zd = Zg / D.  Each block also writes its min and max of D.
 // ----------------------------------------------------------------------------
+template <int Unused = 0>
 __global__ void __launch_bounds__(kThreads) k_dual_div(const double2* z, double2* zd, double* part, int Mi, int d,
                                                       int ai, int q, double scale_bounds) {
   __shared__ double smin[kThreads], smax[kThreads];
@@ -595,6 +602,7 @@ __global__ void __launch_bounds__(kThreads) k_dual_div(const double2* z, double2
   }
 }
 
+template <int Unused = 0>
 __global__ void __launch_bounds__(kThreads) k_minmax_final(const double* part, int nparts, double* out) {
   __shared__ double smin[kThreads], smax[kThreads];
   double mn = 1e308, mx = 0;
@@ -661,15 +669,23 @@ __global__ void __launch_bounds__(kThreads) k_grad_cols(GradArgs<C> A) {
     __syncthreads();
     for (int e = threadIdx.x; e < WD; e += kThreads) {
       const int t = e / W, cc = e - t * W, u = u0 + cc;
-      C v = czero<C>(), h = czero<C>();
+      C v = czero<C>();
       if (u < Mi) {
         int r = u + n0 * A.ai;
         if (r >= Mi) r -= Mi;
         const long long l = r + (long long)t * Mi;
         v = apply_chirp(A.chirp, load_sig<C>(A.x, A.real_in, bo * A.xs + l), l);
-        h = A.H[bo * A.hs + (long long)(n0 + A.q * t) * Mi + r];
       }
       xb[cc * Sd + t] = v;
+    }
+    for (int e = threadIdx.x; e < WD; e += kThreads) {
+      const int cc = e / d, t = e - cc * d, u = u0 + cc;
+      C h = czero<C>();
+      if (u < Mi) {
+        int r = u + n0 * A.ai;
+        if (r >= Mi) r -= Mi;
+        h = A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t];
+      }
       yb[cc * Sd + t] = h;
     }
     __syncthreads();

@@ -1,0 +1,296 @@
+// Wave-FFT versions of the four hot kernels for power-of-two transform
+// lengths (p = 1): forward factorisation ("cols"), channel DFT with the
+// post-processing of Alg. 1 ("rows"), and their adjoints.
+//
+// Intermediate layout (shared with the generic kernels): per signal
+//   h[n0][r][t'] = h_{n0 + q t'}(r),   n0 in Z_q, r in Z_Mi, t' in Z_d,
+// so a factorisation column writes d contiguous values per time offset n0,
+// and a row kernel reads, for each channel r, a contiguous run of time
+// positions t' (one work-group handles RB consecutive t' of one n0).
+#pragma once
+#include "kernels.hpp"
+#include "wave_fft.hpp"
+
+namespace dgtns {
+
+// elements per work-group: 8192 (FP32) or 4096 (FP64)
+template <typename C> struct Budget { static constexpr int value = sizeof(C) == 8 ? 8192 : 4096; };
+
+// Columns per work-group of the fast factorisation kernels for length D.
+template <typename C, int D> struct FastCols {
+  static constexpr int TPW = WInfo<D>::TPW;
+  static constexpr int K0 = Budget<C>::value / (8 * TPW * D);
+  static constexpr int K = K0 < 1 ? 1 : K0;       // wave transforms per wavefront
+  static constexpr int W = 8 * TPW * K;           // columns per work-group (8 wavefronts)
+  static constexpr int SD = D + 1;                // padded column stride of the LDS tile
+  static constexpr int TILE = W * SD;
+  static constexpr int EXW = TPW * WInfo<D>::EX;  // exchange elements per wavefront
+  static constexpr int LDS = (TILE > 8 * EXW ? TILE : 8 * EXW);
+};
+
+// Rows per work-group of the fast row kernels for length MI.
+template <typename C, int MI> struct FastRows {
+  static constexpr int TPW = WInfo<MI>::TPW;
+  static constexpr int K0 = Budget<C>::value / (8 * TPW * MI);
+  static constexpr int K = K0 < 1 ? 1 : K0;
+  static constexpr int RB = 8 * TPW * K;          // rows (time positions t') per work-group
+  static constexpr int SR = RB + 1;               // padded stride of the [Mi][RB] tile
+  static constexpr int TILE = MI * SR;
+  static constexpr int EXW = TPW * WInfo<MI>::EX;
+  static constexpr int LDS = (TILE > 8 * EXW ? TILE : 8 * EXW);
+};
+
+// ----------------------------------------------------------------------------
+// Forward factorisation, p = 1, compile-time d = D.
+// grid (ceil(Mi / W), B), 512 threads.
+// ----------------------------------------------------------------------------
+template <typename C, int D>
+__global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
+  using F = FastCols<C, D>;
+  using I = WInfo<D>;
+  constexpr int E = I::E, T = I::T, K = F::K, W = F::W, SD = F::SD;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
+  const int Mi = A.Mi;
+  const int r0 = blockIdx.x * W;
+  const long long bo = blockIdx.y;
+  // 1. coalesced load of W adjacent columns (d values each), chirp applied
+  for (int e = tid; e < W * D; e += kThreads) {
+    const int t = e / W, cc = e - t * W, r = r0 + cc;
+    C v = czero<C>();
+    if (r < Mi) {
+      const long long li = r + (long long)t * Mi;
+      v = apply_chirp(A.chirp, load_sig<C>(A.x, A.real_in, bo * A.xs + li), li);
+    }
+    lds[cc * SD + t] = v;
+  }
+  WTw<C, D> tw;
+  tw.load(A.twd, l);
+  __syncthreads();
+  C X[K][E];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int cc = (wave * K + k) * I::TPW + tt;
+#pragma unroll
+    for (int e = 0; e < E; ++e) X[k][e] = lds[cc * SD + l + T * e];
+  }
+  __syncthreads();
+  C* ex = lds + wave * F::EXW + tt * I::EX;
+#pragma unroll
+  for (int k = 0; k < K; ++k) wave_fft<C, D, false>(X[k], ex, l, tw);
+  const C* tw_d = A.twd;
+  for (int n0 = 0; n0 < A.q; ++n0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int r = r0 + (wave * K + k) * I::TPW + tt;
+      const bool ok = r < Mi;
+      const int v0 = r - n0 * A.ai;
+      const int u = v0 >= 0 ? v0 : v0 + Mi;
+      const C* zrow = A.zc + (long long)(ok ? u : 0) * D;
+      C Y[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int nu = l + T * e;
+        C z = zrow[nu];
+        if (v0 < 0) z = cmulc(z, tw_d[nu]);
+        Y[e] = cmul(X[k][e], z);
+      }
+      wave_fft<C, D, true>(Y, ex, l, tw);
+      if (ok) {
+        C* hb = A.H + bo * A.hs + ((long long)n0 * Mi + r) * D;
+#pragma unroll
+        for (int e = 0; e < E; ++e) hb[l + T * e] = Y[e];
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint factorisation, p = 1, compile-time d = D.
+// ----------------------------------------------------------------------------
+template <typename C, int D>
+__global__ void __launch_bounds__(kThreads) k_adj_cols_w(ColAdjArgs<C> A) {
+  using F = FastCols<C, D>;
+  using I = WInfo<D>;
+  constexpr int E = I::E, T = I::T, K = F::K, W = F::W, SD = F::SD;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
+  const int Mi = A.Mi;
+  const int r0 = blockIdx.x * W;
+  const long long bo = blockIdx.y;
+  WTw<C, D> tw;
+  tw.load(A.twd, l);
+  C* ex = lds + wave * F::EXW + tt * I::EX;
+  C acc[K][E];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[k][e] = czero<C>();
+  for (int n0 = 0; n0 < A.q; ++n0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int r = r0 + (wave * K + k) * I::TPW + tt;
+      const bool ok = r < Mi;
+      C Y[E];
+      const C* hb = A.H + bo * A.hs + ((long long)n0 * Mi + (ok ? r : 0)) * D;
+#pragma unroll
+      for (int e = 0; e < E; ++e) Y[e] = hb[l + T * e];
+      wave_fft<C, D, false>(Y, ex, l, tw);
+      const int v0 = r - n0 * A.ai;
+      const int u = v0 >= 0 ? v0 : v0 + Mi;
+      const C* zrow = A.zc + (long long)(ok ? u : 0) * D;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int nu = l + T * e;
+        C z = zrow[nu];
+        if (v0 < 0) z = cmulc(z, A.twd[nu]);
+        acc[k][e] = cadd(acc[k][e], cmulc(Y[e], z));
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) wave_fft<C, D, true>(acc[k], ex, l, tw);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int cc = (wave * K + k) * I::TPW + tt;
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[cc * SD + l + T * e] = acc[k][e];
+  }
+  __syncthreads();
+  for (int e = tid; e < W * D; e += kThreads) {
+    const int t = e / W, cc = e - t * W, r = r0 + cc;
+    if (r < Mi) {
+      const long long li = r + (long long)t * Mi;
+      A.y[bo * A.ys + li] = apply_chirp(A.chirp, lds[cc * SD + t], li);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Row kernels, compile-time Mi = MI.  A work-group handles the RB time
+// positions n = n0 + q (t0 + i), i in Z_RB, with n0 = blockIdx.x mod q.
+// grid (q * ceil(d / RB), B), 512 threads.
+// ----------------------------------------------------------------------------
+template <typename C, int MI, int MODE>
+__global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
+  using F = FastRows<C, MI>;
+  using I = WInfo<MI>;
+  constexpr int E = I::E, T = I::T, K = F::K, RB = F::RB, SR = F::SR;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
+  const int q = A.q, d = A.d;
+  const int n0 = blockIdx.x % q, t0 = (blockIdx.x / q) * RB;
+  const long long bo = blockIdx.y;
+  const C* hb = A.H + bo * A.hs + (long long)n0 * MI * d + t0;
+  for (int e = tid; e < RB * MI; e += kThreads) {
+    const int m = e / RB, i = e - m * RB;
+    lds[m * SR + i] = t0 + i < d ? hb[(long long)m * d + i] : czero<C>();
+  }
+  WTw<C, MI> tw;
+  tw.load(A.twm, l);
+  __syncthreads();
+  C v[K][E];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = (wave * K + k) * I::TPW + tt;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[k][e] = lds[(l + T * e) * SR + i];
+  }
+  __syncthreads();
+  C* ex = lds + wave * F::EXW + tt * I::EX;
+  C* cb = A.c + bo * A.cs;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    wave_fft<C, MI, false>(v[k], ex, l, tw);
+    const int i = (wave * K + k) * I::TPW + tt;
+    const int n = n0 + q * (t0 + i);
+    if (t0 + i >= d) {
+      // time position beyond d in the last work-group: nothing to store
+    } else if (MODE == 0) {
+      const C En = A.postE[n];
+      const int rho = A.rho[n];
+      C* row = cb + (long long)n * MI;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        int mo = l + T * e + rho;
+        if (mo >= MI) mo -= MI;
+        row[mo] = cmul(En, v[k][e]);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int kp = l + T * e;
+        const long long kk = kp == 0 ? 0 : MI - kp;
+        long long dst;
+        C Ev;
+        shear_map(A, n, kk, &dst, &Ev);
+        cb[dst] = cmul(Ev, v[k][e]);
+      }
+    }
+  }
+}
+
+template <typename C, int MI, int MODE>
+__global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
+  using F = FastRows<C, MI>;
+  using I = WInfo<MI>;
+  constexpr int E = I::E, T = I::T, K = F::K, RB = F::RB, SR = F::SR;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
+  const int q = A.q, d = A.d;
+  const int n0 = blockIdx.x % q, t0 = (blockIdx.x / q) * RB;
+  const long long bo = blockIdx.y;
+  WTw<C, MI> tw;
+  tw.load(A.twm, l);
+  C* ex = lds + wave * F::EXW + tt * I::EX;
+  const C* cb = A.c + bo * A.cs;
+  C v[K][E];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = (wave * K + k) * I::TPW + tt;
+    const bool ok = t0 + i < d;
+    const int n = n0 + q * (ok ? t0 + i : 0);
+    if (MODE == 0) {
+      const C En = A.postE[n];
+      const int rho = A.rho[n];
+      const C* row = cb + (long long)n * MI;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        int mo = l + T * e + rho;
+        if (mo >= MI) mo -= MI;
+        v[k][e] = cmulc(row[mo], En);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int kp = l + T * e;
+        const long long kk = kp == 0 ? 0 : MI - kp;
+        long long src;
+        C Ev;
+        shear_map(A, n, kk, &src, &Ev);
+        v[k][e] = cmulc(cb[src], Ev);
+      }
+    }
+    wave_fft<C, MI, true>(v[k], ex, l, tw);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = (wave * K + k) * I::TPW + tt;
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds[(l + T * e) * SR + i] = v[k][e];
+  }
+  __syncthreads();
+  C* hb = const_cast<C*>(A.H) + bo * A.hs + (long long)n0 * MI * d + t0;
+  for (int e = tid; e < RB * MI; e += kThreads) {
+    const int m = e / RB, i = e - m * RB;
+    if (t0 + i < d) hb[(long long)m * d + i] = lds[m * SR + i];
+  }
+}
+
+}  // namespace dgtns

@@ -1,0 +1,32 @@
+// Kernel launchers instantiated for complex128 plans.
+#include "launch.hpp"
+
+namespace dgtns {
+namespace host {
+
+int forward_c128(const Plan& P, const void* f, int real_in, void* c, long long B, char* ws, const Layout& l,
+                 hipStream_t st) {
+  return forward_impl<double2>(P, f, real_in, static_cast<double2*>(c), B, ws, l, st);
+}
+
+int adjoint_c128(const Plan& P, const void* c, void* f, long long B, char* ws, const Layout& l, hipStream_t st) {
+  return adjoint_impl<double2>(P, static_cast<const double2*>(c), static_cast<double2*>(f), B, ws, l, st);
+}
+
+int grad_c128(const Plan& P, const void* f, const void* gc, void* gg, long long B, char* ws, const Layout& l,
+              hipStream_t st) {
+  return grad_impl<double2>(P, static_cast<const double2*>(f), static_cast<const double2*>(gc), static_cast<double2*>(gg), B, ws, l,
+                             st);
+}
+
+int set_window_c128(const Plan& P, const double2* g, char* ws, const Layout& l, hipStream_t st) {
+  return window_zak<double2>(P, g, mtab<double2>(P, P.off.zc), nullptr, ws, l, st);
+}
+
+int dual_c128(const Plan& P, const double2* g, double2* gd, double* bounds, char* ws, const Layout& l,
+              hipStream_t st) {
+  return dual_impl(P, g, gd, bounds, ws, l, st);
+}
+
+}  // namespace host
+}  // namespace dgtns

@@ -1,0 +1,27 @@
+// Kernel launchers instantiated for complex64 plans.
+#include "launch.hpp"
+
+namespace dgtns {
+namespace host {
+
+int forward_c64(const Plan& P, const void* f, int real_in, void* c, long long B, char* ws, const Layout& l,
+                hipStream_t st) {
+  return forward_impl<float2>(P, f, real_in, static_cast<float2*>(c), B, ws, l, st);
+}
+
+int adjoint_c64(const Plan& P, const void* c, void* f, long long B, char* ws, const Layout& l, hipStream_t st) {
+  return adjoint_impl<float2>(P, static_cast<const float2*>(c), static_cast<float2*>(f), B, ws, l, st);
+}
+
+int grad_c64(const Plan& P, const void* f, const void* gc, void* gg, long long B, char* ws, const Layout& l,
+             hipStream_t st) {
+  return grad_impl<float2>(P, static_cast<const float2*>(f), static_cast<const float2*>(gc), static_cast<float2*>(gg), B, ws, l,
+                            st);
+}
+
+int set_window_c64(const Plan& P, const double2* g, char* ws, const Layout& l, hipStream_t st) {
+  return window_zak<float2>(P, g, mtab<float2>(P, P.off.zc), nullptr, ws, l, st);
+}
+
+}  // namespace host
+}  // namespace dgtns

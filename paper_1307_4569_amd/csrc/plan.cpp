@@ -2,6 +2,7 @@
 #include "plan.hpp"
 
 #include <cmath>
+#include <cstdlib>
 #include <map>
 
 namespace dgtns {
@@ -232,6 +233,10 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   p.s = p.b * lam1 / lam2;   // absolute shear in normal form (Section 2.1)
   p.dtype = dtype;
   p.max_batch = max_batch;
+  {
+    const char* gen = std::getenv("DGTNS_GENERIC");
+    p.generic = gen && gen[0] == '1';
+  }
   p.sh = shearfind(L, a, M, p.s, p.b, err);
   if (p.sh.br == 0) return kELattice;
   if (p.s == 0) p.branch = kSeparable;

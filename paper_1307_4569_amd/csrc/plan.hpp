@@ -83,6 +83,7 @@ struct Plan {
   } off;
   void* dev = nullptr;       // bound persistent memory
   bool window_set = false;
+  bool generic = false;   // force the runtime-schedule kernels (DGTNS_GENERIC=1)
 };
 
 // Returns 0 on success, else an error status with a message in *err.

@@ -1,0 +1,159 @@
+// Wave-level FFT for compile-time power-of-two lengths N in [32, 1024].
+//
+// A transform is owned by T = N / E lanes of one 64-lane wavefront (64 / T
+// transforms per wavefront); lane position l in Z_T holds the E elements
+// x[l + T e] (e in Z_E) in registers.  The transform runs as Stockham passes
+// whose radices divide E: in a pass of radix R each lane computes E / R
+// butterflies, butterfly j = l + T i reading x[j + r N / R] = v[i + r E / R].
+// Results of all passes but the last go through a wave-private LDS region
+// (no work-group barrier: a wavefront issues its LDS instructions in order),
+// and the last pass leaves X[l + T e] in v[e], i.e. the same strided layout,
+// so global loads and stores of a transform are fully coalesced.
+//
+// Twiddles exp(-+ 2 pi i r k / (Ns R)) are read once per lane from the exact
+// length-N table exp(-2 pi i e / N) and kept in registers (they depend only on
+// the lane, not on the data), so a wavefront that transforms many rows pays
+// for them once.
+#pragma once
+#include "fft_core.hpp"
+
+namespace dgtns {
+
+template <int N> struct WSched;
+template <> struct WSched<32> {
+  static constexpr int E = 8, NP = 2;
+  static constexpr int rad(int p) { return p == 0 ? 8 : 4; }
+};
+template <> struct WSched<64> {
+  static constexpr int E = 8, NP = 2;
+  static constexpr int rad(int) { return 8; }
+};
+template <> struct WSched<128> {
+  static constexpr int E = 8, NP = 3;
+  static constexpr int rad(int p) { return p < 2 ? 8 : 2; }
+};
+template <> struct WSched<256> {
+  static constexpr int E = 8, NP = 3;
+  static constexpr int rad(int p) { return p < 2 ? 8 : 4; }
+};
+template <> struct WSched<512> {
+  static constexpr int E = 8, NP = 3;
+  static constexpr int rad(int) { return 8; }
+};
+template <> struct WSched<1024> {
+  static constexpr int E = 16, NP = 3;
+  static constexpr int rad(int p) { return p < 2 ? 8 : 16; }
+};
+
+// radix-16 DFT: radix-8 DFTs of the even and odd elements, combined with W16^k
+template <typename C, bool INV> struct Bfly<C, 16, INV> {
+  static __device__ __forceinline__ void run(C* v) {
+    using T = decltype(C::x);
+    C e[8], o[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      e[k] = v[2 * k];
+      o[k] = v[2 * k + 1];
+    }
+    Bfly<C, 8, INV>::run(e);
+    Bfly<C, 8, INV>::run(o);
+    // W16^k = cos(pi k / 8) -+ i sin(pi k / 8)
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+    const T h = T(0.70710678118654752440);
+    const T cs[8] = {T(1), c1, h, s1, T(0), -s1, -h, -c1};
+    const T sn[8] = {T(0), s1, h, c1, T(1), c1, h, s1};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const C w = mk<C>(cs[k], INV ? sn[k] : -sn[k]);
+      const C t = k == 0 ? o[0] : cmul(o[k], w);
+      v[k] = cadd(e[k], t);
+      v[k + 8] = csub(e[k], t);
+    }
+  }
+};
+
+template <int N> struct WInfo {
+  using S = WSched<N>;
+  static constexpr int E = S::E;
+  static constexpr int T = N / E;       // lanes per transform
+  static constexpr int TPW = 64 / T;    // transforms per wavefront
+  static constexpr int EX = N + N / 32; // padded exchange region per transform
+  static constexpr int ns(int p) { return p == 0 ? 1 : ns(p - 1) * S::rad(p - 1); }
+  static constexpr int ntw_upto(int p) {  // twiddles used by passes 1 .. p-1
+    return p <= 1 ? 0 : ntw_upto(p - 1) + (E / S::rad(p - 1)) * (S::rad(p - 1) - 1);
+  }
+  static constexpr int NTW = ntw_upto(S::NP);
+};
+
+__device__ __forceinline__ int xpad(int i) { return i + (i >> 5); }
+
+// Per-lane twiddles of all passes after the first.
+template <typename C, int N> struct WTw {
+  C w[WInfo<N>::NTW > 0 ? WInfo<N>::NTW : 1];
+
+  template <int P>
+  __device__ __forceinline__ void fill(const C* tab, int l) {
+    if constexpr (P < WSched<N>::NP) {
+      using I = WInfo<N>;
+      constexpr int R = WSched<N>::rad(P), Ns = I::ns(P), NB = I::E / R, step = N / (Ns * R);
+      constexpr int off = I::ntw_upto(P);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int k = (l + I::T * i) & (Ns - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[off + i * (R - 1) + r - 1] = tab[r * k * step];
+      }
+      fill<P + 1>(tab, l);
+    }
+  }
+  __device__ __forceinline__ void load(const C* tab, int l) { fill<1>(tab, l); }
+};
+
+template <typename C, int N, bool INV, int P>
+__device__ __forceinline__ void wave_pass(C (&v)[WInfo<N>::E], C* ex, int l, const WTw<C, N>& tw) {
+  using I = WInfo<N>;
+  constexpr int E = I::E, T = I::T, R = WSched<N>::rad(P), Ns = I::ns(P), NB = E / R;
+  constexpr bool LAST = P == WSched<N>::NP - 1;
+  constexpr int off = I::ntw_upto(P);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    C u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = v[i + r * NB];
+    if constexpr (P > 0) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const C w = tw.w[off + i * (R - 1) + r - 1];
+        u[r] = INV ? cmulc(u[r], w) : cmul(u[r], w);
+      }
+    }
+    Bfly<C, R, INV>::run(u);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i + r * NB] = u[r];
+    } else {
+      const int j = l + T * i;
+      const int k = j & (Ns - 1);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) ex[xpad(base + r * Ns)] = u[r];
+    }
+  }
+  if constexpr (!LAST) {
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = ex[xpad(l + T * e)];
+    __builtin_amdgcn_wave_barrier();
+    wave_pass<C, N, INV, P + 1>(v, ex, l, tw);
+  }
+}
+
+// In-register transform of the N elements held by this lane's transform
+// group; ex: wave-private LDS region of WInfo<N>::EX elements for this
+// transform.  INV: unnormalised inverse.
+template <typename C, int N, bool INV>
+__device__ __forceinline__ void wave_fft(C (&v)[WInfo<N>::E], C* ex, int l, const WTw<C, N>& tw) {
+  wave_pass<C, N, INV, 0>(v, ex, l, tw);
+}
+
+}  // namespace dgtns

@@ -17,6 +17,17 @@ pytestmark = pytest.mark.gpu
 TOL = {torch.complex64: 1e-5, torch.complex128: 1e-12}
 
 
+@pytest.fixture(params=["fast", "generic"])
+def kernel_path(request, monkeypatch):
+    """Run a test with the wave-FFT kernels (power-of-two lengths) and with the
+    runtime-schedule kernels forced by DGTNS_GENERIC=1."""
+    if request.param == "generic":
+        monkeypatch.setenv("DGTNS_GENERIC", "1")
+    else:
+        monkeypatch.delenv("DGTNS_GENERIC", raising=False)
+    return request.param
+
+
 def rel(x, y):
     x = np.asarray(x)
     y = np.asarray(y)
@@ -59,13 +70,19 @@ def run_forward(lat, dtype, B=2, g=None, seed=0):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_small_workload(dtype):
+def test_small_workload(dtype, kernel_path):
     lat = (SMALL.L, SMALL.a, SMALL.M, SMALL.lam1, SMALL.lam2)
     plan, f, g, c = run_forward(lat, dtype, B=1)
     assert c.shape == (1, 24, 12)
     ref = oracle.dgt_direct(f[0], g, *lat[1:])
     print("small workload", dtype, rel(c[0], ref))
     assert rel(c[0], ref) < TOL[dtype]
+
+
+POW2_LATTICES = [(2048, 16, 64, 1, 2), (4096, 32, 128, 1, 2), (4096, 8, 64, 1, 4), (8192, 32, 256, 1, 2),
+                 (16384, 64, 512, 3, 4), (32768, 64, 1024, 1, 2), (4096, 16, 32, 1, 2),
+                 (12288, 16, 64, 1, 3), (6144, 32, 64, 2, 3), (65536, 64, 256, 0, 1), (1024, 8, 32, 1, 2),
+                 (2048, 64, 64, 1, 2), (18432, 32, 256, 1, 2), (9216, 8, 64, 1, 2)]
 
 
 def sample_lattices(p1_only):
@@ -89,11 +106,18 @@ def sample_lattices(p1_only):
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_random_lattices_forward_and_adjoint(dtype):
+def test_random_lattices_forward_and_adjoint(dtype, kernel_path):
     lats = sample_lattices(False)
     seen = {"fs": 0, "ts": 0, "sep": 0, "p>1": 0}
     worst_f = worst_a = 0.0
-    for (lat, branch, p) in lats[:120]:
+    from paper_1307_4569_amd import _binding as Bb
+    extra = []
+    for lat in POW2_LATTICES:
+        h = Bb.dgtns_plan_create(*lat, 1, 2)
+        info = Bb.dgtns_plan_info(h)
+        Bb.dgtns_plan_destroy(h)
+        extra.append((lat, info.branch, info.p))
+    for (lat, branch, p) in extra + lats[:120]:
         L, a, M, l1, l2 = lat
         plan, f, g, c = run_forward(lat, dtype, B=2, g=complex_normal(L, 77))
         for k in range(2):
@@ -109,7 +133,7 @@ def test_random_lattices_forward_and_adjoint(dtype):
             assert e < TOL[dtype], ("adjoint", lat, branch, p, e)
         seen[["sep", "ts", "fs"][branch]] += 1
         seen["p>1"] += p > 1
-    print("random lattices", dtype, seen, "worst forward", worst_f, "worst adjoint", worst_a)
+    print("random lattices", kernel_path, dtype, seen, "worst forward", worst_f, "worst adjoint", worst_a)
     assert seen["fs"] >= 5 and seen["ts"] >= 20 and seen["p>1"] >= 5
 
 
@@ -188,12 +212,12 @@ def full_size(w, dtype, B, columns, real=False, window=None):
 
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
-def test_large_workload_sampled(dtype):
+def test_large_workload_sampled(dtype, kernel_path):
     w = LARGE
     B = w.batch if dtype == torch.complex64 else 8
     cols = list(range(0, w.N, 97)) + [w.N - 1]
     plan, f, c, errs = full_size(w, dtype, B, cols)
-    print("large workload", dtype, "B", B, "errors", errs)
+    print("large workload", kernel_path, dtype, "B", B, "errors", errs)
     assert max(errs) < TOL[dtype]
     # every signal: Parseval-type invariant ||c||^2 = <S f, f> is not cheap; check
     # adjointness <C f, c'> = <f, C* c'> on the whole batch instead
@@ -205,16 +229,16 @@ def test_large_workload_sampled(dtype):
     assert abs(lhs - rhs) <= (1e-4 if dtype == torch.complex64 else 1e-11) * abs(lhs)
 
 
-def test_precision_workload_real_signals():
+def test_precision_workload_real_signals(kernel_path):
     w = PRECISION
     cols = list(range(0, w.N, 331)) + [w.N - 1]
     for name, win in (("gaussian", None), ("hann", hann_window(w.L, 2048))):
         plan, f, c, errs = full_size(w, torch.complex64, w.batch, cols, real=True, window=win)
-        print("precision workload", name, errs)
+        print("precision workload", kernel_path, name, errs)
         assert max(errs) < 1e-5
 
 
-def test_gradient_workload_sampled():
+def test_gradient_workload_sampled(kernel_path):
     w = GRADIENT
     cols = list(range(0, w.N, 53))
     plan, f, c, errs = full_size(w, torch.complex64, w.batch, cols)
