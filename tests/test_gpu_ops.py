@@ -1,0 +1,218 @@
+"""GPU checks of the operations beside the forward transform: window
+gradient, canonical dual window (FP64) and the autograd function, against
+the FP64 oracle, finite differences and reconstruction."""
+import numpy as np
+import pytest
+
+import oracle
+from dgt_inputs import (GRADIENT, PRECISION, chirp_mixture, complex_normal, complex_normal_batch, gaussian_window,
+                        hann_window, round_to)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex64: 1e-5, torch.complex128: 1e-12}
+
+
+def rel(x, y):
+    x = np.asarray(x)
+    y = np.asarray(y)
+    return float(np.linalg.norm((x - y).ravel()) / np.linalg.norm(y.ravel()))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1307_4569_amd import _binding
+    _binding.lib()
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(params=["fast", "generic"])
+def kernel_path(request, monkeypatch):
+    if request.param == "generic":
+        monkeypatch.setenv("DGTNS_GENERIC", "1")
+    else:
+        monkeypatch.delenv("DGTNS_GENERIC", raising=False)
+    return request.param
+
+
+def plan_for(lat, dtype, B):
+    from paper_1307_4569_amd import Plan
+    return Plan(*lat, dtype=dtype, max_batch=B)
+
+
+# lattices with p = 1 of the sheared lattice, both shear branches
+GRAD_LATTICES = [(144, 6, 12, 1, 2), (16, 4, 8, 1, 2), (72, 6, 12, 1, 3), (2048, 16, 64, 1, 2),
+                 (4096, 32, 128, 1, 2), (18432, 32, 256, 1, 2), (1152, 8, 64, 2, 3), (576, 4, 32, 0, 1)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_window_gradient_matches_oracle(dtype, kernel_path):
+    single = dtype == torch.complex64
+    seen = set()
+    for lat in GRAD_LATTICES:
+        L, a, M, l1, l2 = lat
+        N = L // a
+        B = 3
+        plan = plan_for(lat, dtype, B)
+        seen.add(plan.branch)
+        g = round_to(complex_normal(L, 11), single)
+        f = round_to(np.stack([complex_normal(L, 20 + k) for k in range(B)]), single)
+        G = round_to(np.stack([complex_normal(N * M, 40 + k).reshape(N, M) for k in range(B)]), single)
+        plan.set_window(torch.tensor(g))
+        gg = plan.window_grad(torch.tensor(f), torch.tensor(G)).cpu().numpy()
+        ref = sum(oracle.window_gradient(f[k], G[k], a, M, l1, l2) for k in range(B))
+        e = rel(gg, ref)
+        print("window gradient", kernel_path, dtype, lat, e)
+        assert e < TOL[dtype] * 5, (lat, e)
+    assert {1, 2} <= seen
+
+
+@pytest.mark.parametrize("lat", [(144, 6, 12, 1, 2), (16, 4, 8, 1, 2), (2048, 16, 64, 1, 2), (4096, 32, 128, 1, 2),
+                                 (1152, 8, 64, 2, 3), (576, 4, 32, 0, 1), (240, 6, 12, 1, 2)])
+def test_dual_window_matches_oracle(lat):
+    L, a, M, l1, l2 = lat
+    plan = plan_for(lat, torch.complex64, 1)
+    g = gaussian_window(L, a, M)
+    gd, bounds = plan.dual(torch.tensor(g))
+    gd = gd.cpu().numpy()
+    A, Bb = bounds.cpu().numpy()
+    if L <= 2048:
+        ref = oracle.dual_window(g, a, M, l1, l2)
+        lo, hi = oracle.frame_bounds(g, a, M, l1, l2)
+        print("dual", lat, rel(gd, ref), (A, lo), (Bb, hi))
+        assert rel(gd, ref) < 1e-12
+        assert abs(A - lo) < 1e-10 * hi and abs(Bb - hi) < 1e-10 * hi
+    # S g_d = g at sampled points
+    pts = np.linspace(0, L - 1, 16).astype(np.int64)
+    sg = oracle.frame_operator_apply(gd, g, a, M, l1, l2, pts)
+    assert rel(sg, g[pts]) < 1e-11
+
+
+def test_precision_workload_dual_and_reconstruction():
+    """FP64 dual of the Gaussian and of the Hann window at L = 2^20, lambda =
+    1/4; S g_d = g at sampled points and perfect reconstruction of real chirp
+    signals through the FP64 forward and adjoint transforms."""
+    w = PRECISION
+    lat = (w.L, w.a, w.M, w.lam1, w.lam2)
+    plan = plan_for(lat, torch.complex128, 2)
+    pts = np.linspace(0, w.L - 1, 12).astype(np.int64)
+    for name, g in (("gaussian", gaussian_window(w.L, w.a, w.M)), ("hann", hann_window(w.L, 2048))):
+        gd, bounds = plan.dual(torch.tensor(g))
+        A, Bb = bounds.cpu().numpy()
+        sg = oracle.frame_operator_apply(gd.cpu().numpy(), g, w.a, w.M, w.lam1, w.lam2, pts)
+        e_s = rel(sg, g[pts])
+        x = np.stack([chirp_mixture(w.L, 13074569 + 3000 + k) for k in range(2)])
+        plan.set_window(torch.tensor(g))
+        c = plan.forward(torch.tensor(x))
+        plan.set_window(gd)
+        rec = plan.adjoint(c).cpu().numpy()
+        e_r = rel(rec, x)
+        print("precision dual", name, "bounds", A, Bb, "S gd err", e_s, "reconstruction err", e_r)
+        assert A > 0 and e_s < 1e-11 and e_r < 1e-12
+
+
+def test_autograd_gradcheck_fp64():
+    from paper_1307_4569_amd import DGTFunction
+    lat = (144, 6, 12, 1, 2)
+    plan = plan_for(lat, torch.complex128, 2)
+    rng = np.random.default_rng(5)
+    f = torch.tensor(rng.standard_normal((2, 144)) + 1j * rng.standard_normal((2, 144)), device="cuda",
+                     requires_grad=True)
+    g = torch.tensor(gaussian_window(144, 6, 12) + 0.1j * rng.standard_normal(144), device="cuda",
+                     requires_grad=True)
+    fn = lambda f_, g_: DGTFunction.apply(f_, g_, plan)
+    assert torch.autograd.gradcheck(fn, (f, g), eps=1e-6, atol=1e-8, rtol=1e-6, fast_mode=True)
+
+
+@pytest.mark.parametrize("lat", [(144, 6, 12, 1, 2), (4096, 32, 128, 1, 2)])
+def test_autograd_matches_oracle_gradients(lat):
+    from paper_1307_4569_amd import DGTFunction
+    L, a, M, l1, l2 = lat
+    plan = plan_for(lat, torch.complex128, 2)
+    f = np.stack([complex_normal(L, 60 + k) for k in range(2)])
+    g = gaussian_window(L, a, M)
+    T = np.stack([np.abs(oracle.dgt_fold(complex_normal(L, 90 + k), g, a, M, l1, l2)) ** 2 for k in range(2)])
+    ft = torch.tensor(f, device="cuda", requires_grad=True)
+    gt = torch.tensor(g, device="cuda", requires_grad=True)
+    c = DGTFunction.apply(ft, gt, plan)
+    loss = ((c.abs() ** 2 - torch.tensor(T, device="cuda")) ** 2).sum()
+    loss.backward()
+    gf_ref = []
+    gg_ref = np.zeros(L, complex)
+    l_ref = 0.0
+    for k in range(2):
+        lk, gf, gg = oracle.loss_and_grads(f[k], g, T[k], a, M, l1, l2)
+        l_ref += lk
+        gf_ref.append(gf)
+        gg_ref += gg
+    assert abs(loss.item() - l_ref) < 1e-12 * l_ref
+    assert rel(ft.grad.cpu().numpy(), np.stack(gf_ref)) < 1e-12
+    assert rel(gt.grad.cpu().numpy(), gg_ref) < 1e-12
+
+
+def test_gradient_workload():
+    """Differentiation workload: FP32 forward and hand-written backward at
+    L = 65536, a = 32, M = 256, lambda = 1/2, batch 32; gradients checked
+    against the oracle gradient on two signals and, in FP64, against central
+    finite differences (h = 1e-6) along seeded directions."""
+    from paper_1307_4569_amd import DGTFunction
+    w = GRADIENT
+    lat = (w.L, w.a, w.M, w.lam1, w.lam2)
+    g0 = gaussian_window(w.L, w.a, w.M)
+    fT = complex_normal(w.L, 4000)
+    f = complex_normal_batch(w.batch, w.L, 4)
+    # target spectrogram of a seeded signal through the initial window
+    plan32 = plan_for(lat, torch.complex64, w.batch)
+    plan32.set_window(torch.tensor(g0))
+    T = (plan32.forward(torch.tensor(fT.astype(np.complex64))).abs() ** 2).double()
+    ft = torch.tensor(f.astype(np.complex64), device="cuda", requires_grad=True)
+    gt = torch.tensor(g0.astype(np.complex64), device="cuda", requires_grad=True)
+    c = DGTFunction.apply(ft, gt, plan32)
+    loss = ((c.abs() ** 2 - T.float()) ** 2).sum()
+    loss.backward()
+    # oracle gradients of the first two signals (window gradient of that sub-batch)
+    Tn = T.cpu().numpy()
+    f32 = f.astype(np.complex64).astype(np.complex128)
+    g32 = g0.astype(np.complex64).astype(np.complex128)
+    gf_err = []
+    for k in (0, w.batch - 1):
+        _, gf, _ = oracle.loss_and_grads(f32[k], g32, Tn, w.a, w.M, w.lam1, w.lam2)
+        gf_err.append(rel(ft.grad[k].cpu().numpy(), gf))
+    print("gradient workload grad_f rel err vs oracle", gf_err)
+    assert max(gf_err) < 1e-4
+    sub = torch.tensor(f32[:2].astype(np.complex64), device="cuda", requires_grad=True)
+    gsub = torch.tensor(g0.astype(np.complex64), device="cuda", requires_grad=True)
+    plan2 = plan_for(lat, torch.complex64, 2)
+    csub = DGTFunction.apply(sub, gsub, plan2)
+    ((csub.abs() ** 2 - T.float()) ** 2).sum().backward()
+    gg_ref = sum(oracle.loss_and_grads(f32[k], g32, Tn, w.a, w.M, w.lam1, w.lam2)[2] for k in range(2))
+    e_gg = rel(gsub.grad.cpu().numpy(), gg_ref)
+    print("gradient workload grad_g rel err vs oracle", e_gg)
+    assert e_gg < 1e-4
+    # FP64 central differences on the full batch
+    plan64 = plan_for(lat, torch.complex128, w.batch)
+    f64 = torch.tensor(f, device="cuda", requires_grad=True)
+    g64 = torch.tensor(g0, device="cuda", requires_grad=True)
+
+    def loss_fn(ff, gg):
+        cc = DGTFunction.apply(ff, gg, plan64)
+        return ((cc.abs() ** 2 - T) ** 2).sum()
+
+    L0 = loss_fn(f64, g64)
+    L0.backward()
+    rng = np.random.default_rng(123)
+    h = 1e-6
+    for i in range(3):
+        df = torch.tensor(rng.standard_normal(f.shape) + 1j * rng.standard_normal(f.shape), device="cuda")
+        dg = torch.tensor(rng.standard_normal(w.L) + 1j * rng.standard_normal(w.L), device="cuda") * 1e-2
+        with torch.no_grad():
+            fd_f = (loss_fn(f64 + h * df, g64) - loss_fn(f64 - h * df, g64)).item() / (2 * h)
+            fd_g = (loss_fn(f64, g64 + h * dg) - loss_fn(f64, g64 - h * dg)).item() / (2 * h)
+        an_f = torch.vdot(f64.grad.flatten(), df.flatten()).real.item()
+        an_g = torch.vdot(g64.grad.flatten(), dg.flatten()).real.item()
+        print("finite differences", i, fd_f, an_f, fd_g, an_g)
+        assert abs(fd_f - an_f) < 1e-5 * abs(an_f)
+        assert abs(fd_g - an_g) < 1e-5 * abs(an_g)
