@@ -95,6 +95,73 @@ def cpu_baseline(w, f_host, g_host, c_gpu_fn, budget_s=12.0):
         (err_num / err_den) ** 0.5
 
 
+def serve_bench(nreq, torch, dev):
+    """Serving workload: a seeded stream of nreq requests over the 24 plans
+    (L in {36864, 73728, 147456, 294912}, (a, M) in {(32,256), (64,512)},
+    lambda in {1/2, 1/3, 2/3}), signals CN(0,1) pre-staged in HBM.  The FP32
+    continuous-batching server (4 streams, list batches of up to 8) and the
+    plain FP64 per-request server (1 stream, batch 1) are each measured closed
+    loop (capacity mu) and open loop with Poisson arrivals at 0.5, 0.8 and
+    0.95 mu."""
+    import numpy as np
+
+    from dgt_inputs import gaussian_window, poisson_arrivals, serving_plans, serving_requests, seed_for
+    from paper_1307_4569_amd.serve import GpuExecutor, Request, Server, latency_stats
+
+    plans = serving_plans()
+    spec = serving_requests(nreq)
+    # pre-stage signals: one seeded pool per signal length
+    by_len = {}
+    for j, (_, key, _) in enumerate(spec):
+        by_len.setdefault(key[0], []).append(j)
+    sig32 = [None] * nreq
+    for L, idx in sorted(by_len.items()):
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed_for(5, L))
+        pool = torch.randn((len(idx), L), dtype=torch.complex64, generator=gen, device=dev)
+        for t, j in enumerate(idx):
+            sig32[j] = pool[t]
+    coeffs = lambda r: (r.key[0] // r.key[1]) * r.key[2]
+    out = {"workload": f"serving mix: {nreq} requests over 24 plans (6 with a frequency shear)",
+           "total_coeffs": int(sum((k[0] // k[1]) * k[2] for _, k, _ in spec))}
+
+    def run_server(name, dtype, streams, max_batch, inflight, sigs):
+        ex = GpuExecutor(lambda k: torch.tensor(gaussian_window(k[0], k[1], k[2])), dtype=dtype, streams=streams,
+                         max_batch=max_batch, device=dev)
+        ex.prepare(plans)
+        mk = lambda: [Request(j, key, sigs[j], 0.0) for j, (_, key, _) in enumerate(spec)]
+        srv = Server(ex, hbm_budget=16 << 30, max_inflight_per_slot=inflight, keep_outputs=False)
+        srv.run(mk()[: min(500, nreq)])
+        torch.cuda.synchronize()
+        srv = Server(ex, hbm_budget=16 << 30, max_inflight_per_slot=inflight, keep_outputs=False)
+        cap = latency_stats(srv.run(mk()), coeffs)
+        res = {"capacity": cap}
+        mu = cap["req_per_s"]
+        for frac in (0.5, 0.8, 0.95):
+            arr = list(poisson_arrivals(nreq, frac * mu, seed_for(5, int(frac * 100))))
+            srv = Server(ex, hbm_budget=16 << 30, max_inflight_per_slot=inflight, keep_outputs=False)
+            st = latency_stats(srv.run(mk(), arr), coeffs)
+            st["offered_req_per_s"] = frac * mu
+            res[f"load_{frac}"] = st
+        del ex
+        torch.cuda.synchronize()
+        log(f"serve {name}: capacity {mu:.0f} req/s, p50/p99 at 0.8 mu: "
+            f"{res['load_0.8']['p50_ms']:.3f}/{res['load_0.8']['p99_ms']:.3f} ms")
+        return res
+
+    out["fp32_batched"] = run_server("fp32", torch.complex64, 4, 8, 2, sig32)
+    sig64 = [x.to(torch.complex128) for x in sig32]
+    del sig32
+    out["fp64_per_request"] = run_server("fp64", torch.complex128, 1, 1, 4, sig64)
+    a, b = out["fp32_batched"]["load_0.8"], out["fp64_per_request"]["load_0.8"]
+    out["headline"] = {"p50_ms": a["p50_ms"], "p99_ms": a["p99_ms"], "coeffs_per_s": a["coeffs_per_s"],
+                       "load": "0.8 of measured capacity",
+                       "fp64_baseline_p50_ms": b["p50_ms"], "fp64_baseline_p99_ms": b["p99_ms"],
+                       "capacity_speedup_vs_fp64": out["fp32_batched"]["capacity"]["coeffs_per_s"]
+                       / out["fp64_per_request"]["capacity"]["coeffs_per_s"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +169,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the FP32 forward loop (for rocprofv3)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -226,6 +295,11 @@ def main():
         cb, err = cpu_baseline(w, f_host, g32, gpu_signal)
         out["cpu_baseline"] = cb
         out["rel_err_fp32_vs_oracle"] = err
+    if not args.no_serve:
+        log("serving workload")
+        del c
+        torch.cuda.empty_cache()
+        out["serve"] = serve_bench(args.serve_requests, torch, dev)
     print(json.dumps(out))
 
 

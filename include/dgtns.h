@@ -145,6 +145,17 @@ int dgtns_forward(dgtns_plan plan, const void* f_dev, int real_input, void* c_de
                   void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Forward transform of B signals that live in separate buffers (batching of
+ * independent requests without staging copies): f_list and c_list are HOST
+ * arrays of B device pointers, signal k read from f_list[k] (length L) and
+ * its coefficients written to c_list[k] (N x M).  B <= DGTNS_MAX_LIST_BATCH.
+ * Otherwise as dgtns_forward (same workspace size for the same B).
+ */
+#define DGTNS_MAX_LIST_BATCH 16
+int dgtns_forward_batch(dgtns_plan plan, const void* const* f_list, int real_input, void* const* c_list, int64_t B,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Adjoint (synthesis) transform, the adjoint of eq. (DGT):
  * f_dev[B][L](l) = sum_{m,n} c(m, n) g(l - n a) exp(2 pi i l (m + w(n)) / M).
  * Computed as the adjoint of every stage of Alg. 1 in reverse order.

@@ -65,6 +65,8 @@ SIGNATURES = [
     ("dgtns_workspace_bytes", ctypes.c_int, [c_vp, ctypes.c_int, c_i64, ctypes.POINTER(ctypes.c_size_t)]),
     ("dgtns_set_window", ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_forward", ctypes.c_int, [c_vp, c_vp, ctypes.c_int, c_vp, c_i64, c_vp, ctypes.c_size_t, c_vp]),
+    ("dgtns_forward_batch", ctypes.c_int, [c_vp, ctypes.POINTER(c_vp), ctypes.c_int, ctypes.POINTER(c_vp), c_i64,
+                                           c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_adjoint", ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_window_grad", ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_dual_window", ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
@@ -133,6 +135,16 @@ def dgtns_set_window(plan, g_ptr, ws_ptr, ws_bytes, stream):
 
 def dgtns_forward(plan, f_ptr, real_input, c_ptr, B, ws_ptr, ws_bytes, stream):
     _call("dgtns_forward", plan, f_ptr, int(real_input), c_ptr, B, ws_ptr, ws_bytes, stream)
+
+
+DGTNS_MAX_LIST_BATCH = 16
+
+
+def dgtns_forward_batch(plan, f_ptrs, real_input, c_ptrs, ws_ptr, ws_bytes, stream):
+    B = len(f_ptrs)
+    fa = (c_vp * B)(*f_ptrs)
+    ca = (c_vp * B)(*c_ptrs)
+    _call("dgtns_forward_batch", plan, fa, int(real_input), ca, B, ws_ptr, ws_bytes, stream)
 
 
 def dgtns_adjoint(plan, c_ptr, f_ptr, B, ws_ptr, ws_bytes, stream):

@@ -183,6 +183,22 @@ int dgtns_forward(dgtns_plan plan, const void* f_dev, int real_input, void* c_de
   return forward_c128(P, f_dev, real_input ? 1 : 0, c_dev, B, w, l, st);
 }
 
+int dgtns_forward_batch(dgtns_plan plan, const void* const* f_list, int real_input, void* const* c_list, int64_t B,
+                        void* ws, size_t ws_bytes, void* stream) {
+  Layout l;
+  int rc = check_call(plan, B, ws, ws_bytes, DGTNS_OP_FORWARD, &l);
+  if (rc) return rc;
+  if (!f_list || !c_list) return fail(DGTNS_EINVAL, "null pointer list");
+  if (B > DGTNS_MAX_LIST_BATCH) return fail(DGTNS_EINVAL, "list batch above DGTNS_MAX_LIST_BATCH");
+  for (int64_t k = 0; k < B; ++k)
+    if (!f_list[k] || !c_list[k]) return fail(DGTNS_EINVAL, "null signal or coefficient pointer in list");
+  const Plan& P = plan->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  if (P.dtype == 0) return forward_list_c64(P, f_list, real_input ? 1 : 0, c_list, B, w, l, st);
+  return forward_list_c128(P, f_list, real_input ? 1 : 0, c_list, B, w, l, st);
+}
+
 int dgtns_adjoint(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, void* ws, size_t ws_bytes,
                   void* stream) {
   Layout l;

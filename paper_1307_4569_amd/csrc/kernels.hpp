@@ -22,6 +22,10 @@
 
 namespace dgtns {
 
+// Largest batch of the list-batched forward call (per-signal pointers in the
+// kernel arguments).
+constexpr int kListMax = 16;
+
 template <typename C> struct ChirpSrc {
   const C* tab;   // pchirp values per sample (plan precision), or null
   long long K;    // s (L+1) mod 2L for exact on-the-fly FP64 evaluation when tab is null
@@ -87,6 +91,8 @@ template <typename C> struct ColArgs {
   const void* x;
   long long xs;
   int real_in;
+  int list;                    // 1: signal k at xl[k] instead of x + k xs
+  const void* xl[kListMax];
   ChirpSrc<C> chirp;
   const C* zc;
   C* H;
@@ -112,7 +118,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
     C v = czero<C>();
     if (r < Mi) {
       const long long l = r + (long long)j * Mi;
-      v = apply_chirp(A.chirp, load_sig<C>(A.x, A.real_in, bo * A.xs + l), l);
+      v = apply_chirp(A.chirp, load_sig<C>(A.list ? A.xl[bo] : A.x, A.real_in, (A.list ? 0 : bo * A.xs) + l), l);
     }
     const int j0 = GENP ? j % p : 0, t = GENP ? j / p : j;
     xb[(cc * p + j0) * Sd + t] = v;
@@ -295,6 +301,8 @@ template <typename C> struct RowArgs {
   const C* twm;
   const C* postE;
   const int* rho;
+  int list;                    // forward: coefficients of signal k at cl[k] instead of c + k cs
+  C* cl[kListMax];
   int Mi, Ni, R, Sm, q, d;
   FftSched fm;
   long long N, L, b, M, K1, K2, K3, K4, K5, C1n, C2n, Kt1, Kt6;
@@ -332,7 +340,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows(RowArgs<C> A) {
   }
   __syncthreads();
   fft_lds<C, false>(buf, Sm, A.fm, R, tw);
-  C* cb = A.c + bo * A.cs;
+  C* cb = A.list ? A.cl[bo] : A.c + bo * A.cs;
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
     const int row = e / Mi, mo = e - row * Mi;
     if (t0 + row >= d) continue;
@@ -400,6 +408,8 @@ template <typename C> struct ColFftArgs {
   const void* x;
   long long xs;
   int real_in;
+  int list;
+  const void* xl[kListMax];
   C* y;
   long long ys;
   ChirpSrc<C> pre;
@@ -424,7 +434,7 @@ __global__ void __launch_bounds__(kThreads) k_col_fft(ColFftArgs<C> A) {
     C v = czero<C>();
     if (col < nc) {
       const long long idx = (long long)j * nc + col;
-      v = apply_chirp(A.pre, load_sig<C>(A.x, A.real_in, bo * A.xs + idx), idx);
+      v = apply_chirp(A.pre, load_sig<C>(A.list ? A.xl[bo] : A.x, A.real_in, (A.list ? 0 : bo * A.xs) + idx), idx);
     }
     buf[cc * Sn + j] = v;
   }

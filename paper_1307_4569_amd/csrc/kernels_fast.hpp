@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
     C v = czero<C>();
     if (r < Mi) {
       const long long li = r + (long long)t * Mi;
-      v = apply_chirp(A.chirp, load_sig<C>(A.x, A.real_in, bo * A.xs + li), li);
+      v = apply_chirp(A.chirp, load_sig<C>(A.list ? A.xl[bo] : A.x, A.real_in, (A.list ? 0 : bo * A.xs) + li), li);
     }
     lds[cc * SD + t] = v;
   }
@@ -202,7 +202,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   }
   __syncthreads();
   C* ex = lds + wave * F::EXW + tt * I::EX;
-  C* cb = A.c + bo * A.cs;
+  C* cb = A.list ? A.cl[bo] : A.c + bo * A.cs;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     wave_fft<C, MI, false>(v[k], ex, l, tw);

@@ -191,9 +191,14 @@ int run_rows_fast(const Plan& P, const RowArgs<C>& A, long long B, bool adjoint,
 
 template <typename C>
 int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C> ch, C* H, long long B,
-             hipStream_t st) {
+             hipStream_t st, const void* const* xlist = nullptr) {
   ColArgs<C> A;
+  std::memset(&A, 0, sizeof(A));
   A.x = x; A.xs = xs; A.real_in = real_in; A.chirp = ch;
+  if (xlist) {
+    A.list = 1;
+    for (long long k = 0; k < B; ++k) A.xl[k] = xlist[k];
+  }
   A.zc = tab<C>(P, P.off.zc);
   A.H = H; A.hs = (long long)P.Mi * P.Ni;
   A.twd = tab<C>(P, P.off.tw_d);
@@ -223,6 +228,7 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
 template <typename C>
 int run_adj_cols(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, hipStream_t st) {
   ColAdjArgs<C> A;
+  std::memset(&A, 0, sizeof(A));
   A.H = H; A.hs = (long long)P.Mi * P.Ni;
   A.zc = tab<C>(P, P.off.zc);
   A.twd = tab<C>(P, P.off.tw_d);
@@ -272,8 +278,13 @@ RowArgs<C> row_args(const Plan& P, const C* H, C* c) {
 }
 
 template <typename C>
-int run_rows(const Plan& P, const C* H, C* c, long long B, bool adjoint, hipStream_t st) {
+int run_rows(const Plan& P, const C* H, C* c, long long B, bool adjoint, hipStream_t st,
+             void* const* clist = nullptr) {
   RowArgs<C> A = row_args<C>(P, H, c);
+  if (clist) {
+    A.list = 1;
+    for (long long k = 0; k < B; ++k) A.cl[k] = static_cast<C*>(clist[k]);
+  }
   if (!P.generic) {
     switch (P.Mi) {
       case 32: return run_rows_fast<C, 32>(P, A, B, adjoint, st);
@@ -302,10 +313,15 @@ int run_rows(const Plan& P, const C* H, C* c, long long B, bool adjoint, hipStre
 template <typename C>
 int run_four_step(const Plan& P, const void* x, int real_in, C* tmp, C* y, long long B, bool inv,
                   ChirpSrc<C> pre, ChirpSrc<C> post, decltype(C::x) scale, const C* twL,
-                  const C* tw1, const C* tw2, hipStream_t st) {
+                  const C* tw1, const C* tw2, hipStream_t st, const void* const* xlist = nullptr) {
   const long long n1 = inv ? P.L2 : P.L1, n2 = inv ? P.L1 : P.L2;
   const FftSched s1 = sched(inv ? P.f2 : P.f1), s2 = sched(inv ? P.f1 : P.f2);
   ColFftArgs<C> A;
+  std::memset(&A, 0, sizeof(A));
+  if (xlist) {
+    A.list = 1;
+    for (long long k = 0; k < B; ++k) A.xl[k] = xlist[k];
+  }
   A.x = x; A.xs = P.L; A.real_in = real_in; A.y = tmp; A.ys = P.L; A.pre = pre;
   A.twL = twL; A.L = P.L; A.tws = inv ? tw2 : tw1;
   A.n = int(n1); A.ncols = int(n2); A.Sn = int(n1 | 1); A.W = block_width(A.Sn, sizeof(C)); A.fs = s1;
@@ -315,6 +331,7 @@ int run_four_step(const Plan& P, const void* x, int real_in, C* tmp, C* y, long 
                : launch(k_col_fft<C, false>, g1, lds, st, A, "length-L transform, column pass");
   if (rc) return rc;
   RowFftArgs<C> R;
+  std::memset(&R, 0, sizeof(R));
   R.x = tmp; R.xs = P.L; R.y = y; R.ys = P.L; R.post = post; R.scale = scale;
   R.tws = inv ? tw1 : tw2;
   R.n = int(n2); R.nrows = int(n1); R.Sn = int(n2 | 1); R.R = block_width(R.Sn, sizeof(C)); R.fs = s2;
@@ -342,22 +359,22 @@ inline ChirpSrc<double2> chirp_fly(const Plan& P, long long s, int conj) {
 
 template <typename C>
 int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, char* ws, const Layout& l,
-                 hipStream_t st) {
+                 hipStream_t st, const void* const* flist = nullptr, void* const* clist = nullptr) {
   C* H = reinterpret_cast<C*>(ws + l.H);
   int rc;
   if (P.branch != kFreqShear) {
-    rc = run_cols<C>(P, f, P.L, real_in, chirp_tab<C>(P, P.off.chirp1, 0), H, B, st);
+    rc = run_cols<C>(P, f, P.L, real_in, chirp_tab<C>(P, P.off.chirp1, 0), H, B, st, flist);
   } else {
     C* F = reinterpret_cast<C*>(ws + l.F);
     C* Y = reinterpret_cast<C*>(ws + l.Y);
     rc = run_four_step<C>(P, f, real_in, Y, F, B, false, chirp_tab<C>(P, P.off.chirp1, 0),
                           chirp_tab<C>(P, P.off.chirp0, 0), 1, tab<C>(P, P.off.tw_L), tab<C>(P, P.off.tw_1),
-                          tab<C>(P, P.off.tw_2), st);
+                          tab<C>(P, P.off.tw_2), st, flist);
     if (rc) return rc;
     rc = run_cols<C>(P, F, P.L, 0, no_chirp<C>(P), H, B, st);
   }
   if (rc) return rc;
-  return run_rows<C>(P, H, c, B, false, st);
+  return run_rows<C>(P, H, c, B, false, st, clist);
 }
 
 template <typename C>
@@ -508,6 +525,10 @@ int forward_c64(const Plan& P, const void* f, int real_in, void* c, long long B,
                 hipStream_t st);
 int forward_c128(const Plan& P, const void* f, int real_in, void* c, long long B, char* ws, const Layout& l,
                  hipStream_t st);
+int forward_list_c64(const Plan& P, const void* const* f, int real_in, void* const* c, long long B, char* ws,
+                     const Layout& l, hipStream_t st);
+int forward_list_c128(const Plan& P, const void* const* f, int real_in, void* const* c, long long B, char* ws,
+                      const Layout& l, hipStream_t st);
 int adjoint_c64(const Plan& P, const void* c, void* f, long long B, char* ws, const Layout& l, hipStream_t st);
 int adjoint_c128(const Plan& P, const void* c, void* f, long long B, char* ws, const Layout& l, hipStream_t st);
 int grad_c64(const Plan& P, const void* f, const void* gc, void* gg, long long B, char* ws, const Layout& l,

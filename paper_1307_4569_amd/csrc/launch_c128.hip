@@ -9,6 +9,11 @@ int forward_c128(const Plan& P, const void* f, int real_in, void* c, long long B
   return forward_impl<double2>(P, f, real_in, static_cast<double2*>(c), B, ws, l, st);
 }
 
+int forward_list_c128(const Plan& P, const void* const* f, int real_in, void* const* c, long long B, char* ws,
+                      const Layout& l, hipStream_t st) {
+  return forward_impl<double2>(P, nullptr, real_in, nullptr, B, ws, l, st, f, c);
+}
+
 int adjoint_c128(const Plan& P, const void* c, void* f, long long B, char* ws, const Layout& l, hipStream_t st) {
   return adjoint_impl<double2>(P, static_cast<const double2*>(c), static_cast<double2*>(f), B, ws, l, st);
 }
