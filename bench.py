@@ -258,6 +258,21 @@ def main():
                        "frac_of_compulsory_bound": round(9.0 * value / 1e9 / HBM_PEAK_GBS, 4)},
     }
 
+    # practical HBM ceiling: a plain device copy of the same size as the
+    # coefficient array (read + write)
+    cc = torch.empty_like(c)
+    for _ in range(3):
+        cc.copy_(c)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cc.copy_(c)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_GBps"] = round(2 * c.numel() * 8 / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9, 1)
+    del cc
+
     # adjoint (synthesis) on the same batch, FP32
     log("fp32 adjoint timing")
     fa = torch.empty_like(f32)

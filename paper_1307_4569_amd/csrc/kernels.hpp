@@ -26,6 +26,16 @@ namespace dgtns {
 // kernel arguments).
 constexpr int kListMax = 16;
 
+// a[i] for a work-group-uniform i, with constant indices only (a dynamic
+// index into a by-value kernel argument would move the whole argument block
+// to scratch memory)
+template <typename T, int N> __device__ __forceinline__ T pick(const T (&a)[N], int i) {
+  T r = a[0];
+#pragma unroll
+  for (int k = 1; k < N; ++k) r = i == k ? a[k] : r;
+  return r;
+}
+
 template <typename C> struct ChirpSrc {
   const C* tab;   // pchirp values per sample (plan precision), or null
   long long K;    // s (L+1) mod 2L for exact on-the-fly FP64 evaluation when tab is null
@@ -112,13 +122,15 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
   for (int e = threadIdx.x; e < d; e += kThreads) tw[e] = A.twd[e];
   const int r0 = blockIdx.x * W;
   const long long bo = blockIdx.y;
+  const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
+  const long long xoff = A.list ? 0 : bo * A.xs;
   const int b = p * d;
   for (int e = threadIdx.x; e < W * b; e += kThreads) {
     const int j = e / W, cc = e - j * W, r = r0 + cc;
     C v = czero<C>();
     if (r < Mi) {
       const long long l = r + (long long)j * Mi;
-      v = apply_chirp(A.chirp, load_sig<C>(A.list ? A.xl[bo] : A.x, A.real_in, (A.list ? 0 : bo * A.xs) + l), l);
+      v = apply_chirp(A.chirp, load_sig<C>(xsrc, A.real_in, xoff + l), l);
     }
     const int j0 = GENP ? j % p : 0, t = GENP ? j / p : j;
     xb[(cc * p + j0) * Sd + t] = v;
@@ -340,7 +352,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows(RowArgs<C> A) {
   }
   __syncthreads();
   fft_lds<C, false>(buf, Sm, A.fm, R, tw);
-  C* cb = A.list ? A.cl[bo] : A.c + bo * A.cs;
+  C* cb = A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs;
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
     const int row = e / Mi, mo = e - row * Mi;
     if (t0 + row >= d) continue;
@@ -429,12 +441,14 @@ __global__ void __launch_bounds__(kThreads) k_col_fft(ColFftArgs<C> A) {
   for (int e = threadIdx.x; e < n; e += kThreads) tw[e] = A.tws[e];
   const int c0 = blockIdx.x * W;
   const long long bo = blockIdx.y;
+  const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
+  const long long xoff = A.list ? 0 : bo * A.xs;
   for (int e = threadIdx.x; e < W * n; e += kThreads) {
     const int j = e / W, cc = e - j * W, col = c0 + cc;
     C v = czero<C>();
     if (col < nc) {
       const long long idx = (long long)j * nc + col;
-      v = apply_chirp(A.pre, load_sig<C>(A.list ? A.xl[bo] : A.x, A.real_in, (A.list ? 0 : bo * A.xs) + idx), idx);
+      v = apply_chirp(A.pre, load_sig<C>(xsrc, A.real_in, xoff + idx), idx);
     }
     buf[cc * Sn + j] = v;
   }

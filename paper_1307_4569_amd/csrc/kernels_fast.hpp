@@ -55,13 +55,15 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
   const int Mi = A.Mi;
   const int r0 = blockIdx.x * W;
   const long long bo = blockIdx.y;
+  const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
+  const long long xoff = A.list ? 0 : bo * A.xs;
   // 1. coalesced load of W adjacent columns (d values each), chirp applied
   for (int e = tid; e < W * D; e += kThreads) {
     const int t = e / W, cc = e - t * W, r = r0 + cc;
     C v = czero<C>();
     if (r < Mi) {
       const long long li = r + (long long)t * Mi;
-      v = apply_chirp(A.chirp, load_sig<C>(A.list ? A.xl[bo] : A.x, A.real_in, (A.list ? 0 : bo * A.xs) + li), li);
+      v = apply_chirp(A.chirp, load_sig<C>(xsrc, A.real_in, xoff + li), li);
     }
     lds[cc * SD + t] = v;
   }
@@ -202,7 +204,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   }
   __syncthreads();
   C* ex = lds + wave * F::EXW + tt * I::EX;
-  C* cb = A.list ? A.cl[bo] : A.c + bo * A.cs;
+  C* cb = A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     wave_fft<C, MI, false>(v[k], ex, l, tw);

@@ -205,7 +205,8 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.p = int(P.pi); A.q = int(P.qi);
   A.W = P.W; A.Sd = int(P.di | 1); A.fd = sched(P.fd);
   const size_t es = sizeof(C);
-  if (P.pi == 1 && !P.generic) {
+  // wave kernels up to d = 1024 (FP32) or 512 (FP64; d = 1024 would spill registers)
+  if (P.pi == 1 && !P.generic && P.di * long(sizeof(C)) <= 8192) {
     switch (P.di) {
       case 32: return run_cols_fast<C, 32>(P, A, B, st);
       case 64: return run_cols_fast<C, 64>(P, A, B, st);
@@ -236,14 +237,14 @@ int run_adj_cols(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, h
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.p = int(P.pi); A.q = int(P.qi);
   A.W = P.W; A.Sd = int(P.di | 1); A.fd = sched(P.fd);
   const size_t es = sizeof(C);
-  if (P.pi == 1 && !P.generic) {
+  // adjoint wave kernels up to d = 512 (larger d would spill registers)
+  if (P.pi == 1 && !P.generic && P.di <= 512) {
     switch (P.di) {
       case 32: return run_adj_cols_fast<C, 32>(P, A, B, st);
       case 64: return run_adj_cols_fast<C, 64>(P, A, B, st);
       case 128: return run_adj_cols_fast<C, 128>(P, A, B, st);
       case 256: return run_adj_cols_fast<C, 256>(P, A, B, st);
       case 512: return run_adj_cols_fast<C, 512>(P, A, B, st);
-      case 1024: return run_adj_cols_fast<C, 1024>(P, A, B, st);
       default: break;
     }
   }
