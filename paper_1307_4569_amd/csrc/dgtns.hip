@@ -31,6 +31,50 @@ Timing& timing() {
   return t;
 }
 
+namespace {
+struct Helpers {
+  std::mutex mu;
+  std::map<int, hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+};
+Helpers& helpers() {
+  static Helpers h;
+  return h;
+}
+}  // namespace
+
+hipStream_t helper_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  Helpers& h = helpers();
+  std::lock_guard<std::mutex> g(h.mu);
+  auto it = h.streams.find(dev);
+  if (it != h.streams.end()) return it->second;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  h.streams[dev] = s;
+  return s;
+}
+
+hipEvent_t take_sync_event() {
+  Helpers& h = helpers();
+  std::lock_guard<std::mutex> g(h.mu);
+  if (!h.events.empty()) {
+    hipEvent_t e = h.events.back();
+    h.events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  return e;
+}
+
+void give_sync_event(hipEvent_t e) {
+  Helpers& h = helpers();
+  std::lock_guard<std::mutex> g(h.mu);
+  h.events.push_back(e);
+}
+
 }  // namespace host
 }  // namespace dgtns
 

@@ -33,6 +33,52 @@ inline int check_hip(hipError_t e, const char* what) {
 
 inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// ---------------------------------------------------------------------------
+// Two-stream pipeline over chunks of the batch (time-shear branch): stage 1
+// of chunk k runs on the caller's stream into h buffer k mod 2, stage 2 of
+// chunk k on a helper stream of the device as soon as stage 1 is done, so
+// stage 1 of chunk k+1 overlaps stage 2 of chunk k and each h buffer is read
+// back while it is still in the last-level cache.  The caller's stream waits
+// for the last stage 2 before the call returns.
+// ---------------------------------------------------------------------------
+hipStream_t helper_stream();          // per device, created once (default priority)
+hipEvent_t take_sync_event();
+void give_sync_event(hipEvent_t e);
+
+inline bool pipelined(const Plan& P, long long B) { return P.chunk > 0 && B >= 2 * P.chunk; }
+
+template <typename S1, typename S2>
+int run_pipeline(long long B, long long chunk, hipStream_t st, S1 stage1, S2 stage2) {
+  hipStream_t hs = helper_stream();
+  if (!hs) return fail(DGTNS_EDEVICE, "could not create the helper stream");
+  hipEvent_t eA[2] = {take_sync_event(), take_sync_event()};
+  hipEvent_t eB[2] = {take_sync_event(), take_sync_event()};
+  int rc = DGTNS_OK;
+  long long last = -1;
+  const long long nch = (B + chunk - 1) / chunk;
+  for (long long k = 0; k < nch && rc == DGTNS_OK; ++k) {
+    const long long b0 = k * chunk, nb = B - b0 < chunk ? B - b0 : chunk;
+    const int buf = int(k & 1);
+    if (k >= 2) rc = check_hip(hipStreamWaitEvent(st, eB[buf], 0), "pipeline wait");
+    if (!rc) rc = stage1(b0, nb, buf, st);
+    if (!rc) rc = check_hip(hipEventRecord(eA[buf], st), "pipeline record");
+    if (!rc) rc = check_hip(hipStreamWaitEvent(hs, eA[buf], 0), "pipeline wait");
+    if (!rc) rc = stage2(b0, nb, buf, hs);
+    if (!rc) rc = check_hip(hipEventRecord(eB[buf], hs), "pipeline record");
+    if (!rc) last = k;
+  }
+  if (last >= 0) {
+    int rc2 = check_hip(hipStreamWaitEvent(st, eB[last & 1], 0), "pipeline wait");
+    if (!rc) rc = rc2;
+  }
+  for (int i = 0; i < 2; ++i) {
+    give_sync_event(eA[i]);
+    give_sync_event(eB[i]);
+  }
+  return rc;
+}
+
+
 
 // Optional per-kernel timing: every launch bracketed by two HIP events on
 // the launch stream; dgtns_timing_collect() waits for them and aggregates.
@@ -131,8 +177,13 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
   switch (op) {
     case DGTNS_OP_FORWARD:
     case DGTNS_OP_ADJOINT:
-      l.H = take(es * MN * B);
-      if (fs) { l.F = take(es * L * B); l.Y = take(es * L * B); }
+      if (pipelined(P, B)) {
+        l.H = take(es * MN * P.chunk);
+        l.F = take(es * MN * P.chunk);   // second h buffer
+      } else {
+        l.H = take(es * MN * B);
+        if (fs) { l.F = take(es * L * B); l.Y = take(es * L * B); }
+      }
       break;
     case DGTNS_OP_WINDOW_GRAD:
       l.H = take(es * MN * B);
@@ -363,6 +414,20 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
                  hipStream_t st, const void* const* flist = nullptr, void* const* clist = nullptr) {
   C* H = reinterpret_cast<C*>(ws + l.H);
   int rc;
+  if (!flist && pipelined(P, B)) {
+    C* Hb[2] = {H, reinterpret_cast<C*>(ws + l.F)};
+    const size_t sig_bytes = size_t(P.L) * (real_in ? sizeof(C) / 2 : sizeof(C));
+    const long long MN = P.M * P.N;
+    return run_pipeline(
+        B, P.chunk, st,
+        [&](long long b0, long long nb, int buf, hipStream_t s) {
+          return run_cols<C>(P, static_cast<const char*>(f) + b0 * sig_bytes, P.L, real_in,
+                             chirp_tab<C>(P, P.off.chirp1, 0), Hb[buf], nb, s);
+        },
+        [&](long long b0, long long nb, int buf, hipStream_t s) {
+          return run_rows<C>(P, Hb[buf], c + b0 * MN, nb, false, s);
+        });
+  }
   if (P.branch != kFreqShear) {
     rc = run_cols<C>(P, f, P.L, real_in, chirp_tab<C>(P, P.off.chirp1, 0), H, B, st, flist);
   } else {
@@ -381,6 +446,18 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
 template <typename C>
 int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const Layout& l, hipStream_t st) {
   C* H = reinterpret_cast<C*>(ws + l.H);
+  if (pipelined(P, B)) {
+    C* Hb[2] = {H, reinterpret_cast<C*>(ws + l.F)};
+    const long long MN = P.M * P.N;
+    return run_pipeline(
+        B, P.chunk, st,
+        [&](long long b0, long long nb, int buf, hipStream_t s) {
+          return run_rows<C>(P, Hb[buf], const_cast<C*>(c) + b0 * MN, nb, true, s);
+        },
+        [&](long long b0, long long nb, int buf, hipStream_t s) {
+          return run_adj_cols<C>(P, Hb[buf], chirp_tab<C>(P, P.off.chirp1, 1), f + b0 * P.L, nb, s);
+        });
+  }
   int rc = run_rows<C>(P, H, const_cast<C*>(c), B, true, st);
   if (rc) return rc;
   if (P.branch != kFreqShear) return run_adj_cols<C>(P, H, chirp_tab<C>(P, P.off.chirp1, 1), f, B, st);

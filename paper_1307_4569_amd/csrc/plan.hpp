@@ -84,6 +84,10 @@ struct Plan {
   void* dev = nullptr;       // bound persistent memory
   bool window_set = false;
   bool generic = false;   // force the runtime-schedule kernels (DGTNS_GENERIC=1)
+  // Signals per chunk of the two-stream pipeline of the time-shear branch:
+  // the two h buffers of a chunk pair stay within the last-level (Infinity)
+  // cache.  0 disables the pipeline (DGTNS_NO_PIPELINE=1).
+  int64_t chunk = 0;
 };
 
 // Returns 0 on success, else an error status with a message in *err.
