@@ -265,10 +265,10 @@ def test_pipelined_batches_match_single_launch(dtype, monkeypatch):
         c = plan.forward(f)
         fa = plan.adjoint(c)
         torch.cuda.synchronize()
-        out[mode] = (c, fa, plan.info)
-    from paper_1307_4569_amd import _binding as Bm
-    assert Bm.dgtns_workspace_bytes(make_plan(w.L, w.a, w.M, w.lam1, w.lam2, dtype, B)._h, 0, B) \
-        < B * w.N * w.M * (8 if dtype == torch.complex64 else 16)
+        from paper_1307_4569_amd import _binding as Bm
+        out[mode] = (c, fa, Bm.dgtns_workspace_bytes(plan._h, Bm.DGTNS_OP_FORWARD, B))
+    # the pipeline needs two chunks of the intermediate instead of the whole batch
+    assert out["pipeline"][2] < out["single"][2]
     assert torch.equal(out["pipeline"][0], out["single"][0])
     assert torch.equal(out["pipeline"][1], out["single"][1])
     ref = oracle.dgt_fold(f[B - 1].cpu().numpy().astype(np.complex128),
