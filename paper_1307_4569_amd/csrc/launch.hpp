@@ -414,17 +414,23 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
                  hipStream_t st, const void* const* flist = nullptr, void* const* clist = nullptr) {
   C* H = reinterpret_cast<C*>(ws + l.H);
   int rc;
-  if (!flist && pipelined(P, B)) {
+  // the workspace layout of this batch size decides the path (ws_layout):
+  // pipelined batches only have room for two chunks of h
+  if (pipelined(P, B)) {
     C* Hb[2] = {H, reinterpret_cast<C*>(ws + l.F)};
     const size_t sig_bytes = size_t(P.L) * (real_in ? sizeof(C) / 2 : sizeof(C));
     const long long MN = P.M * P.N;
     return run_pipeline(
         B, P.chunk, st,
         [&](long long b0, long long nb, int buf, hipStream_t s) {
+          if (flist)
+            return run_cols<C>(P, nullptr, P.L, real_in, chirp_tab<C>(P, P.off.chirp1, 0), Hb[buf], nb, s,
+                               flist + b0);
           return run_cols<C>(P, static_cast<const char*>(f) + b0 * sig_bytes, P.L, real_in,
                              chirp_tab<C>(P, P.off.chirp1, 0), Hb[buf], nb, s);
         },
         [&](long long b0, long long nb, int buf, hipStream_t s) {
+          if (clist) return run_rows<C>(P, Hb[buf], nullptr, nb, false, s, clist + b0);
           return run_rows<C>(P, Hb[buf], c + b0 * MN, nb, false, s);
         });
   }
