@@ -36,10 +36,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, es: int, L: int, MN: int, B: int) -> int:
-    """Bytes a kernel must move per launch: its inputs and outputs once.
-    factorisation kernel: read the signal (L) and write h (M N); channel DFT:
-    read h and write the coefficients (2 M N)."""
+def algorithmic_bytes_per_step(kernel: str, es: int, L: int, MN: int, B: int) -> int:
+    """Bytes a kernel must move per step (whole batch): its inputs and outputs
+    once.  factorisation kernel: read the signals (L each) and write h (M N
+    each); channel DFT: read h and write the coefficients (2 M N each).  A
+    launch that processes a chunk of the batch moves its share."""
     if kernel.startswith("factorisation"):
         return es * (L + MN) * B
     if kernel.startswith("channel DFT"):
@@ -217,15 +218,20 @@ def main():
         return
     value = coeffs / (ms * 1e-3)
 
-    # dominant kernel and its roofline
+    # dominant kernel and its roofline: bytes per launch = bytes per step
+    # divided by the launches per step (the batch may run in chunks)
     dom = max(kt.items(), key=lambda kv: kv[1][1])
     dname, (dn, dms) = dom
     avg_ms = dms / dn
-    abytes = algorithmic_bytes(dname, 8, w.L, MN, w.batch)
+    per_step = dn / args.steps
+    abytes = algorithmic_bytes_per_step(dname, 8, w.L, MN, w.batch) / per_step
     achieved = abytes / (avg_ms * 1e-3) / 1e9
-    kernels = {k: {"launches": n, "avg_ms": round(t / n, 4),
-                   "algorithmic_GBps": round(algorithmic_bytes(k, 8, w.L, MN, w.batch) / (t / n * 1e-3) / 1e9, 1)}
-               for k, (n, t) in kt.items()}
+    kernels = {}
+    for k, (n, t) in kt.items():
+        b = algorithmic_bytes_per_step(k, 8, w.L, MN, w.batch) / (n / args.steps)
+        kernels[k] = {"launches_per_step": n / args.steps, "avg_ms": round(t / n, 4),
+                      "algorithmic_bytes_per_launch": int(b),
+                      "algorithmic_GBps": round(b / (t / n * 1e-3) / 1e9, 1)}
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
@@ -250,7 +256,8 @@ def main():
         "config": {"workload": w.name, "L": w.L, "a": w.a, "M": w.M, "lambda": f"{w.lam1}/{w.lam2}",
                    "batch": w.batch, "coeffs_per_step": coeffs, "branch": "time shear (s0=0, s1=-4)"},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_launch": int(abytes), "avg_launch_ms": round(avg_ms, 4)},
         "kernels": kernels,
         "wall_ms_per_step": wall_ms,
         "whole_path": {"compulsory_bytes_per_coeff": 9.0,

@@ -109,6 +109,7 @@ template <typename C> struct ColArgs {
   long long hs;
   const C* twd;
   int Mi, ai, d, p, q, W, Sd;
+  int nsplit;                  // wave kernel: work-groups sharing one column block (split of Z_q)
   FftSched fd;
 };
 

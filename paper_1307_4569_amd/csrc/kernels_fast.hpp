@@ -42,7 +42,9 @@ template <typename C, int MI> struct FastRows {
 
 // ----------------------------------------------------------------------------
 // Forward factorisation, p = 1, compile-time d = D.
-// grid (ceil(Mi / W), B), 512 threads.
+// grid (ceil(Mi / W) * nsplit, B), 512 threads; the nsplit work-groups of a
+// column block each compute the column DFTs and a share of the q offsets n0
+// (more work-groups for small batches).
 // ----------------------------------------------------------------------------
 template <typename C, int D>
 __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
@@ -53,7 +55,11 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
   const int Mi = A.Mi;
-  const int r0 = blockIdx.x * W;
+  // column block and the share of time offsets n0 of this work-group
+  const int cb = blockIdx.x / A.nsplit, part = blockIdx.x - cb * A.nsplit;
+  const int qper = (A.q + A.nsplit - 1) / A.nsplit;
+  const int n0_begin = part * qper, n0_end = min(A.q, n0_begin + qper);
+  const int r0 = cb * W;
   const long long bo = blockIdx.y;
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = A.list ? 0 : bo * A.xs;
@@ -82,7 +88,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
 #pragma unroll
   for (int k = 0; k < K; ++k) wave_fft<C, D, false>(X[k], ex, l, tw);
   const C* tw_d = A.twd;
-  for (int n0 = 0; n0 < A.q; ++n0) {
+  for (int n0 = n0_begin; n0 < n0_end; ++n0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int r = r0 + (wave * K + k) * I::TPW + tt;

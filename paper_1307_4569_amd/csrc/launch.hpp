@@ -45,7 +45,9 @@ hipStream_t helper_stream();          // per device, created once (default prior
 hipEvent_t take_sync_event();
 void give_sync_event(hipEvent_t e);
 
-inline bool pipelined(const Plan& P, long long B) { return P.chunk > 0 && B >= 2 * P.chunk; }
+inline bool pipelined(const Plan& P, long long B, int op) {
+  return op == DGTNS_OP_FORWARD && P.chunk > 0 && B >= 2 * P.chunk;
+}
 
 template <typename S1, typename S2>
 int run_pipeline(long long B, long long chunk, hipStream_t st, S1 stage1, S2 stage2) {
@@ -177,7 +179,7 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
   switch (op) {
     case DGTNS_OP_FORWARD:
     case DGTNS_OP_ADJOINT:
-      if (pipelined(P, B)) {
+      if (pipelined(P, B, op)) {
         l.H = take(es * MN * P.chunk);
         l.F = take(es * MN * P.chunk);   // second h buffer
       } else {
@@ -215,8 +217,15 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
 template <typename C, int D>
 int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t st) {
   using F = FastCols<C, D>;
-  dim3 grid(cdiv(P.Mi, F::W), unsigned(B));
-  return launch(k_fwd_cols_w<C, D>, grid, sizeof(C) * F::LDS, st, A, "factorisation kernel");
+  const long long nblk = cdiv(P.Mi, F::W);
+  // at least about 2048 work-groups (8 per compute unit) when the batch is small
+  long long ns = (2048 + nblk * B - 1) / (nblk * B);
+  if (ns > P.qi) ns = P.qi;
+  if (ns < 1) ns = 1;
+  ColArgs<C> A2 = A;
+  A2.nsplit = int(ns);
+  dim3 grid(unsigned(nblk * ns), unsigned(B));
+  return launch(k_fwd_cols_w<C, D>, grid, sizeof(C) * F::LDS, st, A2, "factorisation kernel");
 }
 
 template <typename C, int D>
@@ -255,6 +264,7 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
   A.twd = tab<C>(P, P.off.tw_d);
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.p = int(P.pi); A.q = int(P.qi);
   A.W = P.W; A.Sd = int(P.di | 1); A.fd = sched(P.fd);
+  A.nsplit = 1;
   const size_t es = sizeof(C);
   // wave kernels up to d = 1024 (FP32) or 512 (FP64; d = 1024 would spill registers)
   if (P.pi == 1 && !P.generic && P.di * long(sizeof(C)) <= 8192) {
@@ -416,7 +426,7 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
   int rc;
   // the workspace layout of this batch size decides the path (ws_layout):
   // pipelined batches only have room for two chunks of h
-  if (pipelined(P, B)) {
+  if (pipelined(P, B, DGTNS_OP_FORWARD)) {
     C* Hb[2] = {H, reinterpret_cast<C*>(ws + l.F)};
     const size_t sig_bytes = size_t(P.L) * (real_in ? sizeof(C) / 2 : sizeof(C));
     const long long MN = P.M * P.N;
@@ -452,7 +462,7 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
 template <typename C>
 int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const Layout& l, hipStream_t st) {
   C* H = reinterpret_cast<C*>(ws + l.H);
-  if (pipelined(P, B)) {
+  if (pipelined(P, B, DGTNS_OP_ADJOINT)) {
     C* Hb[2] = {H, reinterpret_cast<C*>(ws + l.F)};
     const long long MN = P.M * P.N;
     return run_pipeline(

@@ -281,7 +281,10 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   if (!no_pipe && p.branch != kFreqShear) {
     // h of one chunk: chunk * M N elements; two chunks in flight, about 64 MiB each
     const int64_t per_sig = p.Mi * p.Ni * (dtype == 0 ? 8 : 16);
-    p.chunk = (int64_t(64) << 20) / per_sig;
+    int64_t mib = 64;
+    const char* cm = std::getenv("DGTNS_CHUNK_MIB");
+    if (cm && std::atoi(cm) > 0) mib = std::atoi(cm);
+    p.chunk = (mib << 20) / per_sig;
     if (p.chunk < 1) p.chunk = 1;
   }
   p.ci = gcd64(p.ai, p.Mi);
