@@ -278,6 +278,8 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   }
   p.bi = L / p.Mi;
   p.Ni = L / p.ai;
+  p.ntb = (p.Ni / p.qi + 15) / 16;              // 16-wide tiles of the d time offsets t'
+  p.hs = p.qi * p.ntb * 16 * p.Mi;              // elements of h per signal (tiled, padded)
   if (!no_pipe && p.branch != kFreqShear) {
     // opt-in (DGTNS_CHUNK_MIB): chunks of about that many MiB of h, two in flight
     const int64_t per_sig = p.Mi * p.Ni * (dtype == 0 ? 8 : 16);
@@ -291,8 +293,6 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   p.pi = p.ai / p.ci;
   p.qi = p.Mi / p.ci;
   p.di = p.bi / p.pi;
-  p.ntb = (p.di + 15) / 16;                      // 16-wide tiles of the d time offsets t'
-  p.hs = p.qi * p.ntb * 16 * p.Mi;               // elements of h per signal (tiled, padded)
 
   if (!fft_schedule(p.di, &p.fd) || !fft_schedule(p.Mi, &p.fm)) {
     *err = "transform lengths d = " + std::to_string(p.di) + " and M = " + std::to_string(p.Mi) +
