@@ -26,13 +26,6 @@ namespace dgtns {
 // kernel arguments).
 constexpr int kListMax = 16;
 
-// Offset of h_{n0 + q t}(r) in one signal's intermediate, stored in tiles of
-// 16 time offsets: h[n0][t / 16][r][t mod 16].  A row work-group then reads
-// one contiguous tile per 16 time positions, and a column writes runs of 16.
-__device__ __forceinline__ long long hidx(int n0, int r, int t, int Mi, int ntb) {
-  return ((long long)(n0 * ntb + (t >> 4)) * Mi + r) * 16 + (t & 15);
-}
-
 // a[i] for a work-group-uniform i, with constant indices only (a dynamic
 // index into a by-value kernel argument would move the whole argument block
 // to scratch memory)
@@ -115,7 +108,7 @@ template <typename C> struct ColArgs {
   C* H;
   long long hs;
   const C* twd;
-  int Mi, ai, d, p, q, W, Sd, ntb;
+  int Mi, ai, d, p, q, W, Sd;
   int nsplit;                  // wave kernel: work-groups sharing one column block (split of Z_q)
   FftSched fd;
 };
@@ -195,7 +188,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
     fft_lds<C, true>(yb, Sd, A.fd, W, tw);
     for (int e = threadIdx.x; e < WD; e += kThreads) {
       const int cc = e / d, t = e - cc * d, r = r0 + cc;
-      if (r < Mi) A.H[bo * A.hs + hidx(n0, r, t, Mi, A.ntb)] = yb[cc * Sd + t];
+      if (r < Mi) A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t] = yb[cc * Sd + t];
     }
   }
 }
@@ -214,7 +207,7 @@ template <typename C> struct ColAdjArgs {
   ChirpSrc<C> chirp;
   C* y;
   long long ys;
-  int Mi, ai, d, p, q, W, Sd, ntb;
+  int Mi, ai, d, p, q, W, Sd;
   FftSched fd;
 };
 
@@ -239,7 +232,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
     __syncthreads();
     for (int e = threadIdx.x; e < WD; e += kThreads) {
       const int cc = e / d, t = e - cc * d, r = r0 + cc;
-      yb[cc * Sd + t] = r < Mi ? A.H[bo * A.hs + hidx(n0, r, t, Mi, A.ntb)] : czero<C>();
+      yb[cc * Sd + t] = r < Mi ? A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t] : czero<C>();
     }
     __syncthreads();
     fft_lds<C, false>(yb, Sd, A.fd, W, tw);
@@ -323,7 +316,7 @@ template <typename C> struct RowArgs {
   const int* rho;
   int list;                    // forward: coefficients of signal k at cl[k] instead of c + k cs
   C* cl[kListMax];
-  int Mi, Ni, R, Sm, q, d, ntb;
+  int Mi, Ni, R, Sm, q, d;
   FftSched fm;
   long long N, L, b, M, K1, K2, K3, K4, K5, C1n, C2n, Kt1, Kt6;
 };
@@ -353,10 +346,10 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows(RowArgs<C> A) {
   for (int e = threadIdx.x; e < Mi; e += kThreads) tw[e] = A.twm[e];
   const int q = A.q, d = A.d, n0 = blockIdx.x % q, t0 = (blockIdx.x / q) * R;
   const long long bo = blockIdx.y;
-  const C* Hb = A.H + bo * A.hs;
+  const C* Hb = A.H + bo * A.hs + (long long)n0 * Mi * d + t0;
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
     const int m = e / R, i = e - m * R;
-    buf[i * Sm + m] = t0 + i < d ? Hb[hidx(n0, m, t0 + i, Mi, A.ntb)] : czero<C>();
+    buf[i * Sm + m] = t0 + i < d ? Hb[(long long)m * d + i] : czero<C>();
   }
   __syncthreads();
   fft_lds<C, false>(buf, Sm, A.fm, R, tw);
@@ -409,10 +402,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows(RowArgs<C> A) {
   }
   __syncthreads();
   fft_lds<C, true>(buf, Sm, A.fm, R, tw);
-  C* Hb = const_cast<C*>(A.H) + bo * A.hs;
+  C* Hb = const_cast<C*>(A.H) + bo * A.hs + (long long)n0 * Mi * d + t0;
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
     const int m = e / R, i = e - m * R;
-    if (t0 + i < d) Hb[hidx(n0, m, t0 + i, Mi, A.ntb)] = buf[i * Sm + m];
+    if (t0 + i < d) Hb[(long long)m * d + i] = buf[i * Sm + m];
   }
 }
 
@@ -677,7 +670,7 @@ template <typename C> struct GradArgs {
   C* part;
   long long ps;
   const C* twd;
-  int Mi, ai, d, q, W, Sd, ntb;
+  int Mi, ai, d, q, W, Sd;
   FftSched fd;
 };
 
@@ -716,7 +709,7 @@ __global__ void __launch_bounds__(kThreads) k_grad_cols(GradArgs<C> A) {
       if (u < Mi) {
         int r = u + n0 * A.ai;
         if (r >= Mi) r -= Mi;
-        h = A.H[bo * A.hs + hidx(n0, r, t, Mi, A.ntb)];
+        h = A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t];
       }
       yb[cc * Sd + t] = h;
     }

@@ -3,10 +3,10 @@
 // post-processing of Alg. 1 ("rows"), and their adjoints.
 //
 // Intermediate layout (shared with the generic kernels): per signal
-//   h_{n0 + q t'}(r) at h[n0][t' / 16][r][t' mod 16]   (see hidx),
-// so a factorisation column writes runs of 16 time offsets, and a row
-// work-group (RB consecutive t' of one n0, RB a multiple of 16) reads whole
-// contiguous tiles.
+//   h[n0][r][t'] = h_{n0 + q t'}(r),   n0 in Z_q, r in Z_Mi, t' in Z_d,
+// so a factorisation column writes d contiguous values per time offset n0,
+// and a row kernel reads, for each channel r, a contiguous run of time
+// positions t' (one work-group handles RB consecutive t' of one n0).
 #pragma once
 #include "kernels.hpp"
 #include "wave_fft.hpp"
@@ -106,9 +106,9 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
       }
       wave_fft<C, D, true>(Y, ex, l, tw);
       if (ok) {
-        C* hb = A.H + bo * A.hs;
+        C* hb = A.H + bo * A.hs + ((long long)n0 * Mi + r) * D;
 #pragma unroll
-        for (int e = 0; e < E; ++e) hb[hidx(n0, r, l + T * e, Mi, A.ntb)] = Y[e];
+        for (int e = 0; e < E; ++e) hb[l + T * e] = Y[e];
       }
     }
   }
@@ -142,9 +142,9 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols_w(ColAdjArgs<C> A) {
       const int r = r0 + (wave * K + k) * I::TPW + tt;
       const bool ok = r < Mi;
       C Y[E];
-      const C* hb = A.H + bo * A.hs;
+      const C* hb = A.H + bo * A.hs + ((long long)n0 * Mi + (ok ? r : 0)) * D;
 #pragma unroll
-      for (int e = 0; e < E; ++e) Y[e] = hb[hidx(n0, ok ? r : 0, l + T * e, Mi, A.ntb)];
+      for (int e = 0; e < E; ++e) Y[e] = hb[l + T * e];
       wave_fft<C, D, false>(Y, ex, l, tw);
       const int v0 = r - n0 * A.ai;
       const int u = v0 >= 0 ? v0 : v0 + Mi;
@@ -193,19 +193,10 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   const int q = A.q, d = A.d;
   const int n0 = blockIdx.x % q, t0 = (blockIdx.x / q) * RB;
   const long long bo = blockIdx.y;
-  const C* hb = A.H + bo * A.hs;
-  if constexpr (RB % 16 == 0) {
-    // RB / 16 whole tiles of h, each one contiguous run of 16 MI elements
-    const C* tile = hb + ((long long)n0 * A.ntb + (t0 >> 4)) * MI * 16;
-    for (int e = tid; e < RB * MI; e += kThreads) {
-      const int sub = e / (16 * MI), rem = e - sub * (16 * MI), m = rem >> 4, i = sub * 16 + (rem & 15);
-      lds[m * SR + i] = t0 + i < d ? tile[(long long)sub * A.Mi * 16 + rem] : czero<C>();
-    }
-  } else {
-    for (int e = tid; e < RB * MI; e += kThreads) {
-      const int m = e / RB, i = e - m * RB;
-      lds[m * SR + i] = t0 + i < d ? hb[hidx(n0, m, t0 + i, MI, A.ntb)] : czero<C>();
-    }
+  const C* hb = A.H + bo * A.hs + (long long)n0 * MI * d + t0;
+  for (int e = tid; e < RB * MI; e += kThreads) {
+    const int m = e / RB, i = e - m * RB;
+    lds[m * SR + i] = t0 + i < d ? hb[(long long)m * d + i] : czero<C>();
   }
   WTw<C, MI> tw;
   tw.load(A.twm, l);
@@ -303,18 +294,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
     for (int e = 0; e < E; ++e) lds[(l + T * e) * SR + i] = v[k][e];
   }
   __syncthreads();
-  C* hb = const_cast<C*>(A.H) + bo * A.hs;
-  if constexpr (RB % 16 == 0) {
-    C* tile = hb + ((long long)n0 * A.ntb + (t0 >> 4)) * MI * 16;
-    for (int e = tid; e < RB * MI; e += kThreads) {
-      const int sub = e / (16 * MI), rem = e - sub * (16 * MI), m = rem >> 4, i = sub * 16 + (rem & 15);
-      if (t0 + i < d) tile[(long long)sub * A.Mi * 16 + rem] = lds[m * SR + i];
-    }
-  } else {
-    for (int e = tid; e < RB * MI; e += kThreads) {
-      const int m = e / RB, i = e - m * RB;
-      if (t0 + i < d) hb[hidx(n0, m, t0 + i, MI, A.ntb)] = lds[m * SR + i];
-    }
+  C* hb = const_cast<C*>(A.H) + bo * A.hs + (long long)n0 * MI * d + t0;
+  for (int e = tid; e < RB * MI; e += kThreads) {
+    const int m = e / RB, i = e - m * RB;
+    if (t0 + i < d) hb[(long long)m * d + i] = lds[m * SR + i];
   }
 }
 

@@ -170,7 +170,7 @@ struct Layout {
 
 inline Layout ws_layout(const Plan& P, int op, long long B) {
   const size_t es = P.dtype == 0 ? 8 : 16;
-  const size_t MN = size_t(P.hs);   // elements of the (tiled, padded) intermediate per signal
+  const size_t MN = size_t(P.Mi) * size_t(P.Ni);
   const size_t L = size_t(P.L);
   Layout l;
   size_t o = 0;
@@ -260,7 +260,7 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
     for (long long k = 0; k < B; ++k) A.xl[k] = xlist[k];
   }
   A.zc = tab<C>(P, P.off.zc);
-  A.H = H; A.hs = P.hs; A.ntb = int(P.ntb);
+  A.H = H; A.hs = (long long)P.Mi * P.Ni;
   A.twd = tab<C>(P, P.off.tw_d);
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.p = int(P.pi); A.q = int(P.qi);
   A.W = P.W; A.Sd = int(P.di | 1); A.fd = sched(P.fd);
@@ -291,7 +291,7 @@ template <typename C>
 int run_adj_cols(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, hipStream_t st) {
   ColAdjArgs<C> A;
   std::memset(&A, 0, sizeof(A));
-  A.H = H; A.hs = P.hs; A.ntb = int(P.ntb);
+  A.H = H; A.hs = (long long)P.Mi * P.Ni;
   A.zc = tab<C>(P, P.off.zc);
   A.twd = tab<C>(P, P.off.tw_d);
   A.chirp = ch; A.y = y; A.ys = P.L;
@@ -319,7 +319,7 @@ template <typename C>
 RowArgs<C> row_args(const Plan& P, const C* H, C* c) {
   RowArgs<C> A;
   std::memset(&A, 0, sizeof(A));
-  A.H = H; A.hs = P.hs; A.ntb = int(P.ntb);
+  A.H = H; A.hs = (long long)P.Mi * P.Ni;
   A.c = c; A.cs = (long long)P.M * P.N;
   A.twm = tab<C>(P, P.off.tw_m);
   A.Mi = int(P.Mi); A.Ni = int(P.Ni);
@@ -508,7 +508,7 @@ int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* 
   }
   GradArgs<C> A;
   A.x = x; A.xs = P.L; A.real_in = 0; A.chirp = ch;
-  A.H = H; A.hs = P.hs; A.ntb = int(P.ntb);
+  A.H = H; A.hs = (long long)P.Mi * P.Ni;
   A.part = part; A.ps = P.L;
   A.twd = tab<C>(P, P.off.tw_d);
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.q = int(P.qi);

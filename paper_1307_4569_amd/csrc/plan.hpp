@@ -61,8 +61,6 @@ struct Plan {
   int64_t max_batch;
   // separable lattice the factorised DGT runs on (time step ai, channels Mi)
   int64_t ai, Mi, bi, Ni, ci, pi, qi, di;
-  // intermediate h per signal, tiled as h[n0][t' / 16][r][t' mod 16]
-  int64_t ntb, hs;
   // frequency-shear branch constants of Alg. 1 (reduced mod 2N or mod L)
   int64_t ar, Mr, Nr;
   int64_t K1, K2, K3, K4, K5;     // C1, C2, C3, C4, C5 mod 2N
@@ -86,9 +84,9 @@ struct Plan {
   void* dev = nullptr;       // bound persistent memory
   bool window_set = false;
   bool generic = false;   // force the runtime-schedule kernels (DGTNS_GENERIC=1)
-  // Signals per chunk of the optional two-stream pipeline of the time-shear
-  // branch (DGTNS_CHUNK_MIB): the workspace then holds two chunks of h
-  // instead of the whole batch.  0: one launch per stage.
+  // Signals per chunk of the two-stream pipeline of the time-shear branch:
+  // the two h buffers of a chunk pair stay within the last-level (Infinity)
+  // cache.  0 disables the pipeline (DGTNS_NO_PIPELINE=1).
   int64_t chunk = 0;
 };
 
