@@ -237,11 +237,6 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
     const char* gen = std::getenv("DGTNS_GENERIC");
     p.generic = gen && gen[0] == '1';
   }
-  bool no_pipe = false;
-  {
-    const char* np = std::getenv("DGTNS_NO_PIPELINE");
-    no_pipe = np && np[0] == '1';
-  }
   p.sh = shearfind(L, a, M, p.s, p.b, err);
   if (p.sh.br == 0) return kELattice;
   if (p.s == 0) p.branch = kSeparable;
@@ -278,14 +273,14 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   }
   p.bi = L / p.Mi;
   p.Ni = L / p.ai;
-  if (!no_pipe && p.branch != kFreqShear) {
-    // h of one chunk: chunk * M N elements; two chunks in flight, about 64 MiB each
+  if (p.branch != kFreqShear) {
+    // opt-in (DGTNS_CHUNK_MIB): chunks of about that many MiB of h, two in flight
     const int64_t per_sig = p.Mi * p.Ni * (dtype == 0 ? 8 : 16);
-    int64_t mib = 64;
     const char* cm = std::getenv("DGTNS_CHUNK_MIB");
-    if (cm && std::atoi(cm) > 0) mib = std::atoi(cm);
-    p.chunk = (mib << 20) / per_sig;
-    if (p.chunk < 1) p.chunk = 1;
+    if (cm && std::atoi(cm) > 0) {
+      p.chunk = (int64_t(std::atoi(cm)) << 20) / per_sig;
+      if (p.chunk < 1) p.chunk = 1;
+    }
   }
   p.ci = gcd64(p.ai, p.Mi);
   p.pi = p.ai / p.ci;

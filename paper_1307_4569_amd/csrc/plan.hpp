@@ -84,9 +84,9 @@ struct Plan {
   void* dev = nullptr;       // bound persistent memory
   bool window_set = false;
   bool generic = false;   // force the runtime-schedule kernels (DGTNS_GENERIC=1)
-  // Signals per chunk of the two-stream pipeline of the time-shear branch:
-  // the two h buffers of a chunk pair stay within the last-level (Infinity)
-  // cache.  0 disables the pipeline (DGTNS_NO_PIPELINE=1).
+  // Signals per chunk of the optional two-stream pipeline of the time-shear
+  // branch (DGTNS_CHUNK_MIB): the workspace then holds two chunks of h
+  // instead of the whole batch.  0: one launch per stage.
   int64_t chunk = 0;
 };
 

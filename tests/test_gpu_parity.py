@@ -248,8 +248,9 @@ def test_gradient_workload_sampled(kernel_path):
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
 def test_pipelined_batches_match_single_launch(dtype, monkeypatch):
-    """Batches split into chunks on two streams (ragged last chunk) give the
-    same coefficients and adjoints, bit for bit, as one launch per stage."""
+    """The optional two-stream chunk pipeline (DGTNS_CHUNK_MIB; ragged last
+    chunk) gives the same coefficients and adjoints, bit for bit, as one
+    launch per stage, with a smaller workspace."""
     w = LARGE
     B = 11
     f = torch.tensor(complex_normal_batch(B, w.L, 2).astype(np.complex64)).to(dtype).cuda()
@@ -257,9 +258,9 @@ def test_pipelined_batches_match_single_launch(dtype, monkeypatch):
     out = {}
     for mode in ("pipeline", "single"):
         if mode == "single":
-            monkeypatch.setenv("DGTNS_NO_PIPELINE", "1")
+            monkeypatch.delenv("DGTNS_CHUNK_MIB", raising=False)
         else:
-            monkeypatch.delenv("DGTNS_NO_PIPELINE", raising=False)
+            monkeypatch.setenv("DGTNS_CHUNK_MIB", "64")
         plan = make_plan(w.L, w.a, w.M, w.lam1, w.lam2, dtype, B)
         plan.set_window(g)
         c = plan.forward(f)
