@@ -16,11 +16,10 @@ namespace dgtns {
 // elements per work-group: 8192 (FP32) or 4096 (FP64)
 template <typename C> struct Budget { static constexpr int value = sizeof(C) == 8 ? 8192 : 4096; };
 
-// Columns per work-group of the fast factorisation kernels for length D
-// (HALF: half the element budget, i.e. more work-groups per compute unit).
-template <typename C, int D, bool HALF = false> struct FastCols {
+// Columns per work-group of the fast factorisation kernels for length D.
+template <typename C, int D> struct FastCols {
   static constexpr int TPW = WInfo<D>::TPW;
-  static constexpr int K0 = Budget<C>::value / (8 * TPW * D) / (HALF ? 2 : 1);
+  static constexpr int K0 = Budget<C>::value / (8 * TPW * D);
   static constexpr int K = K0 < 1 ? 1 : K0;       // wave transforms per wavefront
   static constexpr int W = 8 * TPW * K;           // columns per work-group (8 wavefronts)
   static constexpr int SD = D + 1;                // padded column stride of the LDS tile
@@ -29,10 +28,11 @@ template <typename C, int D, bool HALF = false> struct FastCols {
   static constexpr int LDS = (TILE > 8 * EXW ? TILE : 8 * EXW);
 };
 
-// Rows per work-group of the fast row kernels for length MI.
-template <typename C, int MI, bool HALF = false> struct FastRows {
+// Rows per work-group of the fast row kernels for length MI: half the element
+// budget, so that four work-groups (32 wavefronts) fit on a compute unit.
+template <typename C, int MI> struct FastRows {
   static constexpr int TPW = WInfo<MI>::TPW;
-  static constexpr int K0 = Budget<C>::value / (8 * TPW * MI) / (HALF ? 2 : 1);
+  static constexpr int K0 = Budget<C>::value / (16 * TPW * MI);
   static constexpr int K = K0 < 1 ? 1 : K0;
   static constexpr int RB = 8 * TPW * K;          // rows (time positions t') per work-group
   static constexpr int SR = RB + 1;               // padded stride of the [Mi][RB] tile
@@ -47,9 +47,9 @@ template <typename C, int MI, bool HALF = false> struct FastRows {
 // column block each compute the column DFTs and a share of the q offsets n0
 // (more work-groups for small batches).
 // ----------------------------------------------------------------------------
-template <typename C, int D, bool HALF>
+template <typename C, int D>
 __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
-  using F = FastCols<C, D, HALF>;
+  using F = FastCols<C, D>;
   using I = WInfo<D>;
   constexpr int E = I::E, T = I::T, K = F::K, W = F::W, SD = F::SD;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -183,9 +183,9 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols_w(ColAdjArgs<C> A) {
 // positions n = n0 + q (t0 + i), i in Z_RB, with n0 = blockIdx.x mod q.
 // grid (q * ceil(d / RB), B), 512 threads.
 // ----------------------------------------------------------------------------
-template <typename C, int MI, int MODE, bool HALF>
+template <typename C, int MI, int MODE>
 __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
-  using F = FastRows<C, MI, HALF>;
+  using F = FastRows<C, MI>;
   using I = WInfo<MI>;
   constexpr int E = I::E, T = I::T, K = F::K, RB = F::RB, SR = F::SR;
   extern __shared__ __align__(16) unsigned char smem_raw[];

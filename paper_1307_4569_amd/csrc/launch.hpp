@@ -214,9 +214,9 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
 // stage launchers (templated on precision)
 // ---------------------------------------------------------------------------
 
-template <typename C, int D, bool HALF>
-int run_cols_fast_v(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t st) {
-  using F = FastCols<C, D, HALF>;
+template <typename C, int D>
+int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t st) {
+  using F = FastCols<C, D>;
   const long long nblk = cdiv(P.Mi, F::W);
   // at least about 2048 work-groups (8 per compute unit) when the batch is small
   long long ns = (2048 + nblk * B - 1) / (nblk * B);
@@ -225,13 +225,7 @@ int run_cols_fast_v(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t
   ColArgs<C> A2 = A;
   A2.nsplit = int(ns);
   dim3 grid(unsigned(nblk * ns), unsigned(B));
-  return launch(k_fwd_cols_w<C, D, HALF>, grid, sizeof(C) * F::LDS, st, A2, "factorisation kernel");
-}
-
-template <typename C, int D>
-int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t st) {
-  if (P.half_cols) return run_cols_fast_v<C, D, true>(P, A, B, st);
-  return run_cols_fast_v<C, D, false>(P, A, B, st);
+  return launch(k_fwd_cols_w<C, D>, grid, sizeof(C) * F::LDS, st, A2, "factorisation kernel");
 }
 
 template <typename C, int D>
@@ -241,16 +235,6 @@ int run_adj_cols_fast(const Plan& P, const ColAdjArgs<C>& A, long long B, hipStr
   return launch(k_adj_cols_w<C, D>, grid, sizeof(C) * F::LDS, st, A, "adjoint factorisation kernel");
 }
 
-template <typename C, int MI, bool HALF>
-int run_fwd_rows_fast(const Plan& P, const RowArgs<C>& A, long long B, hipStream_t st) {
-  using F = FastRows<C, MI, HALF>;
-  dim3 grid(unsigned(P.qi) * cdiv(P.di, F::RB), unsigned(B));
-  const size_t lds = sizeof(C) * F::LDS;
-  if (P.branch == kFreqShear)
-    return launch(k_fwd_rows_w<C, MI, 1, HALF>, grid, lds, st, A, "channel DFT + shear post-processing");
-  return launch(k_fwd_rows_w<C, MI, 0, HALF>, grid, lds, st, A, "channel DFT + phase correction");
-}
-
 template <typename C, int MI>
 int run_rows_fast(const Plan& P, const RowArgs<C>& A, long long B, bool adjoint, hipStream_t st) {
   using F = FastRows<C, MI>;
@@ -258,8 +242,8 @@ int run_rows_fast(const Plan& P, const RowArgs<C>& A, long long B, bool adjoint,
   const size_t lds = sizeof(C) * F::LDS;
   const bool fs = P.branch == kFreqShear;
   if (!adjoint) {
-    if (P.half_rows) return run_fwd_rows_fast<C, MI, true>(P, A, B, st);
-    return run_fwd_rows_fast<C, MI, false>(P, A, B, st);
+    if (fs) return launch(k_fwd_rows_w<C, MI, 1>, grid, lds, st, A, "channel DFT + shear post-processing");
+    return launch(k_fwd_rows_w<C, MI, 0>, grid, lds, st, A, "channel DFT + phase correction");
   }
   if (fs) return launch(k_adj_rows_w<C, MI, 1>, grid, lds, st, A, "adjoint channel DFT (shear)");
   return launch(k_adj_rows_w<C, MI, 0>, grid, lds, st, A, "adjoint channel DFT");

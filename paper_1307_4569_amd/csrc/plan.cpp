@@ -236,10 +236,6 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   {
     const char* gen = std::getenv("DGTNS_GENERIC");
     p.generic = gen && gen[0] == '1';
-    const char* hc = std::getenv("DGTNS_HALF_COLS");
-    p.half_cols = hc && hc[0] == '1';
-    const char* hr = std::getenv("DGTNS_HALF_ROWS");
-    p.half_rows = hr && hr[0] == '1';
   }
   p.sh = shearfind(L, a, M, p.s, p.b, err);
   if (p.sh.br == 0) return kELattice;

@@ -84,9 +84,6 @@ struct Plan {
   void* dev = nullptr;       // bound persistent memory
   bool window_set = false;
   bool generic = false;   // force the runtime-schedule kernels (DGTNS_GENERIC=1)
-  // half-size column / row blocks of the forward wave kernels (more
-  // work-groups per compute unit): DGTNS_HALF_COLS=1, DGTNS_HALF_ROWS=1
-  bool half_cols = false, half_rows = false;
   // Signals per chunk of the optional two-stream pipeline of the time-shear
   // branch (DGTNS_CHUNK_MIB): the workspace then holds two chunks of h
   // instead of the whole batch.  0: one launch per stage.
