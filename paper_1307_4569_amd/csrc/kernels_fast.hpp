@@ -24,20 +24,29 @@ template <typename C, int D> struct FastCols {
   static constexpr int W = 8 * TPW * K;           // columns per work-group (8 wavefronts)
   static constexpr int SD = D + 1;                // padded column stride of the LDS tile
   static constexpr int TILE = W * SD;
-  static constexpr int EXW = TPW * WInfo<D>::EX;  // exchange elements per wavefront
+  static constexpr int EXW = TPW * WEx<C, D>::EX;  // exchange elements per wavefront
   static constexpr int LDS = (TILE > 8 * EXW ? TILE : 8 * EXW);
 };
 
 // Rows per work-group of the fast row kernels for length MI: half the element
 // budget, so that four work-groups (32 wavefronts) fit on a compute unit.
+// The [Mi][RB] tile of the adjoint (strided stores, row-wise loads) uses the
+// padded stride RB + 1; the forward tile (row-wise stores, strided loads)
+// stores element (m, i) at m RB + i + m / PD, which keeps both its stores
+// (128 bytes per cycle) and its column loads (256 bytes per cycle) free of
+// LDS bank conflicts when RB is below the 256 bytes a load serves.
 template <typename C, int MI> struct FastRows {
   static constexpr int TPW = WInfo<MI>::TPW;
   static constexpr int K0 = Budget<C>::value / (16 * TPW * MI);
   static constexpr int K = K0 < 1 ? 1 : K0;
   static constexpr int RB = 8 * TPW * K;          // rows (time positions t') per work-group
-  static constexpr int SR = RB + 1;               // padded stride of the [Mi][RB] tile
-  static constexpr int TILE = MI * SR;
-  static constexpr int EXW = TPW * WInfo<MI>::EX;
+  static constexpr int SR = RB + 1;               // padded stride of the adjoint tile
+  static constexpr int LR = 256 / int(sizeof(C)); // elements one LDS load cycle serves
+  static constexpr int PD = RB >= LR ? 1 : LR / RB;
+  static __device__ __forceinline__ int fwd_at(int m, int i) { return m * RB + i + m / PD; }
+  static constexpr int TILE_F = MI * RB + MI / PD;
+  static constexpr int TILE = MI * SR > TILE_F ? MI * SR : TILE_F;
+  static constexpr int EXW = TPW * WEx<C, MI>::EX;
   static constexpr int LDS = (TILE > 8 * EXW ? TILE : 8 * EXW);
 };
 
@@ -85,7 +94,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
     for (int e = 0; e < E; ++e) X[k][e] = lds[cc * SD + l + T * e];
   }
   __syncthreads();
-  C* ex = lds + wave * F::EXW + tt * I::EX;
+  C* ex = lds + wave * F::EXW + tt * WEx<C, D>::EX;
 #pragma unroll
   for (int k = 0; k < K; ++k) wave_fft<C, D, false>(X[k], ex, l, tw);
   const C* tw_d = A.twd;
@@ -131,7 +140,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols_w(ColAdjArgs<C> A) {
   const long long bo = blockIdx.y;
   WTw<C, D> tw;
   tw.load(A.twd, l);
-  C* ex = lds + wave * F::EXW + tt * I::EX;
+  C* ex = lds + wave * F::EXW + tt * WEx<C, D>::EX;
   C acc[K][E];
 #pragma unroll
   for (int k = 0; k < K; ++k)
@@ -187,7 +196,7 @@ template <typename C, int MI, int MODE>
 __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   using F = FastRows<C, MI>;
   using I = WInfo<MI>;
-  constexpr int E = I::E, T = I::T, K = F::K, RB = F::RB, SR = F::SR;
+  constexpr int E = I::E, T = I::T, K = F::K, RB = F::RB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
@@ -197,7 +206,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   const C* hb = A.H + bo * A.hs + (long long)n0 * MI * d + t0;
   for (int e = tid; e < RB * MI; e += kThreads) {
     const int m = e / RB, i = e - m * RB;
-    lds[m * SR + i] = t0 + i < d ? hb[(long long)m * d + i] : czero<C>();
+    lds[F::fwd_at(m, i)] = t0 + i < d ? hb[(long long)m * d + i] : czero<C>();
   }
   WTw<C, MI> tw;
   tw.load(A.twm, l);
@@ -207,10 +216,10 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   for (int k = 0; k < K; ++k) {
     const int i = (wave * K + k) * I::TPW + tt;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[k][e] = lds[(l + T * e) * SR + i];
+    for (int e = 0; e < E; ++e) v[k][e] = lds[F::fwd_at(l + T * e, i)];
   }
   __syncthreads();
-  C* ex = lds + wave * F::EXW + tt * I::EX;
+  C* ex = lds + wave * F::EXW + tt * WEx<C, MI>::EX;
   C* cb = A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -256,7 +265,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
   const long long bo = blockIdx.y;
   WTw<C, MI> tw;
   tw.load(A.twm, l);
-  C* ex = lds + wave * F::EXW + tt * I::EX;
+  C* ex = lds + wave * F::EXW + tt * WEx<C, MI>::EX;
   const C* cb = A.c + bo * A.cs;
   C v[K][E];
 #pragma unroll

@@ -10,6 +10,15 @@
 // and the last pass leaves X[l + T e] in v[e], i.e. the same strided layout,
 // so global loads and stores of a transform are fully coalesced.
 //
+// Each exchange stores element x of the pass output at x + c (x >> s), with
+// (c, s) chosen per pass and element size so that the strided stores of the
+// pass ((j - k) R + k + r Ns for lanes j, k = j mod Ns) and the contiguous
+// loads that follow spread over the LDS banks.  On gfx950 a store serves 128
+// bytes per cycle (32 banks: 16 lanes of 8-byte or 8 lanes of 16-byte
+// elements) and a load 256 bytes (64 banks), as measured with the
+// SQ_LDS_BANK_CONFLICT counter; the offsets stay affine in the element index,
+// so every access of a lane is one base register plus an immediate offset.
+//
 // Twiddles exp(-+ 2 pi i r k / (Ns R)) are read once per lane from the exact
 // length-N table exp(-2 pi i e / N) and kept in registers (they depend only on
 // the lane, not on the data), so a wavefront that transforms many rows pays
@@ -77,7 +86,6 @@ template <int N> struct WInfo {
   static constexpr int E = S::E;
   static constexpr int T = N / E;       // lanes per transform
   static constexpr int TPW = 64 / T;    // transforms per wavefront
-  static constexpr int EX = N + N / 32; // padded exchange region per transform
   static constexpr int ns(int p) { return p == 0 ? 1 : ns(p - 1) * S::rad(p - 1); }
   static constexpr int ntw_upto(int p) {  // twiddles used by passes 1 .. p-1
     return p <= 1 ? 0 : ntw_upto(p - 1) + (E / S::rad(p - 1)) * (S::rad(p - 1) - 1);
@@ -85,7 +93,30 @@ template <int N> struct WInfo {
   static constexpr int NTW = ntw_upto(S::NP);
 };
 
-__device__ __forceinline__ int xpad(int i) { return i + (i >> 5); }
+// Exchange offset of a pass of stride Ns for ES-byte elements: element x of
+// the pass output lives at x + c (x >> s).  Ns = 1 (stores of stride R = 8):
+// one pad element per 16 (8-byte elements, N >= 128) or per 8; Ns = 8 (runs
+// of 8 at stride 64): 8 pad elements per 64 for 8-byte elements, none for
+// 16-byte ones (8 lanes per store cycle already hit distinct banks).  Later
+// passes store runs of at least 64 contiguous elements and are unpadded.
+template <int ES, int N, int Ns> struct XPad {
+  static constexpr int s = Ns == 1 ? ((ES >= 16 || N <= 64) ? 3 : 4) : 6;
+  static constexpr int c = Ns == 1 ? 1 : (Ns == 8 && ES == 8 ? 8 : 0);
+  static constexpr int need = N + c * ((N - 1) >> s);  // elements spanned
+  static __device__ __forceinline__ int at(int x) { return x + c * (x >> s); }
+};
+
+// Exchange region per transform (elements of type C).  Transforms that share
+// a wavefront (N <= 128) are N + N / 8 apart so that their loads do not
+// collide.
+template <typename C, int N> struct WEx {
+  using I = WInfo<N>;
+  static constexpr int ES = sizeof(C);
+  static constexpr int n0 = XPad<ES, N, 1>::need;
+  static constexpr int n1 = WSched<N>::NP > 2 ? XPad<ES, N, I::ns(1)>::need : 0;
+  static constexpr int need = n0 > n1 ? n0 : n1;
+  static constexpr int EX = (N <= 128 && need < N + N / 8) ? N + N / 8 : need;
+};
 
 // Per-lane twiddles of all passes after the first.
 template <typename C, int N> struct WTw {
@@ -115,6 +146,7 @@ __device__ __forceinline__ void wave_pass(C (&v)[WInfo<N>::E], C* ex, int l, con
   constexpr int E = I::E, T = I::T, R = WSched<N>::rad(P), Ns = I::ns(P), NB = E / R;
   constexpr bool LAST = P == WSched<N>::NP - 1;
   constexpr int off = I::ntw_upto(P);
+  using XP = XPad<int(sizeof(C)), N, Ns>;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     C u[R];
@@ -136,20 +168,20 @@ __device__ __forceinline__ void wave_pass(C (&v)[WInfo<N>::E], C* ex, int l, con
       const int k = j & (Ns - 1);
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) ex[xpad(base + r * Ns)] = u[r];
+      for (int r = 0; r < R; ++r) ex[XP::at(base + r * Ns)] = u[r];
     }
   }
   if constexpr (!LAST) {
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = ex[xpad(l + T * e)];
+    for (int e = 0; e < E; ++e) v[e] = ex[XP::at(l + T * e)];
     __builtin_amdgcn_wave_barrier();
     wave_pass<C, N, INV, P + 1>(v, ex, l, tw);
   }
 }
 
 // In-register transform of the N elements held by this lane's transform
-// group; ex: wave-private LDS region of WInfo<N>::EX elements for this
+// group; ex: wave-private LDS region of WEx<C, N>::EX elements for this
 // transform.  INV: unnormalised inverse.
 template <typename C, int N, bool INV>
 __device__ __forceinline__ void wave_fft(C (&v)[WInfo<N>::E], C* ex, int l, const WTw<C, N>& tw) {
