@@ -20,13 +20,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1307_4569_amd/csrc/kernels.hpp", "paper_1307_4569_amd/csrc/fft_core.hpp",
-                  "paper_1307_4569_amd/csrc/dgtns.hip", "paper_1307_4569_amd/csrc/plan.cpp"]
+CSRC = os.path.join("paper_1307_4569_amd", "csrc")
+
+
+def kernel_sources():
+    """Every source of the native library: stored HBM-counter readings are
+    valid only for the exact code they were taken on."""
+    d = os.path.join(ROOT, CSRC)
+    return sorted(os.path.join(CSRC, n) for n in os.listdir(d) if n.endswith((".hpp", ".hip", ".cpp", ".h")))
 
 
 def sources_hash() -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in kernel_sources():
+        h.update(p.encode())
         with open(os.path.join(ROOT, p), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
