@@ -65,7 +65,14 @@ enum dgtns_dtype { DGTNS_C64 = 0, DGTNS_C128 = 1 };
 enum dgtns_branch {
   DGTNS_SEPARABLE = 0,  /* lambda = 0: no shear */
   DGTNS_TIME_SHEAR = 1, /* s0 = 0: time shear only (Alg. 1, first branch) */
-  DGTNS_FREQ_SHEAR = 2  /* s0 != 0: frequency and time shear (Alg. 1, second branch) */
+  DGTNS_FREQ_SHEAR = 2, /* s0 != 0: frequency and time shear (Alg. 1, second branch) */
+  DGTNS_MULTIWINDOW = 3 /* multiwindow algorithm: lambda2 coset windows (Prop. 4, Prop. 5) */
+};
+
+/* Algorithm of a plan (dgtns_plan_create_alg). */
+enum dgtns_algorithm {
+  DGTNS_ALG_SHEAR = 0,      /* shear algorithm, Alg. 1 (dgtns_plan_create) */
+  DGTNS_ALG_MULTIWINDOW = 1 /* multiwindow algorithm, Section 3.1 (Prop. 4, Prop. 5) */
 };
 
 enum dgtns_op {
@@ -90,6 +97,7 @@ typedef struct {
   int64_t inner_a, inner_M, c, d, p, q;
   int64_t max_batch;
   size_t persistent_bytes; /* device bytes dgtns_plan_bind needs */
+  int64_t windows;         /* windows of the separable lattice: 1, or lambda2 (multiwindow) */
 } dgtns_plan_info_t;
 
 /* Human-readable name of a status code (static storage). */
@@ -110,6 +118,25 @@ const char* dgtns_last_error(void);
  */
 int dgtns_plan_create(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1,
                       int64_t lambda2, int dtype, int64_t max_batch);
+
+/*
+ * Create a plan for a chosen algorithm (enum dgtns_algorithm).
+ * DGTNS_ALG_SHEAR is dgtns_plan_create.  DGTNS_ALG_MULTIWINDOW computes the
+ * same coefficients by the multiwindow decomposition (Section 3.1): the
+ * lattice is the union of lambda2 cosets of the separable lattice
+ * (lambda2 a, M) (Prop. 4), and with n = nt lambda2 + mu
+ *     c(m, n) = exp(-2 pi i nt lambda2 a sigma_mu / L) c_mu(m, nt),
+ * c_mu the separable DGT with window g_mu(l) = exp(2 pi i l sigma_mu / L)
+ * g(l - mu a), sigma_mu = (mu s) mod b (Prop. 5).  The lambda2 windows share
+ * one column transform of the signal.  Such a plan runs dgtns_forward,
+ * dgtns_forward_batch and dgtns_adjoint; dgtns_window_grad returns
+ * DGTNS_EUNSUPPORTED.  dgtns_plan_info reports branch DGTNS_MULTIWINDOW,
+ * s0 = s1 = 0, inner_a = lambda2 a, q per window and windows = lambda2; the
+ * persistent memory holds lambda2 window tables.  Errors as for
+ * dgtns_plan_create, plus DGTNS_EINVAL for an unknown algorithm.
+ */
+int dgtns_plan_create_alg(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1,
+                          int64_t lambda2, int dtype, int64_t max_batch, int algorithm);
 
 /* Fill *info (host only). */
 int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info);

@@ -23,6 +23,10 @@ DGTNS_C128 = 1
 DGTNS_SEPARABLE = 0
 DGTNS_TIME_SHEAR = 1
 DGTNS_FREQ_SHEAR = 2
+DGTNS_MULTIWINDOW = 3
+
+DGTNS_ALG_SHEAR = 0
+DGTNS_ALG_MULTIWINDOW = 1
 
 DGTNS_OP_FORWARD = 0
 DGTNS_OP_ADJOINT = 1
@@ -40,7 +44,7 @@ class dgtns_plan_info_t(ctypes.Structure):
         ("b", c_i64), ("N", c_i64), ("s", c_i64), ("s0", c_i64), ("s1", c_i64), ("b_r", c_i64),
         ("branch", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("inner_a", c_i64), ("inner_M", c_i64), ("c", c_i64), ("d", c_i64), ("p", c_i64), ("q", c_i64),
-        ("max_batch", c_i64), ("persistent_bytes", ctypes.c_size_t),
+        ("max_batch", c_i64), ("persistent_bytes", ctypes.c_size_t), ("windows", c_i64),
     ]
 
 
@@ -60,6 +64,8 @@ SIGNATURES = [
     ("dgtns_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("dgtns_last_error", ctypes.c_char_p, []),
     ("dgtns_plan_create", ctypes.c_int, [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64]),
+    ("dgtns_plan_create_alg", ctypes.c_int,
+     [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64, ctypes.c_int]),
     ("dgtns_plan_info", ctypes.c_int, [c_vp, ctypes.POINTER(dgtns_plan_info_t)]),
     ("dgtns_plan_bind", ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_workspace_bytes", ctypes.c_int, [c_vp, ctypes.c_int, c_i64, ctypes.POINTER(ctypes.c_size_t)]),
@@ -110,6 +116,12 @@ def _call(name, *args):
 def dgtns_plan_create(L, a, M, lambda1, lambda2, dtype, max_batch):
     h = c_vp()
     _call("dgtns_plan_create", ctypes.byref(h), L, a, M, lambda1, lambda2, dtype, max_batch)
+    return h
+
+
+def dgtns_plan_create_alg(L, a, M, lambda1, lambda2, dtype, max_batch, algorithm):
+    h = c_vp()
+    _call("dgtns_plan_create_alg", ctypes.byref(h), L, a, M, lambda1, lambda2, dtype, max_batch, algorithm)
     return h
 
 

@@ -23,20 +23,31 @@ def _stream_handle(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
+_ALG = {"shear": B.DGTNS_ALG_SHEAR, "multiwindow": B.DGTNS_ALG_MULTIWINDOW}
+
+
 class Plan:
-    """A lattice plan with its tables and window resident in device memory."""
+    """A lattice plan with its tables and window resident in device memory.
+
+    algorithm: "shear" (Alg. 1) or "multiwindow" (lambda2 coset windows on the
+    separable lattice (lambda2 a, M), Prop. 4 and Prop. 5); both compute the
+    same coefficients.  Window gradients need a shear plan."""
 
     def __init__(self, L: int, a: int, M: int, lam1: int = 0, lam2: int = 1,
-                 dtype: torch.dtype = torch.complex64, max_batch: int = 64, device=None):
+                 dtype: torch.dtype = torch.complex64, max_batch: int = 64, device=None,
+                 algorithm: str = "shear"):
         if dtype not in _DT:
             raise ValueError("dtype must be torch.complex64 or torch.complex128")
+        if algorithm not in _ALG:
+            raise ValueError("algorithm must be 'shear' or 'multiwindow'")
         if not torch.cuda.is_available():
             raise RuntimeError("libdgtns needs a HIP device")
         self.device = torch.device(device if device is not None else "cuda")
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.dtype = dtype
-        self._h = B.dgtns_plan_create(L, a, M, lam1, lam2, _DT[dtype], max_batch)
+        self.algorithm = algorithm
+        self._h = B.dgtns_plan_create_alg(L, a, M, lam1, lam2, _DT[dtype], max_batch, _ALG[algorithm])
         self.info = B.dgtns_plan_info(self._h)
         self.L, self.a, self.M, self.lam1, self.lam2 = L, a, M, lam1, lam2
         self.N = self.info.N

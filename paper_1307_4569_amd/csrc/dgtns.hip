@@ -126,12 +126,17 @@ const char* dgtns_last_error(void) { return g_err.c_str(); }
 
 int dgtns_plan_create(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
                       int dtype, int64_t max_batch) {
+  return dgtns_plan_create_alg(plan, L, a, M, lambda1, lambda2, dtype, max_batch, DGTNS_ALG_SHEAR);
+}
+
+int dgtns_plan_create_alg(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
+                          int dtype, int64_t max_batch, int algorithm) {
   if (!plan) return fail(DGTNS_EINVAL, "null plan pointer");
   if (max_batch > 65535) return fail(DGTNS_EINVAL, "max_batch above 65535");
   dgtns_plan_s* h = new (std::nothrow) dgtns_plan_s();
   if (!h) return fail(DGTNS_EINVAL, "out of host memory");
   std::string err;
-  int rc = plan_make(L, a, M, lambda1, lambda2, dtype, max_batch, &h->p, &err);
+  int rc = plan_make(L, a, M, lambda1, lambda2, dtype, max_batch, algorithm, &h->p, &err);
   if (rc) {
     delete h;
     return fail(rc, err);
@@ -147,7 +152,8 @@ int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info) {
   info->b = P.b; info->N = P.N; info->s = P.s;
   info->s0 = P.sh.s0; info->s1 = P.sh.s1; info->b_r = P.sh.br;
   info->branch = P.branch; info->dtype = P.dtype;
-  info->inner_a = P.ai; info->inner_M = P.Mi; info->c = P.ci; info->d = P.di; info->p = P.pi; info->q = P.qi;
+  info->inner_a = P.ai; info->inner_M = P.Mi; info->c = P.ci; info->d = P.di; info->p = P.pi; info->q = P.qw;
+  info->windows = P.nw;
   info->max_batch = P.max_batch;
   info->persistent_bytes = P.off.total;
   return DGTNS_OK;
@@ -342,7 +348,7 @@ int dgtns_shearfind(int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t la
   if (!out) return fail(DGTNS_EINVAL, "null output");
   Plan P;
   std::string err;
-  int rc = plan_make(L, a, M, lambda1, lambda2, 0, 1, &P, &err);
+  int rc = plan_make(L, a, M, lambda1, lambda2, 0, 1, kAlgShear, &P, &err);
   if (rc && rc != DGTNS_EUNSUPPORTED) return fail(rc, err);
   if (rc == DGTNS_EUNSUPPORTED) {
     // sizes the kernels do not cover still have a well-defined factorisation

@@ -104,14 +104,35 @@ template <typename C> struct ColArgs {
   int list;                    // 1: signal k at xl[k] instead of x + k xs
   const void* xl[kListMax];
   ChirpSrc<C> chirp;
-  const C* zc;
+  const C* zc;                 // window tables: nw of zs values each
   C* H;
   long long hs;
   const C* twd;
   int Mi, ai, d, p, q, W, Sd;
+  int qw;                      // time offsets per window (q = nw qw)
+  long long zs;
   int nsplit;                  // wave kernel: work-groups sharing one column block (split of Z_q)
   FftSched fd;
 };
+
+// Offset n0 in Z_q of the factorisation: window mu = n0 / qw (its table at
+// zc + mu zs) and time offset n0 mod qw of that window's separable lattice.
+// The shear algorithm has one window (qw = q).
+template <typename C>
+__device__ __forceinline__ const C* window_of(const C* zc, long long zs, int qw, int n0, int* n0w) {
+  const int mu = n0 / qw;
+  *n0w = n0 - mu * qw;
+  return zc + mu * zs;
+}
+
+// Time position of intermediate row (n0, t'): n0 + q t' for the shear
+// algorithm (qw = q, nw = 1); for the multiwindow algorithm (Prop. 5) the
+// separable lattice of window mu = n0 / qw has position nt = n0 mod qw + qw t',
+// which is coefficient column nt nw + mu.
+__device__ __forceinline__ int row_time(int n0, int t, int qw, int nw) {
+  const int mu = n0 / qw;
+  return (n0 - mu * qw + qw * t) * nw + mu;
+}
 
 template <typename C, bool GENP>
 __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
@@ -152,6 +173,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
     }
   }
   for (int n0 = 0; n0 < A.q; ++n0) {
+    int n0w;
+    const C* zc = window_of(A.zc, A.zs, A.qw, n0, &n0w);
     __syncthreads();
     if (!GENP) {
 #pragma unroll
@@ -161,12 +184,12 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
           const int cc = e / d, nu = e - cc * d, r = r0 + cc;
           C y = czero<C>();
           if (r < Mi) {
-            const int v = r - n0 * A.ai;
+            const int v = r - n0w * A.ai;
             C z;
             if (v >= 0) {
-              z = A.zc[(long long)v * d + nu];
+              z = zc[(long long)v * d + nu];
             } else {
-              z = cmulc(A.zc[(long long)(v + Mi) * d + nu], tw[nu]);
+              z = cmulc(zc[(long long)(v + Mi) * d + nu], tw[nu]);
             }
             y = cmul(X[i], z);
           }
@@ -179,7 +202,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
         C y = czero<C>();
         if (r < Mi) {
           for (int j0 = 0; j0 < p; ++j0)
-            y = cadd(y, cmul(xb[(cc * p + j0) * Sd + nu], zc_coef(A.zc, tw, r, n0, j0, nu, A.ai, Mi, p, d)));
+            y = cadd(y, cmul(xb[(cc * p + j0) * Sd + nu], zc_coef(zc, tw, r, n0w, j0, nu, A.ai, Mi, p, d)));
         }
         yb[cc * Sd + nu] = y;
       }
@@ -208,6 +231,8 @@ template <typename C> struct ColAdjArgs {
   C* y;
   long long ys;
   int Mi, ai, d, p, q, W, Sd;
+  int qw;                      // time offsets per window (q = nw qw), tables zs apart
+  long long zs;
   FftSched fd;
 };
 
@@ -236,6 +261,8 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
     }
     __syncthreads();
     fft_lds<C, false>(yb, Sd, A.fd, W, tw);
+    int n0w;
+    const C* zc = window_of(A.zc, A.zs, A.qw, n0, &n0w);
     if (!GENP) {
 #pragma unroll
       for (int i = 0; i < KX; ++i) {
@@ -243,12 +270,12 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
         if (e < WD) {
           const int cc = e / d, nu = e - cc * d, r = r0 + cc;
           if (r < Mi) {
-            const int v = r - n0 * A.ai;
+            const int v = r - n0w * A.ai;
             C z;
             if (v >= 0) {
-              z = A.zc[(long long)v * d + nu];
+              z = zc[(long long)v * d + nu];
             } else {
-              z = cmulc(A.zc[(long long)(v + Mi) * d + nu], tw[nu]);
+              z = cmulc(zc[(long long)(v + Mi) * d + nu], tw[nu]);
             }
             acc[i] = cadd(acc[i], cmulc(yb[cc * Sd + nu], z));
           }
@@ -261,7 +288,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
           const C yv = yb[cc * Sd + nu];
           for (int j0 = 0; j0 < p; ++j0) {
             C& a = xb[(cc * p + j0) * Sd + nu];
-            a = cadd(a, cmulc(yv, zc_coef(A.zc, tw, r, n0, j0, nu, A.ai, Mi, p, d)));
+            a = cadd(a, cmulc(yv, zc_coef(zc, tw, r, n0w, j0, nu, A.ai, Mi, p, d)));
           }
         }
       }
@@ -317,6 +344,7 @@ template <typename C> struct RowArgs {
   int list;                    // forward: coefficients of signal k at cl[k] instead of c + k cs
   C* cl[kListMax];
   int Mi, Ni, R, Sm, q, d;
+  int qw, nw;                  // time offsets per window, windows (row_time)
   FftSched fm;
   long long N, L, b, M, K1, K2, K3, K4, K5, C1n, C2n, Kt1, Kt6;
 };
@@ -357,7 +385,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows(RowArgs<C> A) {
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
     const int row = e / Mi, mo = e - row * Mi;
     if (t0 + row >= d) continue;
-    const int n = n0 + q * (t0 + row);
+    const int n = row_time(n0, t0 + row, A.qw, A.nw);
     if (MODE == 0) {
       int mi = mo - A.rho[n];
       if (mi < 0) mi += Mi;
@@ -383,9 +411,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows(RowArgs<C> A) {
   const long long bo = blockIdx.y;
   const C* cb = A.c + bo * A.cs;
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
-    const int row = e / Mi, m = e - row * Mi, n = n0 + q * (t0 + row);
+    const int row = e / Mi, m = e - row * Mi;
     C v = czero<C>();
     if (t0 + row < d) {
+      const int n = row_time(n0, t0 + row, A.qw, A.nw);
       if (MODE == 0) {
         int mo = m + A.rho[n];
         if (mo >= Mi) mo -= Mi;
@@ -506,6 +535,9 @@ __global__ void __launch_bounds__(kThreads) k_row_fft(RowFftArgs<C> A) {
 template <typename CO> struct ZakArgs {
   const double2* x;
   ChirpSrc<double2> chirp;
+  // source sample l is exp(pi i (mod2 l mod 2L) / L) x[(l - shift) mod L]
+  // (coset window of the multiwindow algorithm; shift = mod2 = 0 otherwise)
+  long long L, shift, mod2;
   CO* zc;
   double2* z64;
   const double2* twd;
@@ -528,7 +560,15 @@ __global__ void __launch_bounds__(kThreads) k_zak_fwd(ZakArgs<CO> A) {
     double2 v = make_double2(0, 0);
     if (r < Mi) {
       const long long l = r + (long long)j * Mi;
-      v = apply_chirp(A.chirp, A.x[l], l);
+      if (A.shift == 0 && A.mod2 == 0) {
+        v = apply_chirp(A.chirp, A.x[l], l);
+      } else {
+        long long ls = l - A.shift;
+        if (ls < 0) ls += A.L;
+        const long long e = (long long)(((unsigned long long)A.mod2 * (unsigned long long)l) %
+                                        (unsigned long long)(2 * A.L));
+        v = cmul(A.x[ls], phase_pi(e, A.L, 0.0));
+      }
     }
     xb[(cc * p + j % p) * Sd + j / p] = v;
   }

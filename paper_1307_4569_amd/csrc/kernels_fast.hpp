@@ -99,13 +99,15 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
   for (int k = 0; k < K; ++k) wave_fft<C, D, false>(X[k], ex, l, tw);
   const C* tw_d = A.twd;
   for (int n0 = n0_begin; n0 < n0_end; ++n0) {
+    int n0w;
+    const C* zc = window_of(A.zc, A.zs, A.qw, n0, &n0w);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int r = r0 + (wave * K + k) * I::TPW + tt;
       const bool ok = r < Mi;
-      const int v0 = r - n0 * A.ai;
+      const int v0 = r - n0w * A.ai;
       const int u = v0 >= 0 ? v0 : v0 + Mi;
-      const C* zrow = A.zc + (long long)(ok ? u : 0) * D;
+      const C* zrow = zc + (long long)(ok ? u : 0) * D;
       C Y[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -147,6 +149,8 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols_w(ColAdjArgs<C> A) {
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[k][e] = czero<C>();
   for (int n0 = 0; n0 < A.q; ++n0) {
+    int n0w;
+    const C* zc = window_of(A.zc, A.zs, A.qw, n0, &n0w);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int r = r0 + (wave * K + k) * I::TPW + tt;
@@ -156,9 +160,9 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols_w(ColAdjArgs<C> A) {
 #pragma unroll
       for (int e = 0; e < E; ++e) Y[e] = hb[l + T * e];
       wave_fft<C, D, false>(Y, ex, l, tw);
-      const int v0 = r - n0 * A.ai;
+      const int v0 = r - n0w * A.ai;
       const int u = v0 >= 0 ? v0 : v0 + Mi;
-      const C* zrow = A.zc + (long long)(ok ? u : 0) * D;
+      const C* zrow = zc + (long long)(ok ? u : 0) * D;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int nu = l + T * e;
@@ -188,8 +192,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols_w(ColAdjArgs<C> A) {
 }
 
 // ----------------------------------------------------------------------------
-// Row kernels, compile-time Mi = MI.  A work-group handles the RB time
-// positions n = n0 + q (t0 + i), i in Z_RB, with n0 = blockIdx.x mod q.
+// Row kernels, compile-time Mi = MI.  A work-group handles the RB
+// intermediate rows (n0, t0 + i), i in Z_RB, n0 = blockIdx.x mod q, whose
+// time positions are n = row_time(n0, t0 + i) (n0 + q (t0 + i) for the shear
+// algorithm).
 // grid (q * ceil(d / RB), B), 512 threads.
 // ----------------------------------------------------------------------------
 template <typename C, int MI, int MODE>
@@ -225,7 +231,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   for (int k = 0; k < K; ++k) {
     wave_fft<C, MI, false>(v[k], ex, l, tw);
     const int i = (wave * K + k) * I::TPW + tt;
-    const int n = n0 + q * (t0 + i);
+    const int n = row_time(n0, t0 + i, A.qw, A.nw);
     if (t0 + i >= d) {
       // time position beyond d in the last work-group: nothing to store
     } else if (MODE == 0) {
@@ -272,7 +278,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
   for (int k = 0; k < K; ++k) {
     const int i = (wave * K + k) * I::TPW + tt;
     const bool ok = t0 + i < d;
-    const int n = n0 + q * (ok ? t0 + i : 0);
+    const int n = row_time(n0, ok ? t0 + i : 0, A.qw, A.nw);
     if (MODE == 0) {
       const C En = A.postE[n];
       const int rho = A.rho[n];

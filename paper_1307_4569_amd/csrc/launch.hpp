@@ -168,9 +168,13 @@ struct Layout {
   size_t H = 0, F = 0, Y = 0, part = 0, G = 0, total = 0;
 };
 
+// Values of the intermediate h per signal: q offsets x Mi columns x d
+// (= Mi Ni for the shear algorithm, nw Mi Ni for nw coset windows).
+inline long long h_per_signal(const Plan& P) { return P.qi * P.Mi * P.di; }
+
 inline Layout ws_layout(const Plan& P, int op, long long B) {
   const size_t es = P.dtype == 0 ? 8 : 16;
-  const size_t MN = size_t(P.Mi) * size_t(P.Ni);
+  const size_t MN = size_t(h_per_signal(P));
   const size_t L = size_t(P.L);
   Layout l;
   size_t o = 0;
@@ -260,9 +264,10 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
     for (long long k = 0; k < B; ++k) A.xl[k] = xlist[k];
   }
   A.zc = tab<C>(P, P.off.zc);
-  A.H = H; A.hs = (long long)P.Mi * P.Ni;
+  A.H = H; A.hs = h_per_signal(P);
   A.twd = tab<C>(P, P.off.tw_d);
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.p = int(P.pi); A.q = int(P.qi);
+  A.qw = int(P.qw); A.zs = P.L;
   A.W = P.W; A.Sd = int(P.di | 1); A.fd = sched(P.fd);
   A.nsplit = 1;
   const size_t es = sizeof(C);
@@ -291,11 +296,12 @@ template <typename C>
 int run_adj_cols(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, hipStream_t st) {
   ColAdjArgs<C> A;
   std::memset(&A, 0, sizeof(A));
-  A.H = H; A.hs = (long long)P.Mi * P.Ni;
+  A.H = H; A.hs = h_per_signal(P);
   A.zc = tab<C>(P, P.off.zc);
   A.twd = tab<C>(P, P.off.tw_d);
   A.chirp = ch; A.y = y; A.ys = P.L;
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.p = int(P.pi); A.q = int(P.qi);
+  A.qw = int(P.qw); A.zs = P.L;
   A.W = P.W; A.Sd = int(P.di | 1); A.fd = sched(P.fd);
   const size_t es = sizeof(C);
   // adjoint wave kernels up to d = 512 (larger d would spill registers)
@@ -319,10 +325,11 @@ template <typename C>
 RowArgs<C> row_args(const Plan& P, const C* H, C* c) {
   RowArgs<C> A;
   std::memset(&A, 0, sizeof(A));
-  A.H = H; A.hs = (long long)P.Mi * P.Ni;
+  A.H = H; A.hs = h_per_signal(P);
   A.c = c; A.cs = (long long)P.M * P.N;
   A.twm = tab<C>(P, P.off.tw_m);
   A.Mi = int(P.Mi); A.Ni = int(P.Ni);
+  A.qw = int(P.qw); A.nw = int(P.nw);
   A.R = block_width(P.Mi | 1, sizeof(C));
   A.Sm = int(P.Mi | 1);
   A.fm = sched(P.fm);
@@ -489,6 +496,8 @@ int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const L
 template <typename C>
 int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* ws, const Layout& l,
               hipStream_t st) {
+  if (P.branch == kMultiwindow)
+    return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for shear-algorithm plans only");
   C* H = reinterpret_cast<C*>(ws + l.H);
   C* part = reinterpret_cast<C*>(ws + l.part);
   int rc = run_rows<C>(P, H, const_cast<C*>(gc), B, true, st);
@@ -508,7 +517,7 @@ int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* 
   }
   GradArgs<C> A;
   A.x = x; A.xs = P.L; A.real_in = 0; A.chirp = ch;
-  A.H = H; A.hs = (long long)P.Mi * P.Ni;
+  A.H = H; A.hs = h_per_signal(P);
   A.part = part; A.ps = P.L;
   A.twd = tab<C>(P, P.off.tw_d);
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.q = int(P.qi);
@@ -555,12 +564,26 @@ int window_zak(const Plan& P, const double2* g, CO* zc_out, double2* z64_out, ch
   }
   ZakArgs<CO> Z;
   Z.x = src; Z.chirp = ch; Z.zc = zc_out; Z.z64 = z64_out;
+  Z.L = P.L; Z.shift = 0; Z.mod2 = 0;
   Z.twd = tab<double2>(P, P.off.tw_d64);
   Z.Mi = int(P.Mi); Z.d = int(P.di); Z.p = int(P.pi); Z.Sd = int(P.di | 1);
   Z.W = block_width(P.pi * Z.Sd, 16);
   Z.fd = sched(P.fd);
   size_t lds = 16 * (P.di + size_t(Z.W) * P.pi * Z.Sd);
-  return launch(k_zak_fwd<CO>, dim3(cdiv(P.Mi, Z.W), 1), lds, st, Z, "window Zak transform");
+  // one table per window: the multiwindow algorithm's coset windows
+  // g_mu(l) = exp(2 pi i l sigma_mu / L) g(l - mu a) (Prop. 5), each L values
+  for (long long mu = 0; mu < P.nw; ++mu) {
+    ZakArgs<CO> Zm = Z;
+    if (P.branch == kMultiwindow) {
+      Zm.shift = mu * P.a;
+      Zm.mod2 = 2 * mw_sigma(P, mu) % (2 * P.L);
+      if (zc_out) Zm.zc = zc_out + mu * P.L;
+      if (z64_out) Zm.z64 = z64_out + mu * P.L;
+    }
+    int rc = launch(k_zak_fwd<CO>, dim3(cdiv(P.Mi, Z.W), 1), lds, st, Zm, "window Zak transform");
+    if (rc) return rc;
+  }
+  return DGTNS_OK;
 }
 
 

@@ -210,10 +210,14 @@ static void fill_chirp(int64_t L, int64_t s, std::vector<double>* v) {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int dtype,
-              int64_t max_batch, Plan* P, std::string* err) {
+              int64_t max_batch, int algorithm, Plan* P, std::string* err) {
   // status codes mirror include/dgtns.h
   const int kEInval = 1, kELattice = 2, kEUnsupported = 4;
   if (dtype != 0 && dtype != 1) { *err = "dtype must be DGTNS_C64 or DGTNS_C128"; return kEInval; }
+  if (algorithm != kAlgShear && algorithm != kAlgMultiwindow) {
+    *err = "algorithm must be DGTNS_ALG_SHEAR or DGTNS_ALG_MULTIWINDOW";
+    return kEInval;
+  }
   if (L < 1 || a < 1 || M < 1 || max_batch < 1) { *err = "L, a, M and max_batch must be positive"; return kEInval; }
   if (L > kMaxL) { *err = "L above 2^30 is not supported"; return kEUnsupported; }
   if (L % a || L % M) { *err = "a and M must divide L"; return kELattice; }
@@ -237,14 +241,23 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
     const char* gen = std::getenv("DGTNS_GENERIC");
     p.generic = gen && gen[0] == '1';
   }
-  p.sh = shearfind(L, a, M, p.s, p.b, err);
-  if (p.sh.br == 0) return kELattice;
-  if (p.s == 0) p.branch = kSeparable;
-  else if (p.sh.s0 == 0) p.branch = kTimeShear;
-  else p.branch = kFreqShear;
+  if (algorithm == kAlgMultiwindow) {
+    // Prop. 4: the lattice is the union of lambda2 cosets of the separable
+    // lattice (lambda2 a, M); no shear is used
+    p.branch = kMultiwindow;
+    p.sh.br = p.b;
+  } else {
+    p.sh = shearfind(L, a, M, p.s, p.b, err);
+    if (p.sh.br == 0) return kELattice;
+    if (p.s == 0) p.branch = kSeparable;
+    else if (p.sh.s0 == 0) p.branch = kTimeShear;
+    else p.branch = kFreqShear;
+  }
 
   const int64_t N = p.N, b = p.b;
-  if (p.branch != kFreqShear) {
+  if (p.branch == kMultiwindow) {
+    p.ai = lam2 * a; p.Mi = M;
+  } else if (p.branch != kFreqShear) {
     p.ai = a; p.Mi = M;
   } else {
     // Alg. 1, frequency-shear branch: separable DGT with time step b_r and
@@ -273,19 +286,21 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   }
   p.bi = L / p.Mi;
   p.Ni = L / p.ai;
+  p.ci = gcd64(p.ai, p.Mi);
+  p.pi = p.ai / p.ci;
+  p.qw = p.Mi / p.ci;
+  p.nw = p.branch == kMultiwindow ? lam2 : 1;
+  p.qi = p.nw * p.qw;
+  p.di = p.bi / p.pi;
   if (p.branch != kFreqShear) {
     // opt-in (DGTNS_CHUNK_MIB): chunks of about that many MiB of h, two in flight
-    const int64_t per_sig = p.Mi * p.Ni * (dtype == 0 ? 8 : 16);
+    const int64_t per_sig = p.qi * p.Mi * p.di * (dtype == 0 ? 8 : 16);
     const char* cm = std::getenv("DGTNS_CHUNK_MIB");
     if (cm && std::atoi(cm) > 0) {
       p.chunk = (int64_t(std::atoi(cm)) << 20) / per_sig;
       if (p.chunk < 1) p.chunk = 1;
     }
   }
-  p.ci = gcd64(p.ai, p.Mi);
-  p.pi = p.ai / p.ci;
-  p.qi = p.Mi / p.ci;
-  p.di = p.bi / p.pi;
 
   if (!fft_schedule(p.di, &p.fd) || !fft_schedule(p.Mi, &p.fm)) {
     *err = "transform lengths d = " + std::to_string(p.di) + " and M = " + std::to_string(p.Mi) +
@@ -330,8 +345,18 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   // ---- host tables (FP64) ----
   fill_twiddles(p.di, &p.tw_d);
   fill_twiddles(p.Mi, &p.tw_m);
-  if (p.branch != kSeparable) fill_chirp(L, p.sh.s1, &p.chirp1);
-  if (p.branch == kFreqShear) {
+  if (p.branch == kTimeShear || p.branch == kFreqShear) fill_chirp(L, p.sh.s1, &p.chirp1);
+  if (p.branch == kMultiwindow) {
+    // Prop. 5: c(m, nt lambda2 + mu) = exp(-2 pi i nt (lambda2 a) sigma_mu / L)
+    // c_mu(m, nt), c_mu the separable DGT of f with the coset window g_mu
+    p.post_E.resize(2 * N);
+    p.post_rho.assign(N, 0);
+    for (int64_t n = 0; n < N; ++n) {
+      const int64_t nt = n / lam2, mu = n % lam2;
+      const int64_t e = mulmod(mulmod(nt, p.ai, L), mw_sigma(p, mu), L);
+      unit_root(fmod64(-e, L), L, &p.post_E[2 * n], &p.post_E[2 * n + 1]);
+    }
+  } else if (p.branch == kFreqShear) {
     fill_twiddles(p.L1, &p.tw_1);
     fill_twiddles(p.L2, &p.tw_2);
     fill_twiddles(L, &p.tw_L);
@@ -370,7 +395,7 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   }
   p.off.post_E = p.post_E.empty() ? 0 : take(es * N);
   p.off.post_rho = p.post_rho.empty() ? 0 : take(4 * N);
-  p.off.zc = take(es * L);
+  p.off.zc = take(es * L * p.nw);   // one Zak table of L values per window
   if (dtype == 0) {
     p.off.tw_d64 = take(16 * p.di);
     p.off.tw_m64 = take(16 * p.Mi);

@@ -7,7 +7,9 @@
 //     constructive proof of Thm. 2 (choice of s1 from prime exponents,
 //     Bezout for k1, s0 from the exponents of k1, check of eq. (modcond)),
 //   * derives the separable lattice the factorised DGT runs on and the
-//     constants of Alg. 1 (C1 ... C6),
+//     constants of Alg. 1 (C1 ... C6), or, for the multiwindow algorithm
+//     (Prop. 4, Prop. 5), the separable lattice (lambda2 a, M) shared by the
+//     lambda2 coset windows,
 //   * builds the FFT radix schedules and all twiddle/chirp/phase tables in
 //     FP64 (rounded to FP32 for single-precision plans).
 #pragma once
@@ -50,7 +52,8 @@ int64_t lcm64(int64_t a, int64_t b);
 bool fft_schedule(int64_t n, FftSchedule* out);
 Shear shearfind(int64_t L, int64_t a, int64_t M, int64_t s, int64_t b, std::string* err);
 
-enum Branch { kSeparable = 0, kTimeShear = 1, kFreqShear = 2 };
+enum Branch { kSeparable = 0, kTimeShear = 1, kFreqShear = 2, kMultiwindow = 3 };
+enum Algorithm { kAlgShear = 0, kAlgMultiwindow = 1 };
 
 struct Plan {
   // lattice
@@ -59,8 +62,12 @@ struct Plan {
   int branch;
   int dtype;           // 0 = complex64, 1 = complex128
   int64_t max_batch;
-  // separable lattice the factorised DGT runs on (time step ai, channels Mi)
+  // separable lattice the factorised DGT runs on (time step ai, channels Mi).
+  // The factorisation runs over qi = nw * qw time offsets n0: nw windows with
+  // qw = Mi / ci offsets each (nw = 1 for the shear algorithm; nw = lambda2
+  // coset windows for the multiwindow algorithm, window mu = n0 / qw).
   int64_t ai, Mi, bi, Ni, ci, pi, qi, di;
+  int64_t qw = 0, nw = 1;
   // frequency-shear branch constants of Alg. 1 (reduced mod 2N or mod L)
   int64_t ar, Mr, Nr;
   int64_t K1, K2, K3, K4, K5;     // C1, C2, C3, C4, C5 mod 2N
@@ -92,7 +99,11 @@ struct Plan {
 
 // Returns 0 on success, else an error status with a message in *err.
 int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int dtype,
-              int64_t max_batch, Plan* p, std::string* err);
+              int64_t max_batch, int algorithm, Plan* p, std::string* err);
+
+// Coset window mu of the multiwindow algorithm: g_mu(l) = exp(2 pi i l sigma / L)
+// g(l - mu a) with sigma = (mu s) mod b (Prop. 5).
+inline int64_t mw_sigma(const Plan& p, int64_t mu) { return int64_t((__int128)mu * p.s % p.b); }
 
 // exp(2 pi i num / den), accurate to about one ulp (num reduced exactly first).
 void unit_root(int64_t num, int64_t den, double* re, double* im);

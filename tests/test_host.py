@@ -150,6 +150,33 @@ def test_workload_plans(lib):
     assert nfs == 6
 
 
+def test_multiwindow_plans(lib):
+    """Multiwindow plans (Prop. 4): no shear, the separable lattice
+    (lambda2 a, M) with its constants (eq. (cd), eq. (pq)) and lambda2 windows
+    whose lambda2 q d intermediate rows cover the N coefficient columns."""
+    n = 0
+    for (L, a, M, l1, l2) in feasible_lattices(max_L=120, max_lam2=4):
+        try:
+            h = B.dgtns_plan_create_alg(L, a, M, l1, l2, 0, 2, B.DGTNS_ALG_MULTIWINDOW)
+        except B.DgtnsError as e:
+            assert e.status == B.DGTNS_EUNSUPPORTED, (L, a, M, l1, l2)
+            continue
+        i = B.dgtns_plan_info(h)
+        B.dgtns_plan_destroy(h)
+        c = math.gcd(l2 * a, M)
+        assert i.branch == B.DGTNS_MULTIWINDOW and i.s0 == 0 and i.s1 == 0
+        assert (i.inner_a, i.inner_M, i.c, i.p, i.q, i.windows) == (l2 * a, M, c, l2 * a // c, M // c, l2)
+        assert i.d * i.p == L // M and i.windows * i.q * i.d == L // a
+        n += 1
+    assert n > 1000
+    with pytest.raises(B.DgtnsError) as e:
+        B.dgtns_plan_create_alg(144, 6, 12, 1, 2, 0, 1, 7)
+    assert e.value.status == B.DGTNS_EINVAL
+    h = B.dgtns_plan_create_alg(144, 6, 12, 1, 2, 0, 1, B.DGTNS_ALG_SHEAR)
+    assert B.dgtns_plan_info(h).branch == B.DGTNS_TIME_SHEAR and B.dgtns_plan_info(h).windows == 1
+    B.dgtns_plan_destroy(h)
+
+
 def test_error_paths_without_device(lib):
     with pytest.raises(B.DgtnsError) as e:
         B.dgtns_plan_create(100, 6, 12, 1, 2, 0, 1)
