@@ -77,6 +77,51 @@ def time_forward(plan, f, c, steps, warmup, torch, B_mod):
     return e0.elapsed_time(e1) / steps, wall / steps * 1e3, kt
 
 
+def crossover_bench(torch, dev, steps=5):
+    """Shear versus multiwindow algorithm as the lattice complexity lambda2
+    grows (the experiment of Section 4.4, Fig. 2): lambda = 1/lambda2,
+    lambda2 = 1..10, L = lcm(a, M) 2520 (the least length feasible for all of
+    them), (a, M) = (32, 64), (40, 60), (60, 80); FP32 forward on a batch of
+    about 2^22 samples, milliseconds per signal."""
+    import math
+
+    import numpy as np
+
+    from dgt_inputs import complex_normal_batch, gaussian_window
+    from paper_1307_4569_amd import Plan
+    from paper_1307_4569_amd import _binding as Bm
+    rows = []
+    for (a, M) in ((32, 64), (40, 60), (60, 80)):
+        L = a * M // math.gcd(a, M) * 2520
+        B = max(1, (1 << 22) // L)
+        f = torch.tensor(complex_normal_batch(B, L, 5).astype(np.complex64), device=dev)
+        g = torch.tensor(gaussian_window(L, a, M))
+        for lam2 in range(1, 11):
+            lam1 = 1 if lam2 > 1 else 0
+            row = {"a": a, "M": M, "L": L, "lambda": f"{lam1}/{lam2}", "batch": B}
+            for alg in ("shear", "multiwindow"):
+                try:
+                    plan = Plan(L, a, M, lam1, lam2, dtype=torch.complex64, max_batch=B, device=dev,
+                                algorithm=alg)
+                except Bm.DgtnsError as e:
+                    row[alg] = {"unsupported": str(e)}
+                    continue
+                plan.set_window(g)
+                c = torch.empty((B, L // a, M), dtype=torch.complex64, device=dev)
+                ms, _, _ = time_forward(plan, f, c, steps, 2, torch, Bm)
+                row[alg] = {"ms_per_signal": round(ms / B, 5), "branch": plan.info.branch, "p": plan.info.p,
+                            "q": plan.info.q, "d": plan.info.d}
+                del c, plan
+            if "ms_per_signal" in row.get("shear", {}) and "ms_per_signal" in row.get("multiwindow", {}):
+                row["faster"] = ("shear" if row["shear"]["ms_per_signal"] < row["multiwindow"]["ms_per_signal"]
+                                 else "multiwindow")
+            rows.append(row)
+            log(f"crossover a={a} M={M} lambda={lam1}/{lam2}: "
+                + ", ".join(f"{k} {v.get('ms_per_signal')}" for k, v in row.items() if isinstance(v, dict)))
+        del f
+    return rows
+
+
 def cpu_baseline(w, f_host, g_host, c_gpu_fn, budget_s=12.0):
     """Time the FP64 oracle (per-column fold form, single-threaded NumPy) on a
     bounded sample of the workload: whole signals of the batch, in order,
@@ -179,6 +224,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--no-multiwindow", action="store_true")
+    ap.add_argument("--no-crossover", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the FP32 forward loop (for rocprofv3)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -313,6 +360,24 @@ def main():
                        "fp32_speedup": ms64 / ms}
         del c64, f64d, plan64
         torch.cuda.synchronize()
+
+    if not args.no_multiwindow:
+        # the same workload by the multiwindow algorithm (Section 3.1)
+        log("fp32 forward timing, multiwindow algorithm")
+        pmw = Plan(w.L, w.a, w.M, w.lam1, w.lam2, dtype=torch.complex64, max_batch=w.batch, device=dev,
+                   algorithm="multiwindow")
+        pmw.set_window(torch.tensor(g32))
+        cmw = torch.empty_like(c)
+        msm, _, ktm = time_forward(pmw, f32, cmw, max(10, args.steps // 2), 3, torch, Bm)
+        out["multiwindow"] = {"ms_per_step": msm, "coeffs_per_s": coeffs / (msm * 1e-3),
+                              "vs_shear": ms / msm,
+                              "kernels": {k: {"launches_per_step": n / max(10, args.steps // 2),
+                                              "avg_ms": round(t / n, 4)} for k, (n, t) in ktm.items()}}
+        del cmw, pmw
+        torch.cuda.synchronize()
+    if not args.no_crossover:
+        log("shear versus multiwindow over lambda2")
+        out["crossover"] = crossover_bench(torch, dev)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
