@@ -19,8 +19,8 @@
  * Conventions for every call:
  *   - Complex data is interleaved (re, im).  DGTNS_C64 plans use float,
  *     DGTNS_C128 plans double, for signals, coefficients and windows given to
- *     the hot-path calls; windows given to dgtns_set_window and
- *     dgtns_dual_window are always complex128.
+ *     the hot-path calls; windows given to dgtns_set_window,
+ *     dgtns_dual_window and dgtns_tight_window are always complex128.
  *   - Signal layout f[B][L] (contiguous), coefficient layout c[B][N][M]:
  *     coefficient (m, n) of signal k at c[(k N + n) M + m] (channel fastest).
  *   - All pointers named *_dev are device pointers on the current HIP device.
@@ -210,11 +210,22 @@ int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, vo
  * optimal frame bounds (A, B); A == 0 means the system is not a frame and
  * gd_dev is then undefined (asynchronous calls cannot report
  * DGTNS_ENOTFRAME; callers check A).  Implemented for p = 1 of the sheared
- * lattice (DGTNS_EUNSUPPORTED otherwise).  Does not change the plan's window.
- * Workspace: DGTNS_OP_DUAL.
+ * lattice and for shear-algorithm plans (DGTNS_EUNSUPPORTED otherwise).
+ * Does not change the plan's window.  Workspace: DGTNS_OP_DUAL.
  */
 int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* bounds_dev,
                       void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Canonical tight window S^{-1/2} g (Section 4.2): the window whose Gabor
+ * system on the plan's lattice is a tight frame with bound 1, so that
+ * f = C*_{gt} C_{gt} f.  Same steps, arguments, bounds output, workspace
+ * (DGTNS_OP_DUAL) and restrictions as dgtns_dual_window, with the Zak-domain
+ * division by the square root of the frame operator's diagonal.
+ * gt_dev: complex128[L].
+ */
+int dgtns_tight_window(dgtns_plan plan, const void* g_dev, void* gt_dev, double* bounds_dev,
+                       void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Kernel timing for profiling and benchmarks.  While enabled (process-wide),

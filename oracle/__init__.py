@@ -15,7 +15,8 @@ Contents and the passages they follow:
   (eq. (mw_phases));
 * ``idgt_adjoint`` -- the synthesis operator, the adjoint of eq. (DGT);
 * ``dual.*`` -- frame operator eq. (frameop) in Walnut form, canonical dual
-  window S^{-1} g, frame bounds;
+  window S^{-1} g, canonical tight window S^{-1/2} g (Section 4.2), frame
+  bounds;
 * ``grad.*`` -- gradients of a spectrogram loss with respect to the signal and
   the window.
 
@@ -24,12 +25,13 @@ brute force, closed forms, library routines and invariants.
 """
 from .dgt import (coefficient_frequencies, dgt_direct, dgt_fold, dgt_multiwindow,
                   dgt_separable, idgt_adjoint, offsets)
-from .dual import dual_window, frame_blocks, frame_bounds, frame_operator_apply, walnut_weights
+from .dual import (dual_window, frame_blocks, frame_bounds, frame_operator_apply, tight_window,
+                   walnut_weights)
 from .grad import loss_and_grads, spectrogram_loss, window_gradient
 
 __all__ = [
     "coefficient_frequencies", "dgt_direct", "dgt_fold", "dgt_multiwindow", "dgt_separable",
     "idgt_adjoint", "offsets", "dual_window", "frame_blocks", "frame_bounds",
-    "frame_operator_apply", "walnut_weights", "loss_and_grads", "spectrogram_loss",
+    "frame_operator_apply", "tight_window", "walnut_weights", "loss_and_grads", "spectrogram_loss",
     "window_gradient",
 ]

@@ -13,7 +13,8 @@ couples samples that are a multiple of M apart (Walnut form):
 For every r in Z_M this is a b x b matrix acting on the samples
 f(r), f(r + M), ..., f(r + (b-1) M): S_r[i, i'] = W_{(i - i') mod b}(r + i M).
 The canonical dual window is S^{-1} g (Section 2.1), obtained here by one
-dense FP64 solve per block.
+dense FP64 solve per block, and the canonical tight window S^{-1/2} g
+(Section 4.2) by the inverse square root of each Hermitian block.
 """
 from __future__ import annotations
 
@@ -82,6 +83,25 @@ def dual_window(g, a, M, lam1, lam2):
     for r in range(M):
         gd[r + i * M] = np.linalg.solve(S[r], g[r + i * M])
     return gd
+
+
+def tight_window(g, a, M, lam1, lam2):
+    """Canonical tight window S^{-1/2} g: each Walnut block is Hermitian
+    positive definite for a frame, S_r = V diag(ev) V^H, and its inverse
+    square root is V diag(ev^{-1/2}) V^H.  Raises ValueError if a block is
+    singular (not a frame)."""
+    g = np.asarray(g, dtype=np.complex128)
+    L = g.shape[-1]
+    b = L // M
+    S = frame_blocks(g, a, M, lam1, lam2)
+    gt = np.empty(L, dtype=np.complex128)
+    i = np.arange(b)
+    for r in range(M):
+        ev, V = np.linalg.eigh(S[r])
+        if ev.min() <= 1e-14 * max(ev.max(), 1e-300):
+            raise ValueError("frame operator is singular: no tight window")
+        gt[r + i * M] = V @ ((V.conj().T @ g[r + i * M]) / np.sqrt(ev))
+    return gt
 
 
 def frame_bounds(g, a, M, lam1, lam2):

@@ -155,15 +155,22 @@ class Plan:
         B.dgtns_window_grad(self._h, f.data_ptr(), gc.data_ptr(), out.data_ptr(), nb, ws, wsb, st)
         return out
 
-    def dual(self, g: Optional[torch.Tensor] = None):
-        """Canonical dual window (complex128) and the frame bounds (A, B)."""
+    def _dual_or_tight(self, fn, g):
         g64 = (self.window if g is None else g).detach().to(device=self.device, dtype=torch.complex128).contiguous()
-        gd = torch.empty(self.L, dtype=torch.complex128, device=self.device)
+        out = torch.empty(self.L, dtype=torch.complex128, device=self.device)
         bounds = torch.empty(2, dtype=torch.float64, device=self.device)
         st = _stream_handle(self.device)
         ws, wsb = self.workspace(B.DGTNS_OP_DUAL, 1, st)
-        B.dgtns_dual_window(self._h, g64.data_ptr(), gd.data_ptr(), bounds.data_ptr(), ws, wsb, st)
-        return gd, bounds
+        fn(self._h, g64.data_ptr(), out.data_ptr(), bounds.data_ptr(), ws, wsb, st)
+        return out, bounds
+
+    def dual(self, g: Optional[torch.Tensor] = None):
+        """Canonical dual window S^{-1} g (complex128) and the frame bounds (A, B)."""
+        return self._dual_or_tight(B.dgtns_dual_window, g)
+
+    def tight(self, g: Optional[torch.Tensor] = None):
+        """Canonical tight window S^{-1/2} g (complex128) and the frame bounds (A, B)."""
+        return self._dual_or_tight(B.dgtns_tight_window, g)
 
 
 def dgt(f: torch.Tensor, plan: Plan) -> torch.Tensor:

@@ -276,17 +276,31 @@ int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, vo
   return grad_c128(P, f_dev, gc_dev, gg_dev, B, w, l, st);
 }
 
-int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* bounds_dev, void* ws,
-                      size_t ws_bytes, void* stream) {
+static int dual_or_tight(dgtns_plan plan, const void* g_dev, void* out_dev, double* bounds_dev, void* ws,
+                         size_t ws_bytes, void* stream, bool tight) {
   Layout l;
   int rc = check_call(plan, 1, ws, ws_bytes, DGTNS_OP_DUAL, &l);
   if (rc) return rc;
-  if (!g_dev || !gd_dev || !bounds_dev) return fail(DGTNS_EINVAL, "null argument");
+  if (!g_dev || !out_dev || !bounds_dev) return fail(DGTNS_EINVAL, "null argument");
   const Plan& P = plan->p;
-  if (P.pi != 1) return fail(DGTNS_EUNSUPPORTED, "dual window is implemented for p = 1 of the sheared lattice");
+  if (P.branch == kMultiwindow)
+    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are computed with shear-algorithm plans");
+  if (P.pi != 1)
+    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p = 1 of the sheared lattice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  return dual_c128(P, static_cast<const double2*>(g_dev), static_cast<double2*>(gd_dev), bounds_dev, w, l, st);
+  return dual_c128(P, static_cast<const double2*>(g_dev), static_cast<double2*>(out_dev), bounds_dev, w, l, tight,
+                   st);
+}
+
+int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* bounds_dev, void* ws,
+                      size_t ws_bytes, void* stream) {
+  return dual_or_tight(plan, g_dev, gd_dev, bounds_dev, ws, ws_bytes, stream, false);
+}
+
+int dgtns_tight_window(dgtns_plan plan, const void* g_dev, void* gt_dev, double* bounds_dev, void* ws,
+                       size_t ws_bytes, void* stream) {
+  return dual_or_tight(plan, g_dev, gt_dev, bounds_dev, ws, ws_bytes, stream, true);
 }
 
 int dgtns_timing_enable(int on) {

@@ -623,14 +623,15 @@ __global__ void __launch_bounds__(kThreads) k_zak_inv(ZakInvArgs A) {
 }
 
 // ----------------------------------------------------------------------------
-// Canonical dual in the Zak domain (p = 1): the frame operator of the
-// separable system is diagonal there with entries
+// Canonical dual and tight windows in the Zak domain (p = 1): the frame
+// operator of the separable system is diagonal there with entries
 //   D(u, nu) = Mi sum_{n0 in Z_q} |Zg_{(u - n0 ai) mod Mi}(nu)|^2,
-// so Zd = Zg / D.  Each block also writes its min and max of D.
+// so the dual S^{-1} g has Zak Zg / D and the tight window S^{-1/2} g has
+// Zak Zg / sqrt(D) (tight != 0).  Each block also writes its min and max of D.
 // ----------------------------------------------------------------------------
 template <int Unused = 0>
 __global__ void __launch_bounds__(kThreads) k_dual_div(const double2* z, double2* zd, double* part, int Mi, int d,
-                                                      int ai, int q, double scale_bounds) {
+                                                      int ai, int q, double scale_bounds, int tight) {
   __shared__ double smin[kThreads], smax[kThreads];
   const long long tot = (long long)Mi * d;
   const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
@@ -647,7 +648,8 @@ __global__ void __launch_bounds__(kThreads) k_dual_div(const double2* z, double2
     }
     D *= Mi;
     const double2 v = z[i];
-    zd[i] = D > 0 ? make_double2(v.x / D, v.y / D) : make_double2(0, 0);
+    const double den = tight ? sqrt(D) : D;
+    zd[i] = D > 0 ? make_double2(v.x / den, v.y / den) : make_double2(0, 0);
     mn = D * scale_bounds;
     mx = D * scale_bounds;
   }

@@ -591,8 +591,12 @@ int window_zak(const Plan& P, const double2* g, CO* zc_out, double2* z64_out, ch
 // Canonical dual window in FP64 (Alg. 2, with the time shear undone at the
 // end): Zak of the sheared window, division by the diagonal of the frame
 // operator (p = 1), inverse Zak, and for s0 != 0 the inverse frequency shear.
+// tight: the canonical tight window S^{-1/2} g by the same steps (Section
+// 4.2), dividing by the square root of the diagonal; with a frequency shear
+// the window transform scaled by 1/L is undone by sqrt(L) instead of L, as
+// S^{-1/2} of a positive multiple of a window is that of the window itself.
 inline int dual_impl(const Plan& P, const double2* g_dev, double2* gd_dev, double* bounds_dev, char* w,
-                     const Layout& l, hipStream_t st) {
+                     const Layout& l, hipStream_t st, bool tight = false) {
   int rc;
   double2* Z = reinterpret_cast<double2*>(w + l.H);
   double2* Zd = reinterpret_cast<double2*>(w + l.F);
@@ -609,7 +613,7 @@ inline int dual_impl(const Plan& P, const double2* g_dev, double2* gd_dev, doubl
   const unsigned nb = cdiv(tot, kThreads);
   const double sb = P.branch == kFreqShear ? double(P.L) : 1.0;
   rc = launch_raw(k_dual_div<>, dim3(nb), dim3(kThreads), 0, st, "dual division", Z, Zd, part, int(P.Mi),
-                  int(P.di), int(P.ai), int(P.qi), sb);
+                  int(P.di), int(P.ai), int(P.qi), sb, tight ? 1 : 0);
   if (rc) return rc;
   rc = launch_raw(k_minmax_final<>, dim3(1), dim3(kThreads), 0, st, "frame bounds", (const double*)part, int(nb),
                   bounds_dev);
@@ -633,7 +637,8 @@ inline int dual_impl(const Plan& P, const double2* g_dev, double2* gd_dev, doubl
   // g_d = conj(p1) IFFT(conj(p0) dual_sep(G))  (Alg. 2 with the time shear undone)
   double2* Y = reinterpret_cast<double2*>(w + l.Y);
   return run_four_step<double2>(P, Gd, 0, Y, gd_dev, 1, true, chirp_fly(P, -P.sh.s0, 1),
-                                chirp_fly(P, P.sh.s1, 1), 1.0 / double(P.L), nullptr,
+                                chirp_fly(P, P.sh.s1, 1), tight ? 1.0 / std::sqrt(double(P.L)) : 1.0 / double(P.L),
+                                nullptr,
                                 tab<double2>(P, P.off.tw_1_64), tab<double2>(P, P.off.tw_2_64), st);
 }
 
@@ -654,7 +659,7 @@ int grad_c128(const Plan& P, const void* f, const void* gc, void* gg, long long 
               hipStream_t st);
 int set_window_c64(const Plan& P, const double2* g, char* ws, const Layout& l, hipStream_t st);
 int set_window_c128(const Plan& P, const double2* g, char* ws, const Layout& l, hipStream_t st);
-int dual_c128(const Plan& P, const double2* g, double2* gd, double* bounds, char* ws, const Layout& l,
+int dual_c128(const Plan& P, const double2* g, double2* gd, double* bounds, char* ws, const Layout& l, bool tight,
               hipStream_t st);
 
 }  // namespace host

@@ -28,9 +28,9 @@ int set_window_c128(const Plan& P, const double2* g, char* ws, const Layout& l, 
   return window_zak<double2>(P, g, mtab<double2>(P, P.off.zc), nullptr, ws, l, st);
 }
 
-int dual_c128(const Plan& P, const double2* g, double2* gd, double* bounds, char* ws, const Layout& l,
+int dual_c128(const Plan& P, const double2* g, double2* gd, double* bounds, char* ws, const Layout& l, bool tight,
               hipStream_t st) {
-  return dual_impl(P, g, gd, bounds, ws, l, st);
+  return dual_impl(P, g, gd, bounds, ws, l, st, tight);
 }
 
 }  // namespace host

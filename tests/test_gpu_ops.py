@@ -70,8 +70,11 @@ def test_window_gradient_matches_oracle(dtype, kernel_path):
     assert {1, 2} <= seen
 
 
-@pytest.mark.parametrize("lat", [(144, 6, 12, 1, 2), (16, 4, 8, 1, 2), (2048, 16, 64, 1, 2), (4096, 32, 128, 1, 2),
-                                 (1152, 8, 64, 2, 3), (576, 4, 32, 0, 1), (240, 6, 12, 1, 2)])
+DUAL_LATTICES = [(144, 6, 12, 1, 2), (16, 4, 8, 1, 2), (2048, 16, 64, 1, 2), (4096, 32, 128, 1, 2),
+                 (1152, 8, 64, 2, 3), (576, 4, 32, 0, 1), (240, 6, 12, 1, 2)]
+
+
+@pytest.mark.parametrize("lat", DUAL_LATTICES)
 def test_dual_window_matches_oracle(lat):
     L, a, M, l1, l2 = lat
     plan = plan_for(lat, torch.complex64, 1)
@@ -89,6 +92,62 @@ def test_dual_window_matches_oracle(lat):
     pts = np.linspace(0, L - 1, 16).astype(np.int64)
     sg = oracle.frame_operator_apply(gd, g, a, M, l1, l2, pts)
     assert rel(sg, g[pts]) < 1e-11
+
+
+@pytest.mark.parametrize("lat", DUAL_LATTICES + [(24, 2, 6, 1, 4), (18, 3, 6, 2, 3)])
+def test_tight_window_matches_oracle(lat):
+    """Canonical tight window S^{-1/2} g (time shear, frequency shear and
+    separable plans): oracle values, the frame bounds, and tightness S_gt = I
+    at sampled points."""
+    L, a, M, l1, l2 = lat
+    plan = plan_for(lat, torch.complex64, 1)
+    g = gaussian_window(L, a, M) + 0.1j * complex_normal(L, 8)
+    gt, bounds = plan.tight(torch.tensor(g))
+    gt = gt.cpu().numpy()
+    A, Bb = bounds.cpu().numpy()
+    _, bounds_d = plan.dual(torch.tensor(g))
+    assert np.allclose(bounds.cpu().numpy(), bounds_d.cpu().numpy(), rtol=1e-12)
+    if L <= 2048:
+        ref = oracle.tight_window(g, a, M, l1, l2)
+        lo, hi = oracle.frame_bounds(g, a, M, l1, l2)
+        print("tight", lat, plan.branch, rel(gt, ref), (A, lo), (Bb, hi))
+        assert rel(gt, ref) < 1e-12
+        assert abs(A - lo) < 1e-10 * hi and abs(Bb - hi) < 1e-10 * hi
+    pts = np.linspace(0, L - 1, 16).astype(np.int64)
+    x = complex_normal(L, 9)
+    st = oracle.frame_operator_apply(x, gt, a, M, l1, l2, pts)
+    assert rel(st, x[pts]) < 1e-11
+
+
+def test_multiwindow_plans_refuse_dual_and_tight():
+    from paper_1307_4569_amd import Plan
+    from paper_1307_4569_amd import _binding as Bb
+    plan = Plan(144, 6, 12, 1, 2, dtype=torch.complex64, max_batch=1, algorithm="multiwindow")
+    g = torch.tensor(gaussian_window(144, 6, 12))
+    for fn in (plan.dual, plan.tight):
+        with pytest.raises(Bb.DgtnsError) as e:
+            fn(g)
+        assert e.value.status == Bb.DGTNS_EUNSUPPORTED
+
+
+def test_precision_workload_tight_and_reconstruction():
+    """FP64 tight windows of the Gaussian and the Hann window at L = 2^20,
+    lambda = 1/4: S_gt = I at sampled points, and f = C*_gt C_gt f through the
+    FP64 forward and adjoint transforms."""
+    w = PRECISION
+    lat = (w.L, w.a, w.M, w.lam1, w.lam2)
+    plan = plan_for(lat, torch.complex128, 2)
+    pts = np.linspace(0, w.L - 1, 12).astype(np.int64)
+    for name, g in (("gaussian", gaussian_window(w.L, w.a, w.M)), ("hann", hann_window(w.L, 2048))):
+        gt, bounds = plan.tight(torch.tensor(g))
+        x1 = complex_normal(w.L, 5)
+        e_s = rel(oracle.frame_operator_apply(x1, gt.cpu().numpy(), w.a, w.M, w.lam1, w.lam2, pts), x1[pts])
+        x = np.stack([chirp_mixture(w.L, 13074569 + 3000 + k) for k in range(2)])
+        plan.set_window(gt)
+        rec = plan.adjoint(plan.forward(torch.tensor(x))).cpu().numpy()
+        e_r = rel(rec, x)
+        print("precision tight", name, "bounds", bounds.cpu().numpy(), "S_gt err", e_s, "reconstruction err", e_r)
+        assert e_s < 1e-11 and e_r < 1e-12
 
 
 def test_precision_workload_dual_and_reconstruction():

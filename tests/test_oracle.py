@@ -214,6 +214,41 @@ def test_frame_operator_and_dual(lat):
     assert abs(np.vdot(c, c).real - np.vdot(f, S @ f).real) < 1e-11 * np.vdot(c, c).real
 
 
+@pytest.mark.parametrize("lat", SMALL_LATTICES)
+def test_tight_window(lat):
+    """Canonical tight window S^{-1/2} g: its Gabor system is a tight frame
+    with bound 1 (dense frame operator from brute-force atoms is the
+    identity), and it equals S^{-1/2} g computed from the dense L x L frame
+    operator (no Walnut blocks)."""
+    L, a, M, l1, l2 = lat
+    g = gaussian_window(L, a, M) + 0.2j * rand_c(L)
+    A = brute_force_atoms(g, L, a, M, l1, l2).reshape(L, -1)
+    S = A @ A.conj().T
+    ev, V = np.linalg.eigh(S)
+    if ev.min() < 1e-8 * ev.max():
+        with pytest.raises(ValueError):
+            oracle.tight_window(g, a, M, l1, l2)
+        return
+    gt = oracle.tight_window(g, a, M, l1, l2)
+    At = brute_force_atoms(gt, L, a, M, l1, l2).reshape(L, -1)
+    assert np.abs(At @ At.conj().T - np.eye(L)).max() < 1e-12
+    dense = V @ ((V.conj().T @ g) / np.sqrt(ev))
+    assert rel(gt, dense) < 1e-12
+    # painless reconstruction with the tight window alone
+    f = rand_c(L)
+    assert rel(oracle.idgt_adjoint(oracle.dgt_fold(f, gt, a, M, l1, l2), gt, a, M, l1, l2), f) < 1e-11
+
+
+def test_painless_tight_closed_form():
+    """Separable lattice, window supported in [0, M): S is diagonal with
+    entries M sum_n |g(l - n a)|^2, so the tight window is g / sqrt of it."""
+    L, a, M = 48, 4, 12
+    g = np.zeros(L, complex)
+    g[:M] = RNG.uniform(0.5, 1.5, M) + 0.3j * RNG.uniform(-1, 1, M)
+    diag = M * sum(np.abs(np.roll(g, n * a)) ** 2 for n in range(L // a))
+    assert rel(oracle.tight_window(g, a, M, 0, 1), g / np.sqrt(diag)) < 1e-13
+
+
 def test_painless_dual_closed_form():
     """Separable lattice and a window supported in [0, M): S is diagonal with
     entries M sum_n |g(l - n a)|^2, so the dual is g / that diagonal."""
