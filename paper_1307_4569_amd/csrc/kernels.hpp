@@ -60,6 +60,30 @@ template <typename C> __device__ __forceinline__ C apply_chirp(const ChirpSrc<C>
   return cmul_comp(v, p);
 }
 
+// Streaming (non-temporal) accesses for the intermediate h, which is read
+// once.  Stores stream only when the launch's h cannot stay in the 256 MB
+// last-level cache anyway (hstream): a smaller h is re-read from that cache by
+// the next kernel.  The element is moved as one native 2-vector.
+template <typename T> struct NVec;
+template <> struct NVec<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct NVec<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <typename C> __device__ __forceinline__ void st_stream(C* p, C v) {
+  using T = decltype(C::x);
+  typename NVec<T>::type w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<typename NVec<T>::type*>(p));
+}
+template <typename C> __device__ __forceinline__ void st_h(C* p, C v, int hstream) {
+  if (hstream)
+    st_stream(p, v);
+  else
+    *p = v;
+}
+template <typename C> __device__ __forceinline__ C ld_stream(const C* p) {
+  using T = decltype(C::x);
+  const typename NVec<T>::type w = __builtin_nontemporal_load(reinterpret_cast<const typename NVec<T>::type*>(p));
+  return mk<C>(w.x, w.y);
+}
+
 template <typename C> __device__ __forceinline__ C load_sig(const void* x, int real_in, long long idx) {
   using T = decltype(C::x);
   if (real_in) return mk<C>(reinterpret_cast<const T*>(x)[idx], T(0));
@@ -111,6 +135,7 @@ template <typename C> struct ColArgs {
   int Mi, ai, d, p, q, W, Sd;
   int qw;                      // time offsets per window (q = nw qw)
   long long zs;
+  int hstream;                 // stream the h stores (st_h)
   int nsplit;                  // wave kernel: work-groups sharing one column block (split of Z_q)
   FftSched fd;
 };
@@ -211,7 +236,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
     fft_lds<C, true>(yb, Sd, A.fd, W, tw);
     for (int e = threadIdx.x; e < WD; e += kThreads) {
       const int cc = e / d, t = e - cc * d, r = r0 + cc;
-      if (r < Mi) A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t] = yb[cc * Sd + t];
+      if (r < Mi) st_h(A.H + bo * A.hs + ((long long)n0 * Mi + r) * d + t, yb[cc * Sd + t], A.hstream);
     }
   }
 }
@@ -345,6 +370,7 @@ template <typename C> struct RowArgs {
   C* cl[kListMax];
   int Mi, Ni, R, Sm, q, d;
   int qw, nw;                  // time offsets per window, windows (row_time)
+  int hstream;                 // stream the stores: h (adjoint) or the coefficients (forward)
   FftSched fm;
   long long N, L, b, M, K1, K2, K3, K4, K5, C1n, C2n, Kt1, Kt6;
 };
@@ -389,13 +415,13 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows(RowArgs<C> A) {
     if (MODE == 0) {
       int mi = mo - A.rho[n];
       if (mi < 0) mi += Mi;
-      cb[(long long)n * Mi + mo] = cmul(A.postE[n], buf[row * Sm + mi]);
+      st_h(cb + (long long)n * Mi + mo, cmul(A.postE[n], buf[row * Sm + mi]), A.hstream);
     } else {
       const long long k = mo == 0 ? 0 : Mi - mo;
       long long dst;
       C E;
       shear_map(A, n, k, &dst, &E);
-      cb[dst] = cmul(E, buf[row * Sm + mo]);
+      st_h(cb + dst, cmul(E, buf[row * Sm + mo]), A.hstream);
     }
   }
 }
@@ -434,7 +460,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows(RowArgs<C> A) {
   C* Hb = const_cast<C*>(A.H) + bo * A.hs + (long long)n0 * Mi * d + t0;
   for (int e = threadIdx.x; e < R * Mi; e += kThreads) {
     const int m = e / R, i = e - m * R;
-    if (t0 + i < d) Hb[(long long)m * d + i] = buf[i * Sm + m];
+    if (t0 + i < d) st_h(Hb + (long long)m * d + i, buf[i * Sm + m], A.hstream);
   }
 }
 

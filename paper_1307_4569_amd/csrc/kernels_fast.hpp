@@ -56,7 +56,8 @@ template <typename C, int MI> struct FastRows {
 // column block each compute the column DFTs and a share of the q offsets n0
 // (more work-groups for small batches).
 // ----------------------------------------------------------------------------
-template <typename C, int D>
+// HS: streaming stores of h (chosen at launch from the size of h, stream_h).
+template <typename C, int D, bool HS>
 __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
   using F = FastCols<C, D>;
   using I = WInfo<D>;
@@ -120,7 +121,12 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
       if (ok) {
         C* hb = A.H + bo * A.hs + ((long long)n0 * Mi + r) * D;
 #pragma unroll
-        for (int e = 0; e < E; ++e) hb[l + T * e] = Y[e];
+        for (int e = 0; e < E; ++e) {
+          if constexpr (HS)
+            st_stream(hb + l + T * e, Y[e]);
+          else
+            hb[l + T * e] = Y[e];
+        }
       }
     }
   }
@@ -198,7 +204,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols_w(ColAdjArgs<C> A) {
 // algorithm).
 // grid (q * ceil(d / RB), B), 512 threads.
 // ----------------------------------------------------------------------------
-template <typename C, int MI, int MODE>
+// HS: streaming stores of the coefficients (a launch whose output cannot stay
+// in the last-level cache; otherwise its dirty lines are written back while
+// the next kernel runs).
+template <typename C, int MI, int MODE, bool HS>
 __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   using F = FastRows<C, MI>;
   using I = WInfo<MI>;
@@ -212,7 +221,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   const C* hb = A.H + bo * A.hs + (long long)n0 * MI * d + t0;
   for (int e = tid; e < RB * MI; e += kThreads) {
     const int m = e / RB, i = e - m * RB;
-    lds[F::fwd_at(m, i)] = t0 + i < d ? hb[(long long)m * d + i] : czero<C>();
+    lds[F::fwd_at(m, i)] = t0 + i < d ? ld_stream(hb + (long long)m * d + i) : czero<C>();
   }
   WTw<C, MI> tw;
   tw.load(A.twm, l);
@@ -242,7 +251,10 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
       for (int e = 0; e < E; ++e) {
         int mo = l + T * e + rho;
         if (mo >= MI) mo -= MI;
-        row[mo] = cmul(En, v[k][e]);
+        if constexpr (HS)
+          st_stream(row + mo, cmul(En, v[k][e]));
+        else
+          row[mo] = cmul(En, v[k][e]);
       }
     } else {
 #pragma unroll
@@ -252,13 +264,16 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
         long long dst;
         C Ev;
         shear_map(A, n, kk, &dst, &Ev);
-        cb[dst] = cmul(Ev, v[k][e]);
+        if constexpr (HS)
+          st_stream(cb + dst, cmul(Ev, v[k][e]));
+        else
+          cb[dst] = cmul(Ev, v[k][e]);
       }
     }
   }
 }
 
-template <typename C, int MI, int MODE>
+template <typename C, int MI, int MODE, bool HS>
 __global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
   using F = FastRows<C, MI>;
   using I = WInfo<MI>;
@@ -313,7 +328,12 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
   C* hb = const_cast<C*>(A.H) + bo * A.hs + (long long)n0 * MI * d + t0;
   for (int e = tid; e < RB * MI; e += kThreads) {
     const int m = e / RB, i = e - m * RB;
-    if (t0 + i < d) hb[(long long)m * d + i] = lds[m * SR + i];
+    if (t0 + i < d) {
+      if constexpr (HS)
+        st_stream(hb + (long long)m * d + i, lds[m * SR + i]);
+      else
+        hb[(long long)m * d + i] = lds[m * SR + i];
+    }
   }
 }
 

@@ -172,6 +172,17 @@ struct Layout {
 // (= Mi Ni for the shear algorithm, nw Mi Ni for nw coset windows).
 inline long long h_per_signal(const Plan& P) { return P.qi * P.Mi * P.di; }
 
+// Stream the stores of h when a launch's h (B signals) cannot stay in the
+// 256 MB last-level cache for the kernel that reads it next; the same for a
+// launch's coefficients (their dirty lines would otherwise be written back
+// while the next kernel runs).
+inline int stream_h(const Plan& P, long long B, size_t es) {
+  return double(h_per_signal(P)) * double(B) * double(es) >= double(256ll << 20) ? 1 : 0;
+}
+inline int stream_c(const Plan& P, long long B, size_t es) {
+  return double(P.M) * double(P.N) * double(B) * double(es) >= double(256ll << 20) ? 1 : 0;
+}
+
 inline Layout ws_layout(const Plan& P, int op, long long B) {
   const size_t es = P.dtype == 0 ? 8 : 16;
   const size_t MN = size_t(h_per_signal(P));
@@ -229,7 +240,8 @@ int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t s
   ColArgs<C> A2 = A;
   A2.nsplit = int(ns);
   dim3 grid(unsigned(nblk * ns), unsigned(B));
-  return launch(k_fwd_cols_w<C, D>, grid, sizeof(C) * F::LDS, st, A2, "factorisation kernel");
+  if (A2.hstream) return launch(k_fwd_cols_w<C, D, true>, grid, sizeof(C) * F::LDS, st, A2, "factorisation kernel");
+  return launch(k_fwd_cols_w<C, D, false>, grid, sizeof(C) * F::LDS, st, A2, "factorisation kernel");
 }
 
 template <typename C, int D>
@@ -246,11 +258,19 @@ int run_rows_fast(const Plan& P, const RowArgs<C>& A, long long B, bool adjoint,
   const size_t lds = sizeof(C) * F::LDS;
   const bool fs = P.branch == kFreqShear;
   if (!adjoint) {
-    if (fs) return launch(k_fwd_rows_w<C, MI, 1>, grid, lds, st, A, "channel DFT + shear post-processing");
-    return launch(k_fwd_rows_w<C, MI, 0>, grid, lds, st, A, "channel DFT + phase correction");
+    if (A.hstream) {
+      if (fs) return launch(k_fwd_rows_w<C, MI, 1, true>, grid, lds, st, A, "channel DFT + shear post-processing");
+      return launch(k_fwd_rows_w<C, MI, 0, true>, grid, lds, st, A, "channel DFT + phase correction");
+    }
+    if (fs) return launch(k_fwd_rows_w<C, MI, 1, false>, grid, lds, st, A, "channel DFT + shear post-processing");
+    return launch(k_fwd_rows_w<C, MI, 0, false>, grid, lds, st, A, "channel DFT + phase correction");
   }
-  if (fs) return launch(k_adj_rows_w<C, MI, 1>, grid, lds, st, A, "adjoint channel DFT (shear)");
-  return launch(k_adj_rows_w<C, MI, 0>, grid, lds, st, A, "adjoint channel DFT");
+  if (A.hstream) {
+    if (fs) return launch(k_adj_rows_w<C, MI, 1, true>, grid, lds, st, A, "adjoint channel DFT (shear)");
+    return launch(k_adj_rows_w<C, MI, 0, true>, grid, lds, st, A, "adjoint channel DFT");
+  }
+  if (fs) return launch(k_adj_rows_w<C, MI, 1, false>, grid, lds, st, A, "adjoint channel DFT (shear)");
+  return launch(k_adj_rows_w<C, MI, 0, false>, grid, lds, st, A, "adjoint channel DFT");
 }
 
 template <typename C>
@@ -268,6 +288,7 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
   A.twd = tab<C>(P, P.off.tw_d);
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.p = int(P.pi); A.q = int(P.qi);
   A.qw = int(P.qw); A.zs = P.L;
+  A.hstream = stream_h(P, B, sizeof(C));
   A.W = P.W; A.Sd = int(P.di | 1); A.fd = sched(P.fd);
   A.nsplit = 1;
   const size_t es = sizeof(C);
@@ -350,6 +371,8 @@ template <typename C>
 int run_rows(const Plan& P, const C* H, C* c, long long B, bool adjoint, hipStream_t st,
              void* const* clist = nullptr) {
   RowArgs<C> A = row_args<C>(P, H, c);
+  // the adjoint writes h, the forward the coefficients
+  A.hstream = adjoint ? stream_h(P, B, sizeof(C)) : stream_c(P, B, sizeof(C));
   if (clist) {
     A.list = 1;
     for (long long k = 0; k < B; ++k) A.cl[k] = static_cast<C*>(clist[k]);
