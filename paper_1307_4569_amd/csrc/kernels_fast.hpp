@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   const C* hb = A.H + bo * A.hs + (long long)n0 * MI * d + t0;
   for (int e = tid; e < RB * MI; e += kThreads) {
     const int m = e / RB, i = e - m * RB;
-    lds[F::fwd_at(m, i)] = t0 + i < d ? ld_stream(hb + (long long)m * d + i) : czero<C>();
+    lds[F::fwd_at(m, i)] = t0 + i < d ? hb[(long long)m * d + i] : czero<C>();
   }
   WTw<C, MI> tw;
   tw.load(A.twm, l);
