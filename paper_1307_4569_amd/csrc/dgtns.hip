@@ -177,6 +177,14 @@ int dgtns_plan_bind(dgtns_plan plan, void* dev, size_t bytes, void* stream) {
   const int dt = P.dtype;
   put_tab(img, P.off.tw_d, P.tw_d, dt);
   put_tab(img, P.off.tw_m, P.tw_m, dt);
+  if (P.longd) {
+    put_tab(img, P.off.tw_d1, P.tw_d1, dt);
+    put_tab(img, P.off.tw_d2, P.tw_d2, dt);
+    if (dt == 0) {
+      put_tab(img, P.off.tw_d1_64, P.tw_d1, 1);
+      put_tab(img, P.off.tw_d2_64, P.tw_d2, 1);
+    }
+  }
   if (P.off.chirp1) put_tab(img, P.off.chirp1, P.chirp1, dt);
   if (P.branch == kFreqShear) {
     put_tab(img, P.off.tw_1, P.tw_1, dt);
@@ -287,6 +295,8 @@ static int dual_or_tight(dgtns_plan plan, const void* g_dev, void* out_dev, doub
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are computed with shear-algorithm plans");
   if (P.pi != 1)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p = 1 of the sheared lattice");
+  if (P.longd)
+    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for columns of at most 4096 values");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   return dual_c128(P, static_cast<const double2*>(g_dev), static_cast<double2*>(out_dev), bounds_dev, w, l, tight,

@@ -13,6 +13,7 @@
 #include "../../include/dgtns.h"
 #include "kernels.hpp"
 #include "kernels_fast.hpp"
+#include "kernels_long.hpp"
 #include "plan.hpp"
 
 namespace dgtns {
@@ -165,7 +166,7 @@ inline int block_width(long long n, int es, int maxw = 16) {
 }
 
 struct Layout {
-  size_t H = 0, F = 0, Y = 0, part = 0, G = 0, total = 0;
+  size_t H = 0, F = 0, Y = 0, part = 0, G = 0, U = 0, V = 0, total = 0;
 };
 
 // Values of the intermediate h per signal: q offsets x Mi columns x d
@@ -200,6 +201,7 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
       } else {
         l.H = take(es * MN * B);
         if (fs) { l.F = take(es * L * B); l.Y = take(es * L * B); }
+        if (P.longd) { l.U = take(es * L * B); l.V = take(es * MN * B); }   // two-level column passes
       }
       break;
     case DGTNS_OP_WINDOW_GRAD:
@@ -209,6 +211,7 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
       break;
     case DGTNS_OP_SET_WINDOW:
       if (fs) { l.Y = take(16 * L); l.G = take(16 * L); }
+      if (P.longd) l.U = take(16 * L);
       break;
     case DGTNS_OP_DUAL:
       l.H = take(16 * L);   // Zak of the sheared window
@@ -273,9 +276,110 @@ int run_rows_fast(const Plan& P, const RowArgs<C>& A, long long B, bool adjoint,
   return launch(k_adj_rows_w<C, MI, 0, false>, grid, lds, st, A, "adjoint channel DFT");
 }
 
+// ---------------------------------------------------------------------------
+// Two-level column passes (kernels_long.hpp) for columns longer than one
+// in-LDS transform; U and V are workspace buffers of L and q Mi d values per
+// signal.
+// ---------------------------------------------------------------------------
+template <typename C>
+LongColArgs<C> long_col_args(const Plan& P) {
+  LongColArgs<C> A;
+  std::memset(&A, 0, sizeof(A));
+  A.pre.L = A.post.L = P.L;
+  A.tws = tab<C>(P, P.off.tw_d1);
+  A.twd = tab<C>(P, P.off.tw_d);
+  A.n = int(P.d1); A.Sn = int(P.d1 | 1); A.W = P.Wl;
+  A.d = int(P.di); A.d2 = int(P.d2);
+  A.fs = sched(P.fd1);
+  return A;
+}
+
+template <typename C>
+LongMidArgs<C> long_mid_args(const Plan& P, C* U, C* V) {
+  LongMidArgs<C> A;
+  std::memset(&A, 0, sizeof(A));
+  A.U = U; A.us = P.L; A.V = V; A.vs = h_per_signal(P);
+  A.zc = tab<C>(P, P.off.zc); A.zs = P.L;
+  A.twd = tab<C>(P, P.off.tw_d); A.tw2 = tab<C>(P, P.off.tw_d2);
+  A.Mi = int(P.Mi); A.ai = int(P.ai); A.p = int(P.pi); A.q = int(P.qi); A.qw = int(P.qw);
+  A.d = int(P.di); A.d1 = int(P.d1); A.d2 = int(P.d2); A.W = P.Wm; A.Sd2 = int(P.d2 | 1);
+  A.ncol = int(P.Mi * P.pi);
+  A.fs2 = sched(P.fd2);
+  return A;
+}
+
+template <typename C>
+int run_cols_long(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C> ch, C* H, long long B,
+                  hipStream_t st, const void* const* xlist, C* U, C* V) {
+  if (!U || !V) return fail(DGTNS_EINVAL, "internal: no workspace for the two-level column passes");
+  const long long ncol = P.Mi * P.pi, Md = P.Mi * P.di;
+  const size_t es = sizeof(C);
+  // 1: length-d1 DFTs of the signal with the chirp, twiddle W_d^{t2 k1}
+  LongColArgs<C> A = long_col_args<C>(P);
+  A.x = x; A.xs = xs; A.real_in = real_in; A.pre = ch;
+  if (xlist) {
+    A.list = 1;
+    for (long long k = 0; k < B; ++k) A.xl[k] = xlist[k];
+  }
+  A.y = U; A.ys = P.L;
+  A.ncols = int(P.d2 * ncol); A.inmode = 0; A.outmode = 0; A.twmode = 1; A.tdiv = int(ncol);
+  size_t lds = es * (P.d1 + size_t(A.W) * A.Sn);
+  int rc = launch(k_long_col<C, false>, dim3(cdiv(A.ncols, A.W), unsigned(B), 1), lds, st, A,
+                  "factorisation, first column pass");
+  if (rc) return rc;
+  // 2: length-d2 DFTs, window products, inverse length-d2 DFTs
+  LongMidArgs<C> M = long_mid_args<C>(P, U, V);
+  lds = es * (P.d2 + size_t(M.W) * (P.pi + 1) * M.Sd2);
+  rc = launch(k_long_mid<C>, dim3(unsigned(P.d1) * cdiv(P.Mi, M.W), unsigned(B)), lds, st, M,
+              "factorisation, middle pass");
+  if (rc) return rc;
+  // 3: inverse length-d1 DFTs into h[n0][r][t']
+  LongColArgs<C> A3 = long_col_args<C>(P);
+  A3.x = V; A3.xs = h_per_signal(P); A3.xz = Md;
+  A3.pre.K = 0;
+  A3.y = H; A3.ys = h_per_signal(P); A3.yz = Md;
+  A3.ncols = int(P.Mi * P.d2); A3.inmode = 0; A3.outmode = 1; A3.twmode = 0;
+  lds = es * (P.d1 + size_t(A3.W) * A3.Sn);
+  return launch(k_long_col<C, true>, dim3(cdiv(A3.ncols, A3.W), unsigned(B), unsigned(P.qi)), lds, st, A3,
+                "factorisation, last column pass");
+}
+
+template <typename C>
+int run_adj_cols_long(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, hipStream_t st, C* U, C* V) {
+  if (!U || !V) return fail(DGTNS_EINVAL, "internal: no workspace for the two-level column passes");
+  const long long ncol = P.Mi * P.pi, Md = P.Mi * P.di;
+  const size_t es = sizeof(C);
+  // 1: length-d1 DFTs over s1 of h, twiddle W_d^{s2 k1}
+  LongColArgs<C> A = long_col_args<C>(P);
+  A.x = H; A.xs = h_per_signal(P); A.xz = Md;
+  A.y = V; A.ys = h_per_signal(P); A.yz = Md;
+  A.ncols = int(P.Mi * P.d2); A.inmode = 1; A.outmode = 0; A.twmode = 2; A.tdiv = int(P.d2);
+  size_t lds = es * (P.d1 + size_t(A.W) * A.Sn);
+  int rc = launch(k_long_col<C, false>, dim3(cdiv(A.ncols, A.W), unsigned(B), unsigned(P.qi)), lds, st, A,
+                  "adjoint factorisation, first column pass");
+  if (rc) return rc;
+  // 2: per n0 length-d2 DFTs and conjugate window products, accumulated;
+  //    inverse length-d2 DFTs with twiddle
+  LongMidArgs<C> M = long_mid_args<C>(P, U, V);
+  lds = es * (P.d2 + size_t(M.W) * (P.pi + 1) * M.Sd2);
+  rc = launch(k_long_mid_adj<C>, dim3(unsigned(P.d1) * cdiv(P.Mi, M.W), unsigned(B)), lds, st, M,
+              "adjoint factorisation, middle pass");
+  if (rc) return rc;
+  // 3: inverse length-d1 DFTs into the signal with the conjugate chirp
+  LongColArgs<C> A3 = long_col_args<C>(P);
+  A3.x = U; A3.xs = P.L;
+  A3.post = ch;
+  A3.y = y; A3.ys = P.L;
+  A3.ncols = int(P.d2 * ncol); A3.inmode = 0; A3.outmode = 2; A3.twmode = 0;
+  lds = es * (P.d1 + size_t(A3.W) * A3.Sn);
+  return launch(k_long_col<C, true>, dim3(cdiv(A3.ncols, A3.W), unsigned(B), 1), lds, st, A3,
+                "adjoint factorisation, last column pass");
+}
+
 template <typename C>
 int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C> ch, C* H, long long B,
-             hipStream_t st, const void* const* xlist = nullptr) {
+             hipStream_t st, const void* const* xlist = nullptr, C* U = nullptr, C* V = nullptr) {
+  if (P.longd) return run_cols_long<C>(P, x, xs, real_in, ch, H, B, st, xlist, U, V);
   ColArgs<C> A;
   std::memset(&A, 0, sizeof(A));
   A.x = x; A.xs = xs; A.real_in = real_in; A.chirp = ch;
@@ -314,7 +418,9 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
 }
 
 template <typename C>
-int run_adj_cols(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, hipStream_t st) {
+int run_adj_cols(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, hipStream_t st, C* U = nullptr,
+                 C* V = nullptr) {
+  if (P.longd) return run_adj_cols_long<C>(P, H, ch, y, B, st, U, V);
   ColAdjArgs<C> A;
   std::memset(&A, 0, sizeof(A));
   A.H = H; A.hs = h_per_signal(P);
@@ -475,7 +581,8 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
         });
   }
   if (P.branch != kFreqShear) {
-    rc = run_cols<C>(P, f, P.L, real_in, chirp_tab<C>(P, P.off.chirp1, 0), H, B, st, flist);
+    rc = run_cols<C>(P, f, P.L, real_in, chirp_tab<C>(P, P.off.chirp1, 0), H, B, st, flist,
+                     reinterpret_cast<C*>(ws + l.U), reinterpret_cast<C*>(ws + l.V));
   } else {
     C* F = reinterpret_cast<C*>(ws + l.F);
     C* Y = reinterpret_cast<C*>(ws + l.Y);
@@ -483,7 +590,8 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
                           chirp_tab<C>(P, P.off.chirp0, 0), 1, tab<C>(P, P.off.tw_L), tab<C>(P, P.off.tw_1),
                           tab<C>(P, P.off.tw_2), st, flist);
     if (rc) return rc;
-    rc = run_cols<C>(P, F, P.L, 0, no_chirp<C>(P), H, B, st);
+    rc = run_cols<C>(P, F, P.L, 0, no_chirp<C>(P), H, B, st, nullptr, reinterpret_cast<C*>(ws + l.U),
+                     reinterpret_cast<C*>(ws + l.V));
   }
   if (rc) return rc;
   return run_rows<C>(P, H, c, B, false, st, clist);
@@ -506,10 +614,12 @@ int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const L
   }
   int rc = run_rows<C>(P, H, const_cast<C*>(c), B, true, st);
   if (rc) return rc;
-  if (P.branch != kFreqShear) return run_adj_cols<C>(P, H, chirp_tab<C>(P, P.off.chirp1, 1), f, B, st);
+  C* U = reinterpret_cast<C*>(ws + l.U);
+  C* V = reinterpret_cast<C*>(ws + l.V);
+  if (P.branch != kFreqShear) return run_adj_cols<C>(P, H, chirp_tab<C>(P, P.off.chirp1, 1), f, B, st, U, V);
   C* F = reinterpret_cast<C*>(ws + l.F);
   C* Y = reinterpret_cast<C*>(ws + l.Y);
-  rc = run_adj_cols<C>(P, H, no_chirp<C>(P), F, B, st);
+  rc = run_adj_cols<C>(P, H, no_chirp<C>(P), F, B, st, U, V);
   if (rc) return rc;
   return run_four_step<C>(P, F, 0, Y, f, B, true, chirp_tab<C>(P, P.off.chirp0, 1),
                           chirp_tab<C>(P, P.off.chirp1, 1), 1, tab<C>(P, P.off.tw_L), tab<C>(P, P.off.tw_1),
@@ -521,6 +631,8 @@ int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* 
               hipStream_t st) {
   if (P.branch == kMultiwindow)
     return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for shear-algorithm plans only");
+  if (P.longd)
+    return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for columns of at most 4096 values");
   C* H = reinterpret_cast<C*>(ws + l.H);
   C* part = reinterpret_cast<C*>(ws + l.part);
   int rc = run_rows<C>(P, H, const_cast<C*>(gc), B, true, st);
@@ -584,6 +696,38 @@ int window_zak(const Plan& P, const double2* g, CO* zc_out, double2* z64_out, ch
     if (rc) return rc;
     src = G;
     ch = no_chirp<double2>(P);
+  }
+  if (P.longd) {
+    // long columns: first column pass of the prepared window in FP64, then
+    // the length-d2 DFTs into the digit-reversed tables (one window: the
+    // planner refuses multiwindow plans with long columns)
+    double2* U = reinterpret_cast<double2*>(ws + l.U);
+    LongColArgs<double2> A;
+    std::memset(&A, 0, sizeof(A));
+    A.x = src; A.pre = ch; A.post.L = P.L;
+    A.y = U; A.ys = P.L;
+    A.tws = tab<double2>(P, P.off.tw_d1_64); A.twd = tab<double2>(P, P.off.tw_d64);
+    A.n = int(P.d1); A.Sn = int(P.d1 | 1); A.W = block_width(A.Sn, 16);
+    A.ncols = int(P.d2 * P.Mi * P.pi); A.inmode = 0; A.outmode = 0; A.twmode = 1; A.tdiv = int(P.Mi * P.pi);
+    A.d = int(P.di); A.d2 = int(P.d2); A.fs = sched(P.fd1);
+    int rc = launch(k_long_col<double2, false>, dim3(cdiv(A.ncols, A.W), 1, 1), 16 * (P.d1 + size_t(A.W) * A.Sn), st,
+                    A, "window Zak, first column pass");
+    if (rc) return rc;
+    const int S = int(P.d2 | 1);
+    int W = 16;
+    while (W > 1 && (W * P.pi * P.d2 > 4096 || 16 * (P.d2 + size_t(W) * P.pi * S) > (64u << 10))) --W;
+    const size_t zl = 16 * (P.d2 + size_t(W) * P.pi * S);
+    if (zl > 160 * 1024) return fail(DGTNS_EUNSUPPORTED, "window Zak: LDS request above 160 KiB");
+    if (zl > 64 * 1024) {
+      rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_long_zak<CO>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(zl)),
+                     "window Zak");
+      if (rc) return rc;
+    }
+    return launch_raw(k_long_zak<CO>, dim3(unsigned(P.d1) * cdiv(P.Mi, W)), dim3(kThreads),
+                      zl, st, "window Zak, middle pass", (const double2*)U, zc_out,
+                      z64_out, tab<double2>(P, P.off.tw_d2_64), int(P.Mi), int(P.pi), int(P.di), int(P.d1),
+                      int(P.d2), W, S, sched(P.fd2));
   }
   ZakArgs<CO> Z;
   Z.x = src; Z.chirp = ch; Z.zc = zc_out; Z.z64 = z64_out;

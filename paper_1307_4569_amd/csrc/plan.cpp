@@ -292,7 +292,7 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   p.nw = p.branch == kMultiwindow ? lam2 : 1;
   p.qi = p.nw * p.qw;
   p.di = p.bi / p.pi;
-  if (p.branch != kFreqShear) {
+  if (p.branch != kFreqShear && p.di <= kMaxFft) {
     // opt-in (DGTNS_CHUNK_MIB): chunks of about that many MiB of h, two in flight
     const int64_t per_sig = p.qi * p.Mi * p.di * (dtype == 0 ? 8 : 16);
     const char* cm = std::getenv("DGTNS_CHUNK_MIB");
@@ -302,20 +302,56 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
     }
   }
 
-  if (!fft_schedule(p.di, &p.fd) || !fft_schedule(p.Mi, &p.fm)) {
-    *err = "transform lengths d = " + std::to_string(p.di) + " and M = " + std::to_string(p.Mi) +
-           " must be 7-smooth and at most 4096";
-    return kEUnsupported;
-  }
   // LDS element budget per work-group: 8192 complex elements (FP32) or 4096 (FP64)
   const int64_t budget = dtype == 0 ? 8192 : 4096;
-  const int64_t Sd = p.di | 1;
-  int64_t W = 16;
-  while (W > 1 && (W * p.pi * p.di > budget || W * (p.pi * Sd + (p.pi > 1 ? Sd : 0)) > budget + 64 * W))
-    --W;
-  if (W * p.pi * p.di > budget) {
-    *err = "column length b = " + std::to_string(p.bi) + " exceeds the in-LDS limit";
+  if (!fft_schedule(p.Mi, &p.fm)) {
+    *err = "channel count M = " + std::to_string(p.Mi) + " must be 7-smooth and at most 4096";
     return kEUnsupported;
+  }
+  int64_t W = 1;
+  // one column's p sub-columns must fit one FP64 in-LDS transform call (4096
+  // values): the window's Zak transform runs in FP64 for every plan
+  if (fft_schedule(p.di, &p.fd) && p.pi * p.di <= 4096) {
+    const int64_t Sd = p.di | 1;
+    W = 16;
+    while (W > 1 && (W * p.pi * p.di > budget || W * (p.pi * Sd + (p.pi > 1 ? Sd : 0)) > budget + 64 * W))
+      --W;
+  } else {
+    // long columns: d = d1 d2, both 7-smooth in-LDS lengths, the middle pass
+    // holding p sub-columns of length d2 per column (p d2 <= 4096, the FP64
+    // capacity used by the window transform); the most balanced split
+    int64_t best = 0;
+    double bestq = 1e300;
+    for (int64_t a2 = 2; a2 <= kMaxFft && a2 <= p.di; ++a2) {
+      if (p.di % a2) continue;
+      const int64_t a1 = p.di / a2;
+      FftSchedule s1, s2;
+      if (a1 < 2 || a1 > kMaxFft || p.pi * a2 > 4096) continue;
+      if (!fft_schedule(a1, &s1) || !fft_schedule(a2, &s2)) continue;
+      const double qd = std::fabs(std::log(double(a1)) - std::log(double(a2)));
+      if (qd < bestq) { bestq = qd; best = a2; }
+    }
+    if (best == 0) {
+      *err = "column length d = " + std::to_string(p.di) + " (p = " + std::to_string(p.pi) +
+             ") has no split d1 d2 into 7-smooth in-LDS lengths";
+      return kEUnsupported;
+    }
+    if (p.branch == kMultiwindow) {
+      *err = "multiwindow plans need columns of at most 4096 values (d = " + std::to_string(p.di) + ")";
+      return kEUnsupported;
+    }
+    p.longd = true;
+    p.d2 = best;
+    p.d1 = p.di / best;
+    fft_schedule(p.d1, &p.fd1);
+    fft_schedule(p.d2, &p.fd2);
+    const int64_t es = dtype == 0 ? 8 : 16, S2 = p.d2 | 1;
+    int64_t wm = 16;
+    while (wm > 1 && (wm * p.pi * p.d2 > budget || es * (p.d2 + wm * (p.pi + 1) * S2) > (64 << 10))) --wm;
+    p.Wm = int(wm);
+    const int64_t wl = budget / (p.d1 | 1);
+    p.Wl = int(wl > 16 ? 16 : (wl < 1 ? 1 : wl));
+    p.chunk = 0;
   }
   if (p.Mi > budget) {
     *err = "channel count exceeds the in-LDS limit";
@@ -345,6 +381,10 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   // ---- host tables (FP64) ----
   fill_twiddles(p.di, &p.tw_d);
   fill_twiddles(p.Mi, &p.tw_m);
+  if (p.longd) {
+    fill_twiddles(p.d1, &p.tw_d1);
+    fill_twiddles(p.d2, &p.tw_d2);
+  }
   if (p.branch == kTimeShear || p.branch == kFreqShear) fill_chirp(L, p.sh.s1, &p.chirp1);
   if (p.branch == kMultiwindow) {
     // Prop. 5: c(m, nt lambda2 + mu) = exp(-2 pi i nt (lambda2 a) sigma_mu / L)
@@ -384,6 +424,13 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
   p.off.tw_d = take(es * p.di);
   p.off.tw_m = take(es * p.Mi);
+  p.off.tw_d1 = p.off.tw_d2 = p.off.tw_d1_64 = p.off.tw_d2_64 = 0;
+  if (p.longd) {
+    p.off.tw_d1 = take(es * p.d1);
+    p.off.tw_d2 = take(es * p.d2);
+    p.off.tw_d1_64 = dtype == 0 ? take(16 * p.d1) : p.off.tw_d1;
+    p.off.tw_d2_64 = dtype == 0 ? take(16 * p.d2) : p.off.tw_d2;
+  }
   p.off.chirp1 = p.chirp1.empty() ? 0 : take(es * L);
   p.off.tw_1 = p.off.tw_2 = p.off.tw_L = p.off.chirp0 = 0;
   p.off.tw_1_64 = p.off.tw_2_64 = p.off.tw_L64 = 0;

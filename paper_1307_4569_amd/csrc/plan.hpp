@@ -76,15 +76,23 @@ struct Plan {
   // FFT schedules
   FftSchedule fd, fm, f1, f2;     // length di, Mi, and L = L1 * L2 (freq shear)
   int64_t L1, L2;
+  // Columns longer than one in-LDS transform: d = d1 d2 (two-level column
+  // transforms); Wl columns per work-group of the length-d1 passes and Wm
+  // columns r per work-group of the middle pass.
+  bool longd = false;
+  int64_t d1 = 0, d2 = 0;
+  FftSchedule fd1, fd2;
+  int Wl = 1, Wm = 1;
   // column-block width of the factorisation kernels
   int W;
   // host tables (FP64, interleaved re/im); uploaded by bind
-  std::vector<double> tw_d, tw_m, tw_1, tw_2, tw_L, chirp1, chirp0, post_E;
+  std::vector<double> tw_d, tw_m, tw_1, tw_2, tw_L, chirp1, chirp0, post_E, tw_d1, tw_d2;
   std::vector<int32_t> post_rho;
   // device memory map (byte offsets into the persistent block)
   struct Off {
     size_t tw_d, tw_m, tw_1, tw_2, tw_L, chirp1, chirp0, post_E, post_rho, zc;   // plan dtype
     size_t tw_d64, tw_m64, tw_1_64, tw_2_64, tw_L64;                             // FP64 copies
+    size_t tw_d1, tw_d2, tw_d1_64, tw_d2_64;                                     // long columns
     size_t bounds;  // 2 doubles
     size_t total;
   } off;

@@ -177,6 +177,25 @@ def test_multiwindow_plans(lib):
     B.dgtns_plan_destroy(h)
 
 
+def test_long_column_plans(lib):
+    """Columns longer than one in-LDS transform plan as d = d1 d2 (every
+    branch, p = 1 and p = 3, the Fig. 2 lengths); a column length with a
+    prime factor above 7 is still refused."""
+    cases = [((20160, 2, 4, 0, 1), 0, 5040), ((20160, 3, 4, 1, 2), 1, 1680), ((20160, 3, 6, 1, 3), 2, 10080),
+             ((161280, 32, 64, 1, 2), 2, 20160), ((302400, 40, 60, 1, 4), 2, 5040), ((1 << 20, 32, 64, 1, 2), 1, 16384)]
+    for lat, branch, d in cases:
+        h = B.dgtns_plan_create(*lat, 0, 2)
+        i = B.dgtns_plan_info(h)
+        B.dgtns_plan_destroy(h)
+        assert (i.branch, i.d) == (branch, d), (lat, i.branch, i.d)
+    with pytest.raises(B.DgtnsError) as e:
+        B.dgtns_plan_create(4099 * 4, 2, 4, 0, 1, 0, 1)        # d = 4099 is prime
+    assert e.value.status == B.DGTNS_EUNSUPPORTED
+    with pytest.raises(B.DgtnsError) as e:                      # multiwindow plans keep d <= 4096
+        B.dgtns_plan_create_alg(20160, 2, 4, 1, 2, 0, 1, B.DGTNS_ALG_MULTIWINDOW)
+    assert e.value.status == B.DGTNS_EUNSUPPORTED
+
+
 def test_error_paths_without_device(lib):
     with pytest.raises(B.DgtnsError) as e:
         B.dgtns_plan_create(100, 6, 12, 1, 2, 0, 1)
