@@ -599,7 +599,9 @@ __global__ void __launch_bounds__(kThreads) k_zak_fwd(ZakArgs<CO> A) {
     xb[(cc * p + j % p) * Sd + j / p] = v;
   }
   __syncthreads();
-  fft_lds<double2, false>(xb, Sd, A.fd, W * p, tw);
+  // at most MaxE * kThreads values per transform call (4096 in FP64)
+  const int per = (MaxE<double2>::value * kThreads) / d;
+  for (int t0 = 0; t0 < W * p; t0 += per) fft_lds<double2, false>(xb + t0 * Sd, Sd, A.fd, min(per, W * p - t0), tw);
   const double inv_d = 1.0 / d;
   for (int e = threadIdx.x; e < W * b; e += kThreads) {
     const int cc = e / b, rem = e - cc * b, j0 = rem / d, nu = rem - j0 * d, r = r0 + cc;

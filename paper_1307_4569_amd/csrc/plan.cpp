@@ -309,9 +309,9 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
     return kEUnsupported;
   }
   int64_t W = 1;
-  // one column's p sub-columns must fit one FP64 in-LDS transform call (4096
-  // values): the window's Zak transform runs in FP64 for every plan
-  if (fft_schedule(p.di, &p.fd) && p.pi * p.di <= 4096) {
+  // in-LDS columns: the p sub-columns of a column within the element budget,
+  // and within the LDS of the FP64 window Zak transform (16 bytes per value)
+  if (fft_schedule(p.di, &p.fd) && p.pi * p.di <= budget && 16 * (p.di + p.pi * (p.di | 1)) <= (160 << 10)) {
     const int64_t Sd = p.di | 1;
     W = 16;
     while (W > 1 && (W * p.pi * p.di > budget || W * (p.pi * Sd + (p.pi > 1 ? Sd : 0)) > budget + 64 * W))
