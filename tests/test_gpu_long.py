@@ -2,7 +2,10 @@
 transform (d = d1 d2, two-level column transforms; Sec. 4 full-window
 algorithm): separable, time-shear and frequency-shear plans with p = 1 and
 p = 3, against the FP64 oracle, and the frequency-shear lattice of Fig. 2's
-first shape (L = 161280, a = 32, M = 64, lambda = 1/2, d = 20160)."""
+first shape (L = 161280, a = 32, M = 64, lambda = 1/2, d = 20160).  The p = 3
+lattices have p d = 5040: FP64 plans take the two-level path, FP32 plans the
+in-LDS one with the window's FP64 Zak transform split into calls of at most
+4096 values."""
 import numpy as np
 import pytest
 
