@@ -354,13 +354,20 @@ def main():
         plan.adjoint(c, out=fa)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    na = max(5, args.steps // 5)
+    Bm.dgtns_timing_reset()
+    Bm.dgtns_timing_enable(1)
     e0.record()
-    for _ in range(max(5, args.steps // 5)):
+    for _ in range(na):
         plan.adjoint(c, out=fa)
     e1.record()
     torch.cuda.synchronize()
-    ams = e0.elapsed_time(e1) / max(5, args.steps // 5)
-    out["adjoint"] = {"ms_per_step": ams, "coeffs_per_s": coeffs / (ams * 1e-3)}
+    Bm.dgtns_timing_enable(0)
+    akt = Bm.kernel_times()
+    ams = e0.elapsed_time(e1) / na
+    out["adjoint"] = {"ms_per_step": ams, "coeffs_per_s": coeffs / (ams * 1e-3),
+                      "kernels": {k: {"launches_per_step": n / na, "avg_ms": round(t / n, 4)}
+                                  for k, (n, t) in akt.items()}}
 
     if not args.no_fp64:
         log("fp64 forward timing")

@@ -16,11 +16,13 @@ namespace dgtns {
 // elements per work-group: 8192 (FP32) or 4096 (FP64)
 template <typename C> struct Budget { static constexpr int value = sizeof(C) == 8 ? 8192 : 4096; };
 
-// Columns per work-group of the fast factorisation kernels for length D.
-template <typename C, int D> struct FastCols {
+// Columns per work-group of the fast factorisation kernels for length D
+// (KF > 0: that many wave transforms per wavefront; the adjoint uses one, as
+// its accumulators stay live across the loop over n0).
+template <typename C, int D, int KF = 0> struct FastCols {
   static constexpr int TPW = WInfo<D>::TPW;
   static constexpr int K0 = Budget<C>::value / (8 * TPW * D);
-  static constexpr int K = K0 < 1 ? 1 : K0;       // wave transforms per wavefront
+  static constexpr int K = KF > 0 ? KF : (K0 < 1 ? 1 : K0);   // wave transforms per wavefront
   static constexpr int W = 8 * TPW * K;           // columns per work-group (8 wavefronts)
   static constexpr int SD = D + 1;                // padded column stride of the LDS tile
   static constexpr int TILE = W * SD;
@@ -135,9 +137,10 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
 // ----------------------------------------------------------------------------
 // Adjoint factorisation, p = 1, compile-time d = D.
 // ----------------------------------------------------------------------------
+// FP32: at least four waves per SIMD (two work-groups per compute unit).
 template <typename C, int D>
-__global__ void __launch_bounds__(kThreads) k_adj_cols_w(ColAdjArgs<C> A) {
-  using F = FastCols<C, D>;
+__global__ void __launch_bounds__(kThreads, sizeof(C) == 8 ? 4 : 1) k_adj_cols_w(ColAdjArgs<C> A) {
+  using F = FastCols<C, D, 1>;
   using I = WInfo<D>;
   constexpr int E = I::E, T = I::T, K = F::K, W = F::W, SD = F::SD;
   extern __shared__ __align__(16) unsigned char smem_raw[];

@@ -249,7 +249,7 @@ int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t s
 
 template <typename C, int D>
 int run_adj_cols_fast(const Plan& P, const ColAdjArgs<C>& A, long long B, hipStream_t st) {
-  using F = FastCols<C, D>;
+  using F = FastCols<C, D, 1>;   // as in k_adj_cols_w
   dim3 grid(cdiv(P.Mi, F::W), unsigned(B));
   return launch(k_adj_cols_w<C, D>, grid, sizeof(C) * F::LDS, st, A, "adjoint factorisation kernel");
 }
