@@ -66,13 +66,15 @@ enum dgtns_branch {
   DGTNS_SEPARABLE = 0,  /* lambda = 0: no shear */
   DGTNS_TIME_SHEAR = 1, /* s0 = 0: time shear only (Alg. 1, first branch) */
   DGTNS_FREQ_SHEAR = 2, /* s0 != 0: frequency and time shear (Alg. 1, second branch) */
-  DGTNS_MULTIWINDOW = 3 /* multiwindow algorithm: lambda2 coset windows (Prop. 4, Prop. 5) */
+  DGTNS_MULTIWINDOW = 3, /* multiwindow algorithm: lambda2 coset windows (Prop. 4, Prop. 5) */
+  DGTNS_FIR = 4          /* FIR-window algorithm (dgtns_plan_create_fir) */
 };
 
 /* Algorithm of a plan (dgtns_plan_create_alg). */
 enum dgtns_algorithm {
   DGTNS_ALG_SHEAR = 0,      /* shear algorithm, Alg. 1 (dgtns_plan_create) */
-  DGTNS_ALG_MULTIWINDOW = 1 /* multiwindow algorithm, Section 3.1 (Prop. 4, Prop. 5) */
+  DGTNS_ALG_MULTIWINDOW = 1, /* multiwindow algorithm, Section 3.1 (Prop. 4, Prop. 5) */
+  DGTNS_ALG_FIR = 2          /* FIR-window algorithm: use dgtns_plan_create_fir */
 };
 
 enum dgtns_op {
@@ -130,13 +132,34 @@ int dgtns_plan_create(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t
  * g(l - mu a), sigma_mu = (mu s) mod b (Prop. 5).  The lambda2 windows share
  * one column transform of the signal.  Such a plan runs dgtns_forward,
  * dgtns_forward_batch and dgtns_adjoint; dgtns_window_grad returns
- * DGTNS_EUNSUPPORTED.  dgtns_plan_info reports branch DGTNS_MULTIWINDOW,
+ * DGTNS_EUNSUPPORTED.  DGTNS_ALG_FIR is refused here (DGTNS_EINVAL): it needs the
+ * window support of dgtns_plan_create_fir.  dgtns_plan_info reports branch DGTNS_MULTIWINDOW,
  * s0 = s1 = 0, inner_a = lambda2 a, q per window and windows = lambda2; the
  * persistent memory holds lambda2 window tables.  Errors as for
  * dgtns_plan_create, plus DGTNS_EINVAL for an unknown algorithm.
  */
 int dgtns_plan_create_alg(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1,
                           int64_t lambda2, int dtype, int64_t max_batch, int algorithm);
+
+/*
+ * Create a plan for a window of short support (the FIR-window algorithm of
+ * Section 4, the weighted overlap-add DGT; Table 1's multiwindow FIR row on
+ * a nonseparable lattice).  The window is taken to be zero outside the g_len
+ * samples g_start, ..., g_start + g_len - 1 (mod L): dgtns_set_window keeps
+ * only those samples, and the coefficients are eq. (DGT) for that truncated
+ * window.  Per time position n the windowed samples f(l) conj(g(l - n a)) are
+ * modulated by exp(-2 pi i l w(n) / M), folded modulo M and transformed by
+ * one M-point DFT: no intermediate array, about 8 L g_len / a + 4 N M log2 M
+ * flops.  M must be 7-smooth and at most 4096; any lattice of
+ * dgtns_plan_create.  Such a plan runs dgtns_forward, dgtns_forward_batch
+ * and dgtns_adjoint (workspace: M N values per signal);
+ * dgtns_window_grad, dgtns_dual_window and dgtns_tight_window return
+ * DGTNS_EUNSUPPORTED.  dgtns_plan_info reports branch DGTNS_FIR and c = d =
+ * p = q = 0.  Errors as for dgtns_plan_create, plus DGTNS_EINVAL for g_len
+ * outside [1, L].
+ */
+int dgtns_plan_create_fir(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1,
+                          int64_t lambda2, int dtype, int64_t max_batch, int64_t g_start, int64_t g_len);
 
 /* Fill *info (host only). */
 int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info);

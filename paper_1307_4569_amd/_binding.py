@@ -24,9 +24,11 @@ DGTNS_SEPARABLE = 0
 DGTNS_TIME_SHEAR = 1
 DGTNS_FREQ_SHEAR = 2
 DGTNS_MULTIWINDOW = 3
+DGTNS_FIR = 4
 
 DGTNS_ALG_SHEAR = 0
 DGTNS_ALG_MULTIWINDOW = 1
+DGTNS_ALG_FIR = 2
 
 DGTNS_OP_FORWARD = 0
 DGTNS_OP_ADJOINT = 1
@@ -66,6 +68,8 @@ SIGNATURES = [
     ("dgtns_plan_create", ctypes.c_int, [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64]),
     ("dgtns_plan_create_alg", ctypes.c_int,
      [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64, ctypes.c_int]),
+    ("dgtns_plan_create_fir", ctypes.c_int,
+     [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64, c_i64, c_i64]),
     ("dgtns_plan_info", ctypes.c_int, [c_vp, ctypes.POINTER(dgtns_plan_info_t)]),
     ("dgtns_plan_bind", ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_workspace_bytes", ctypes.c_int, [c_vp, ctypes.c_int, c_i64, ctypes.POINTER(ctypes.c_size_t)]),
@@ -123,6 +127,12 @@ def dgtns_plan_create(L, a, M, lambda1, lambda2, dtype, max_batch):
 def dgtns_plan_create_alg(L, a, M, lambda1, lambda2, dtype, max_batch, algorithm):
     h = c_vp()
     _call("dgtns_plan_create_alg", ctypes.byref(h), L, a, M, lambda1, lambda2, dtype, max_batch, algorithm)
+    return h
+
+
+def dgtns_plan_create_fir(L, a, M, lambda1, lambda2, dtype, max_batch, g_start, g_len):
+    h = c_vp()
+    _call("dgtns_plan_create_fir", ctypes.byref(h), L, a, M, lambda1, lambda2, dtype, max_batch, g_start, g_len)
     return h
 
 

@@ -23,23 +23,28 @@ def _stream_handle(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-_ALG = {"shear": B.DGTNS_ALG_SHEAR, "multiwindow": B.DGTNS_ALG_MULTIWINDOW}
+_ALG = {"shear": B.DGTNS_ALG_SHEAR, "multiwindow": B.DGTNS_ALG_MULTIWINDOW, "fir": B.DGTNS_ALG_FIR}
 
 
 class Plan:
     """A lattice plan with its tables and window resident in device memory.
 
-    algorithm: "shear" (Alg. 1) or "multiwindow" (lambda2 coset windows on the
-    separable lattice (lambda2 a, M), Prop. 4 and Prop. 5); both compute the
-    same coefficients.  Window gradients need a shear plan."""
+    algorithm: "shear" (Alg. 1), "multiwindow" (lambda2 coset windows on the
+    separable lattice (lambda2 a, M), Prop. 4 and Prop. 5) or "fir" (windows of
+    short support, support=(start, length): the window is taken to be zero
+    outside samples start, ..., start + length - 1 mod L).  All compute the
+    coefficients of eq. (DGT).  Window gradients, dual and tight windows need
+    a shear plan."""
 
     def __init__(self, L: int, a: int, M: int, lam1: int = 0, lam2: int = 1,
                  dtype: torch.dtype = torch.complex64, max_batch: int = 64, device=None,
-                 algorithm: str = "shear"):
+                 algorithm: str = "shear", support: Optional[Tuple[int, int]] = None):
         if dtype not in _DT:
             raise ValueError("dtype must be torch.complex64 or torch.complex128")
         if algorithm not in _ALG:
-            raise ValueError("algorithm must be 'shear' or 'multiwindow'")
+            raise ValueError("algorithm must be 'shear', 'multiwindow' or 'fir'")
+        if (algorithm == "fir") != (support is not None):
+            raise ValueError("support=(start, length) is given exactly for algorithm 'fir'")
         if not torch.cuda.is_available():
             raise RuntimeError("libdgtns needs a HIP device")
         self.device = torch.device(device if device is not None else "cuda")
@@ -47,7 +52,11 @@ class Plan:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.dtype = dtype
         self.algorithm = algorithm
-        self._h = B.dgtns_plan_create_alg(L, a, M, lam1, lam2, _DT[dtype], max_batch, _ALG[algorithm])
+        if algorithm == "fir":
+            self._h = B.dgtns_plan_create_fir(L, a, M, lam1, lam2, _DT[dtype], max_batch, int(support[0]),
+                                              int(support[1]))
+        else:
+            self._h = B.dgtns_plan_create_alg(L, a, M, lam1, lam2, _DT[dtype], max_batch, _ALG[algorithm])
         self.info = B.dgtns_plan_info(self._h)
         self.L, self.a, self.M, self.lam1, self.lam2 = L, a, M, lam1, lam2
         self.N = self.info.N

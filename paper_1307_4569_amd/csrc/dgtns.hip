@@ -129,20 +129,31 @@ int dgtns_plan_create(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t
   return dgtns_plan_create_alg(plan, L, a, M, lambda1, lambda2, dtype, max_batch, DGTNS_ALG_SHEAR);
 }
 
-int dgtns_plan_create_alg(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
-                          int dtype, int64_t max_batch, int algorithm) {
+static int create_plan(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
+                       int dtype, int64_t max_batch, int algorithm, int64_t g_start, int64_t g_len) {
   if (!plan) return fail(DGTNS_EINVAL, "null plan pointer");
   if (max_batch > 65535) return fail(DGTNS_EINVAL, "max_batch above 65535");
   dgtns_plan_s* h = new (std::nothrow) dgtns_plan_s();
   if (!h) return fail(DGTNS_EINVAL, "out of host memory");
   std::string err;
-  int rc = plan_make(L, a, M, lambda1, lambda2, dtype, max_batch, algorithm, &h->p, &err);
+  int rc = plan_make(L, a, M, lambda1, lambda2, dtype, max_batch, algorithm, &h->p, &err, g_start, g_len);
   if (rc) {
     delete h;
     return fail(rc, err);
   }
   *plan = h;
   return DGTNS_OK;
+}
+
+int dgtns_plan_create_alg(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
+                          int dtype, int64_t max_batch, int algorithm) {
+  if (algorithm == kAlgFir) return fail(DGTNS_EINVAL, "FIR plans are created with dgtns_plan_create_fir");
+  return create_plan(plan, L, a, M, lambda1, lambda2, dtype, max_batch, algorithm, 0, 0);
+}
+
+int dgtns_plan_create_fir(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
+                          int dtype, int64_t max_batch, int64_t g_start, int64_t g_len) {
+  return create_plan(plan, L, a, M, lambda1, lambda2, dtype, max_batch, kAlgFir, g_start, g_len);
 }
 
 int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info) {
@@ -177,6 +188,7 @@ int dgtns_plan_bind(dgtns_plan plan, void* dev, size_t bytes, void* stream) {
   const int dt = P.dtype;
   put_tab(img, P.off.tw_d, P.tw_d, dt);
   put_tab(img, P.off.tw_m, P.tw_m, dt);
+  if (P.off.fir_ph) put_tab(img, P.off.fir_ph, P.fir_ph, dt);
   if (P.longd) {
     put_tab(img, P.off.tw_d1, P.tw_d1, dt);
     put_tab(img, P.off.tw_d2, P.tw_d2, dt);
@@ -291,7 +303,7 @@ static int dual_or_tight(dgtns_plan plan, const void* g_dev, void* out_dev, doub
   if (rc) return rc;
   if (!g_dev || !out_dev || !bounds_dev) return fail(DGTNS_EINVAL, "null argument");
   const Plan& P = plan->p;
-  if (P.branch == kMultiwindow)
+  if (P.branch == kMultiwindow || P.branch == kFir)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are computed with shear-algorithm plans");
   if (P.pi != 1)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p = 1 of the sheared lattice");

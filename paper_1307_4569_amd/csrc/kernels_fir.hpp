@@ -1,0 +1,203 @@
+// FIR-window algorithm (Sec. 4: the weighted-overlap-add DGT for windows of
+// short support, cost 8 L L_g / a + 4 N M log2 M; on a nonseparable lattice
+// the multiwindow route of Table 1 with FIR separable transforms).  For a
+// window supported on the L_g samples start, ..., start + L_g - 1 (mod L),
+// eq. (DGT) reads, per time position n,
+//     y_n(j) = f(l_j) conj(g(l_j - n a)) exp(-2 pi i l_j w(n) / M),
+//              l_j = (n a + start + j) mod L, j in Z_{L_g},
+//     c(m, n) = sum_k Y_n(k) exp(-2 pi i k m / M),  Y_n(k) = sum_{l_j = k mod M} y_n(j),
+// with w(n) = (n lambda1 mod lambda2) / lambda2: the windowed samples are
+// folded modulo M and one length-M DFT gives column n.  No intermediate
+// array: the signal is read (each sample by about L_g / a time positions,
+// from cache) and the coefficients written once.
+//
+// The adjoint f(l) = sum_n g(l - n a) exp(2 pi i l w(n) / M) y_n(l mod M),
+// y_n = unnormalised inverse DFT of c(., n), runs as the inverse DFTs of the
+// columns into Y[n][k] and a gather over the time positions whose window
+// covers each sample.
+#pragma once
+#include "kernels.hpp"
+#include "wave_fft.hpp"
+
+namespace dgtns {
+
+template <typename C> struct FirArgs {
+  const void* x;
+  long long xs;
+  int real_in;
+  int list;
+  const void* xl[kListMax];
+  C* c;
+  long long cs;
+  C* cl[kListMax];
+  const C* gw;     // conj(g(start + j)), j in Z_{L_g}
+  const C* ph;     // exp(-2 pi i e / (lambda2 M)), e in Z_{lambda2 M} (lambda2 > 1)
+  const C* twm;    // length-M stage twiddles
+  long long L, start;
+  int a, M, Lg, lam1, lam2, N, R, Sm;
+  FftSched fm;
+};
+
+// Windowed, modulated and folded bin k of time position n (the sum over the
+// support samples j = k - base (mod M) + t M).
+template <typename C>
+__device__ __forceinline__ C fir_bin(const FirArgs<C>& A, const void* xsrc, long long xoff, long long base, int kn,
+                                     int k) {
+  const int M = A.M;
+  const long long PM = (long long)A.lam2 * M;
+  int jk = (k - int(base % M)) % M;
+  if (jk < 0) jk += M;
+  C acc = czero<C>();
+  for (int j = jk; j < A.Lg; j += M) {
+    long long idx = base + j;
+    if (idx >= A.L) idx -= A.L;
+    C v = cmul(load_sig<C>(xsrc, A.real_in, xoff + idx), A.gw[j]);
+    if (kn) v = cmul(v, A.ph[((idx % PM) * kn) % PM]);
+    acc = cadd(acc, v);
+  }
+  return acc;
+}
+
+// ----------------------------------------------------------------------------
+// Forward, power-of-two M = MI in [32, 1024]: one wave transform per time
+// position; a work-group handles 8 TPW consecutive positions.
+// grid (ceil(N / (8 TPW)), B), 512 threads.
+// HS: streaming stores of the coefficients.
+// ----------------------------------------------------------------------------
+template <typename C, int MI, bool HS>
+__global__ void __launch_bounds__(kThreads) k_fir_fwd_w(FirArgs<C> A) {
+  using I = WInfo<MI>;
+  constexpr int E = I::E, T = I::T, TPW = I::TPW;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
+  const long long bo = blockIdx.y;
+  const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
+  const long long xoff = A.list ? 0 : bo * A.xs;
+  const int n = (blockIdx.x * 8 + wave) * TPW + tt;
+  const int nn = n < A.N ? n : A.N - 1;
+  long long base = ((long long)nn * A.a + A.start) % A.L;
+  const int kn = int(((long long)nn * A.lam1) % A.lam2);
+  C v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = fir_bin(A, xsrc, xoff, base, kn, l + T * e);
+  WTw<C, MI> tw;
+  tw.load(A.twm, l);
+  C* ex = lds + (wave * TPW + tt) * WEx<C, MI>::EX;
+  wave_fft<C, MI, false>(v, ex, l, tw);
+  if (n < A.N) {
+    C* row = (A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs) + (long long)n * MI;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if constexpr (HS)
+        st_stream(row + l + T * e, v[e]);
+      else
+        row[l + T * e] = v[e];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Forward, any in-LDS M: R time positions per work-group, LDS transforms.
+// grid (ceil(N / R), B), 512 threads.
+// ----------------------------------------------------------------------------
+template <typename C>
+__global__ void __launch_bounds__(kThreads) k_fir_fwd(FirArgs<C> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  const int M = A.M, R = A.R, Sm = A.Sm;
+  C* buf = tw + M;
+  for (int e = threadIdx.x; e < M; e += kThreads) tw[e] = A.twm[e];
+  const long long bo = blockIdx.y;
+  const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
+  const long long xoff = A.list ? 0 : bo * A.xs;
+  const int n0 = blockIdx.x * R;
+  for (int e = threadIdx.x; e < R * M; e += kThreads) {
+    const int r = e / M, k = e - r * M, n = n0 + r;
+    C v = czero<C>();
+    if (n < A.N) {
+      const long long base = ((long long)n * A.a + A.start) % A.L;
+      v = fir_bin(A, xsrc, xoff, base, int(((long long)n * A.lam1) % A.lam2), k);
+    }
+    buf[r * Sm + k] = v;
+  }
+  __syncthreads();
+  fft_lds<C, false>(buf, Sm, A.fm, R, tw);
+  C* cb = A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs;
+  for (int e = threadIdx.x; e < R * M; e += kThreads) {
+    const int r = e / M, m = e - r * M, n = n0 + r;
+    if (n < A.N) cb[(long long)n * M + m] = buf[r * Sm + m];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint, first pass: Y[n][k] = sum_m c(m, n) exp(2 pi i k m / M).
+// grid (ceil(N / R), B), 512 threads.
+// ----------------------------------------------------------------------------
+template <typename C>
+__global__ void __launch_bounds__(kThreads) k_fir_adj_rows(FirArgs<C> A, C* Y, long long ys) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  const int M = A.M, R = A.R, Sm = A.Sm;
+  C* buf = tw + M;
+  for (int e = threadIdx.x; e < M; e += kThreads) tw[e] = A.twm[e];
+  const long long bo = blockIdx.y;
+  const int n0 = blockIdx.x * R;
+  const C* cb = A.c + bo * A.cs;
+  for (int e = threadIdx.x; e < R * M; e += kThreads) {
+    const int r = e / M, m = e - r * M, n = n0 + r;
+    buf[r * Sm + m] = n < A.N ? cb[(long long)n * M + m] : czero<C>();
+  }
+  __syncthreads();
+  fft_lds<C, true>(buf, Sm, A.fm, R, tw);
+  for (int e = threadIdx.x; e < R * M; e += kThreads) {
+    const int r = e / M, k = e - r * M, n = n0 + r;
+    if (n < A.N) Y[bo * ys + (long long)n * M + k] = buf[r * Sm + k];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Adjoint, gather: f(l) = sum over the time positions n whose window covers
+// l (u = (l - start) mod L, n = floor(u / a) - t, j = u mod a + t a < L_g)
+// of g(l - n a) exp(2 pi i l w(n) / M) Y[n][l mod M].  One sample per thread.
+// grid (ceil(L / 512), B).
+// ----------------------------------------------------------------------------
+template <typename C>
+__global__ void __launch_bounds__(kThreads) k_fir_adj_gather(FirArgs<C> A, const C* Y, long long ys, C* f) {
+  const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= A.L) return;
+  const long long bo = blockIdx.y;
+  const int M = A.M;
+  const long long PM = (long long)A.lam2 * M;
+  long long u = idx - A.start;
+  if (u < 0) u += A.L;
+  const long long nt = u / A.a;
+  const int j0 = int(u - nt * A.a);
+  const int km = int(idx % M);
+  const C* Yb = Y + bo * ys;
+  C acc = czero<C>();
+  for (int t = 0, j = j0; j < A.Lg; ++t, j += A.a) {
+    long long n = nt - t;
+    if (n < 0) n += A.N;
+    C v = cmulc(Yb[n * M + km], A.gw[j]);      // times g(l - n a) = conj(gw[j])
+    const int kn = int((n * A.lam1) % A.lam2);
+    if (kn) v = cmulc(v, A.ph[((idx % PM) * kn) % PM]);
+    acc = cadd(acc, v);
+  }
+  f[bo * A.L + idx] = acc;
+}
+
+// Window support for the FIR algorithm: gw[j] = conj(g((start + j) mod L))
+// in the plan precision, from the FP64 window.
+template <typename CO>
+__global__ void __launch_bounds__(kThreads) k_fir_window(const double2* g, CO* gw, long long L, long long start,
+                                                         int Lg) {
+  using TO = decltype(CO::x);
+  const int j = blockIdx.x * kThreads + threadIdx.x;
+  if (j >= Lg) return;
+  long long idx = start + j;
+  if (idx >= L) idx -= L;
+  gw[j] = mk<CO>(TO(g[idx].x), TO(-g[idx].y));
+}
+
+}  // namespace dgtns

@@ -14,6 +14,7 @@
 #include "kernels.hpp"
 #include "kernels_fast.hpp"
 #include "kernels_long.hpp"
+#include "kernels_fir.hpp"
 #include "plan.hpp"
 
 namespace dgtns {
@@ -195,6 +196,10 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
   switch (op) {
     case DGTNS_OP_FORWARD:
     case DGTNS_OP_ADJOINT:
+      if (P.branch == kFir) {   // the adjoint's inverse DFTs of the columns
+        if (op == DGTNS_OP_ADJOINT) l.H = take(es * size_t(P.M) * size_t(P.N) * B);
+        break;
+      }
       if (pipelined(P, B, op)) {
         l.H = take(es * MN * P.chunk);
         l.F = take(es * MN * P.chunk);   // second h buffer
@@ -555,9 +560,77 @@ inline ChirpSrc<double2> chirp_fly(const Plan& P, long long s, int conj) {
   return c;
 }
 
+// ---------------------------------------------------------------------------
+// FIR-window algorithm (kernels_fir.hpp)
+// ---------------------------------------------------------------------------
+template <typename C>
+FirArgs<C> fir_args(const Plan& P) {
+  FirArgs<C> A;
+  std::memset(&A, 0, sizeof(A));
+  A.gw = tab<C>(P, P.off.zc);
+  A.ph = P.off.fir_ph ? tab<C>(P, P.off.fir_ph) : nullptr;
+  A.twm = tab<C>(P, P.off.tw_m);
+  A.L = P.L; A.start = P.fir_start;
+  A.a = int(P.a); A.M = int(P.M); A.Lg = int(P.fir_len); A.lam1 = int(P.lam1); A.lam2 = int(P.lam2);
+  A.N = int(P.N);
+  A.R = block_width(P.M | 1, sizeof(C)); A.Sm = int(P.M | 1);
+  A.fm = sched(P.fm);
+  return A;
+}
+
+template <typename C, int MI>
+int run_fir_fwd_w(const FirArgs<C>& A, const Plan& P, long long B, hipStream_t st) {
+  using I = WInfo<MI>;
+  dim3 grid(cdiv(P.N, 8 * I::TPW), unsigned(B));
+  const size_t lds = sizeof(C) * 8 * I::TPW * WEx<C, MI>::EX;
+  if (stream_c(P, B, sizeof(C))) return launch(k_fir_fwd_w<C, MI, true>, grid, lds, st, A, "FIR DGT");
+  return launch(k_fir_fwd_w<C, MI, false>, grid, lds, st, A, "FIR DGT");
+}
+
+template <typename C>
+int run_fir_fwd(const Plan& P, const void* f, int real_in, C* c, long long B, hipStream_t st,
+                const void* const* flist, void* const* clist) {
+  FirArgs<C> A = fir_args<C>(P);
+  A.x = f; A.xs = P.L; A.real_in = real_in; A.c = c; A.cs = P.M * P.N;
+  if (flist) {
+    A.list = 1;
+    for (long long k = 0; k < B; ++k) {
+      A.xl[k] = flist[k];
+      A.cl[k] = static_cast<C*>(clist[k]);
+    }
+  }
+  if (!P.generic && P.M * long(sizeof(C)) <= 8192) {
+    switch (P.M) {
+      case 32: return run_fir_fwd_w<C, 32>(A, P, B, st);
+      case 64: return run_fir_fwd_w<C, 64>(A, P, B, st);
+      case 128: return run_fir_fwd_w<C, 128>(A, P, B, st);
+      case 256: return run_fir_fwd_w<C, 256>(A, P, B, st);
+      case 512: return run_fir_fwd_w<C, 512>(A, P, B, st);
+      case 1024: return run_fir_fwd_w<C, 1024>(A, P, B, st);
+      default: break;
+    }
+  }
+  const size_t lds = sizeof(C) * (P.M + size_t(A.R) * A.Sm);
+  return launch(k_fir_fwd<C>, dim3(cdiv(P.N, A.R), unsigned(B)), lds, st, A, "FIR DGT");
+}
+
+template <typename C>
+int run_fir_adj(const Plan& P, const C* c, C* f, long long B, C* Y, hipStream_t st) {
+  FirArgs<C> A = fir_args<C>(P);
+  A.c = const_cast<C*>(c); A.cs = P.M * P.N;
+  const long long ys = P.M * P.N;
+  const size_t lds = sizeof(C) * (P.M + size_t(A.R) * A.Sm);
+  int rc = launch_raw(k_fir_adj_rows<C>, dim3(cdiv(P.N, A.R), unsigned(B)), dim3(kThreads), lds, st,
+                      "FIR adjoint, inverse DFTs", A, Y, ys);
+  if (rc) return rc;
+  return launch_raw(k_fir_adj_gather<C>, dim3(cdiv(P.L, kThreads), unsigned(B)), dim3(kThreads), 0, st,
+                    "FIR adjoint, gather", A, (const C*)Y, ys, f);
+}
+
 template <typename C>
 int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, char* ws, const Layout& l,
                  hipStream_t st, const void* const* flist = nullptr, void* const* clist = nullptr) {
+  if (P.branch == kFir) return run_fir_fwd<C>(P, f, real_in, c, B, st, flist, clist);
   C* H = reinterpret_cast<C*>(ws + l.H);
   int rc;
   // the workspace layout of this batch size decides the path (ws_layout):
@@ -600,6 +673,7 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
 template <typename C>
 int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const Layout& l, hipStream_t st) {
   C* H = reinterpret_cast<C*>(ws + l.H);
+  if (P.branch == kFir) return run_fir_adj<C>(P, c, f, B, H, st);
   if (pipelined(P, B, DGTNS_OP_ADJOINT)) {
     C* Hb[2] = {H, reinterpret_cast<C*>(ws + l.F)};
     const long long MN = P.M * P.N;
@@ -629,7 +703,7 @@ int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const L
 template <typename C>
 int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* ws, const Layout& l,
               hipStream_t st) {
-  if (P.branch == kMultiwindow)
+  if (P.branch == kMultiwindow || P.branch == kFir)
     return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for shear-algorithm plans only");
   if (P.longd)
     return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for columns of at most 4096 values");
@@ -684,6 +758,11 @@ int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* 
 template <typename CO>
 int window_zak(const Plan& P, const double2* g, CO* zc_out, double2* z64_out, char* ws, const Layout& l,
                hipStream_t st) {
+  if (P.branch == kFir) {
+    if (!zc_out) return fail(DGTNS_EUNSUPPORTED, "FIR plans keep only the window support");
+    return launch_raw(k_fir_window<CO>, dim3(cdiv(P.fir_len, kThreads)), dim3(kThreads), 0, st,
+                      "FIR window support", g, zc_out, (long long)P.L, (long long)P.fir_start, int(P.fir_len));
+  }
   const double2* src = g;
   ChirpSrc<double2> ch = chirp_fly(P, P.sh.s1, 0);
   if (P.branch == kSeparable) ch = no_chirp<double2>(P);

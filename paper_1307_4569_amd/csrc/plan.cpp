@@ -210,12 +210,12 @@ static void fill_chirp(int64_t L, int64_t s, std::vector<double>* v) {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int dtype,
-              int64_t max_batch, int algorithm, Plan* P, std::string* err) {
+              int64_t max_batch, int algorithm, Plan* P, std::string* err, int64_t fir_start, int64_t fir_len) {
   // status codes mirror include/dgtns.h
   const int kEInval = 1, kELattice = 2, kEUnsupported = 4;
   if (dtype != 0 && dtype != 1) { *err = "dtype must be DGTNS_C64 or DGTNS_C128"; return kEInval; }
-  if (algorithm != kAlgShear && algorithm != kAlgMultiwindow) {
-    *err = "algorithm must be DGTNS_ALG_SHEAR or DGTNS_ALG_MULTIWINDOW";
+  if (algorithm != kAlgShear && algorithm != kAlgMultiwindow && algorithm != kAlgFir) {
+    *err = "algorithm must be DGTNS_ALG_SHEAR, DGTNS_ALG_MULTIWINDOW or DGTNS_ALG_FIR";
     return kEInval;
   }
   if (L < 1 || a < 1 || M < 1 || max_batch < 1) { *err = "L, a, M and max_batch must be positive"; return kEInval; }
@@ -240,6 +240,38 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   {
     const char* gen = std::getenv("DGTNS_GENERIC");
     p.generic = gen && gen[0] == '1';
+  }
+  if (algorithm == kAlgFir) {
+    // FIR-window algorithm: per time position the windowed samples folded
+    // modulo M and one length-M DFT; needs the M-point transform and the
+    // lambda2 M phases exp(-2 pi i e / (lambda2 M)) of the offsets w(n)
+    if (fir_len < 1 || fir_len > L) { *err = "window support length must be in [1, L]"; return kEInval; }
+    if (!fft_schedule(M, &p.fm)) {
+      *err = "channel count M = " + std::to_string(M) + " must be 7-smooth and at most 4096";
+      return kEUnsupported;
+    }
+    p.branch = kFir;
+    p.sh.br = p.b;
+    p.ai = a; p.Mi = M; p.bi = p.b; p.Ni = p.N;
+    p.ci = p.pi = p.qw = p.qi = p.di = 0;
+    p.fir_start = fmod64(fir_start, L);
+    p.fir_len = fir_len;
+    fill_twiddles(M, &p.tw_m);
+    if (lam2 > 1) {
+      p.fir_ph.resize(2 * lam2 * M);
+      for (int64_t e = 0; e < lam2 * M; ++e) unit_root(-e, lam2 * M, &p.fir_ph[2 * e], &p.fir_ph[2 * e + 1]);
+    }
+    const size_t es = dtype == 0 ? 8 : 16;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    p.off = Plan::Off();
+    p.off.tw_m = take(es * M);
+    p.off.tw_m64 = dtype == 0 ? take(16 * M) : p.off.tw_m;   // FP64 copy, uploaded for every FP32 plan
+    p.off.fir_ph = p.fir_ph.empty() ? 0 : take(es * lam2 * M);
+    p.off.zc = take(es * fir_len);   // conj of the window support
+    p.off.bounds = take(16);
+    p.off.total = o;
+    return 0;
   }
   if (algorithm == kAlgMultiwindow) {
     // Prop. 4: the lattice is the union of lambda2 cosets of the separable

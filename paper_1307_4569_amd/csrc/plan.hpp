@@ -52,8 +52,8 @@ int64_t lcm64(int64_t a, int64_t b);
 bool fft_schedule(int64_t n, FftSchedule* out);
 Shear shearfind(int64_t L, int64_t a, int64_t M, int64_t s, int64_t b, std::string* err);
 
-enum Branch { kSeparable = 0, kTimeShear = 1, kFreqShear = 2, kMultiwindow = 3 };
-enum Algorithm { kAlgShear = 0, kAlgMultiwindow = 1 };
+enum Branch { kSeparable = 0, kTimeShear = 1, kFreqShear = 2, kMultiwindow = 3, kFir = 4 };
+enum Algorithm { kAlgShear = 0, kAlgMultiwindow = 1, kAlgFir = 2 };
 
 struct Plan {
   // lattice
@@ -80,19 +80,22 @@ struct Plan {
   // transforms); Wl columns per work-group of the length-d1 passes and Wm
   // columns r per work-group of the middle pass.
   bool longd = false;
+  // FIR-window algorithm: window support start, ..., start + fir_len - 1 (mod L)
+  int64_t fir_start = 0, fir_len = 0;
   int64_t d1 = 0, d2 = 0;
   FftSchedule fd1, fd2;
   int Wl = 1, Wm = 1;
   // column-block width of the factorisation kernels
   int W;
   // host tables (FP64, interleaved re/im); uploaded by bind
-  std::vector<double> tw_d, tw_m, tw_1, tw_2, tw_L, chirp1, chirp0, post_E, tw_d1, tw_d2;
+  std::vector<double> tw_d, tw_m, tw_1, tw_2, tw_L, chirp1, chirp0, post_E, tw_d1, tw_d2, fir_ph;
   std::vector<int32_t> post_rho;
   // device memory map (byte offsets into the persistent block)
   struct Off {
     size_t tw_d, tw_m, tw_1, tw_2, tw_L, chirp1, chirp0, post_E, post_rho, zc;   // plan dtype
     size_t tw_d64, tw_m64, tw_1_64, tw_2_64, tw_L64;                             // FP64 copies
     size_t tw_d1, tw_d2, tw_d1_64, tw_d2_64;                                     // long columns
+    size_t fir_ph;                                                               // FIR: lambda2 M phases
     size_t bounds;  // 2 doubles
     size_t total;
   } off;
@@ -107,7 +110,8 @@ struct Plan {
 
 // Returns 0 on success, else an error status with a message in *err.
 int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int dtype,
-              int64_t max_batch, int algorithm, Plan* p, std::string* err);
+              int64_t max_batch, int algorithm, Plan* p, std::string* err, int64_t fir_start = 0,
+              int64_t fir_len = 0);
 
 // Coset window mu of the multiwindow algorithm: g_mu(l) = exp(2 pi i l sigma / L)
 // g(l - mu a) with sigma = (mu s) mod b (Prop. 5).

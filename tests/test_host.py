@@ -196,6 +196,24 @@ def test_long_column_plans(lib):
     assert e.value.status == B.DGTNS_EUNSUPPORTED
 
 
+def test_fir_plans(lib):
+    """FIR-window plans: branch, no factorisation constants, and the errors."""
+    h = B.dgtns_plan_create_fir(144, 6, 12, 1, 2, 0, 2, 140, 20)
+    i = B.dgtns_plan_info(h)
+    B.dgtns_plan_destroy(h)
+    assert i.branch == B.DGTNS_FIR and (i.c, i.d, i.p, i.q) == (0, 0, 0, 0) and i.N == 24
+    for args, status in (((144, 6, 12, 1, 2, 0, 1, 0, 0), B.DGTNS_EINVAL),
+                         ((144, 6, 12, 1, 2, 0, 1, 0, 145), B.DGTNS_EINVAL),
+                         ((242, 2, 11, 0, 1, 0, 1, 0, 10), B.DGTNS_EUNSUPPORTED),   # M = 11 is not 7-smooth
+                         ((100, 6, 12, 1, 2, 0, 1, 0, 10), B.DGTNS_ELATTICE)):
+        with pytest.raises(B.DgtnsError) as e:
+            B.dgtns_plan_create_fir(*args)
+        assert e.value.status == status, args
+    with pytest.raises(B.DgtnsError) as e:
+        B.dgtns_plan_create_alg(144, 6, 12, 1, 2, 0, 1, B.DGTNS_ALG_FIR)
+    assert e.value.status == B.DGTNS_EINVAL
+
+
 def test_error_paths_without_device(lib):
     with pytest.raises(B.DgtnsError) as e:
         B.dgtns_plan_create(100, 6, 12, 1, 2, 0, 1)
