@@ -132,6 +132,42 @@ def crossover_bench(torch, dev, steps=5):
     return rows
 
 
+def fir_bench(torch, dev, steps=20):
+    """FIR-window algorithm versus the shear algorithm on the precision
+    workload: L = 2^20, a = 128, M = 1024, lambda = 1/4, 16 real chirp
+    signals (FP32), the periodic Hann window of length 2048 centred at 0
+    (support L - 1024 ... L + 1023 mod L).  The FIR kernel's compulsory
+    traffic is the real signal (4 bytes per sample) and the coefficients
+    (8 bytes each)."""
+    import numpy as np
+
+    from dgt_inputs import PRECISION, chirp_mixture, hann_window
+    from paper_1307_4569_amd import Plan
+    from paper_1307_4569_amd import _binding as Bm
+    w = PRECISION
+    lat = (w.L, w.a, w.M, w.lam1, w.lam2)
+    x = np.stack([chirp_mixture(w.L, 13074569 + 3000 + k) for k in range(w.batch)]).real.astype(np.float32)
+    xr = rotating(torch.tensor(x, device=dev))
+    g = torch.tensor(hann_window(w.L, 2048))
+    coeffs = w.batch * w.M * w.N
+    out = {"workload": f"precision L={w.L} a={w.a} M={w.M} lambda={w.lam1}/{w.lam2} B={w.batch} real, "
+                       "Hann window of length 2048"}
+    for name, kw in (("fir", {"algorithm": "fir", "support": (w.L - 1024, 2048)}), ("shear", {})):
+        plan = Plan(*lat, dtype=torch.complex64, max_batch=w.batch, device=dev, **kw)
+        plan.set_window(g)
+        c = torch.empty((w.batch, w.N, w.M), dtype=torch.complex64, device=dev)
+        ms, _, kt = time_forward(plan, xr, c, steps, 3, torch, Bm)
+        out[name] = {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3),
+                     "kernels": {k: round(t / n, 4) for k, (n, t) in kt.items()}}
+        del plan, c
+    fb = w.batch * (4 * w.L + 8 * w.M * w.N)
+    out["fir"]["compulsory_GBps"] = round(fb / (out["fir"]["ms_per_step"] * 1e-3) / 1e9, 1)
+    out["fir_speedup"] = out["shear"]["ms_per_step"] / out["fir"]["ms_per_step"]
+    log(f"FIR {out['fir']['coeffs_per_s'] / 1e9:.1f} Gcoeff/s, shear {out['shear']['coeffs_per_s'] / 1e9:.1f} "
+        f"Gcoeff/s on the precision workload")
+    return out
+
+
 def cpu_baseline(w, f_host, g_host, c_gpu_fn, budget_s=12.0):
     """Time the FP64 oracle (per-column fold form, single-threaded NumPy) on a
     bounded sample of the workload: whole signals of the batch, in order,
@@ -236,6 +272,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--no-multiwindow", action="store_true")
     ap.add_argument("--no-crossover", action="store_true")
+    ap.add_argument("--no-fir", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the FP32 forward loop (for rocprofv3)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -398,6 +435,9 @@ def main():
     if not args.no_crossover:
         log("shear versus multiwindow over lambda2")
         out["crossover"] = crossover_bench(torch, dev)
+    if not args.no_fir:
+        log("FIR-window algorithm on the precision workload")
+        out["fir"] = fir_bench(torch, dev)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -38,22 +38,76 @@ template <typename C> struct FirArgs {
   FftSched fm;
 };
 
-// Windowed, modulated and folded bin k of time position n (the sum over the
-// support samples j = k - base (mod M) + t M).
+// Per-time-position constants of the folding: base = (n a + start) mod L
+// (index of support sample 0), bm = base mod M, kn = n lambda1 mod lambda2
+// and eb = (base kn) mod (lambda2 M), the phase index of sample 0.  Phase
+// indices then advance without divisions: lambda2 M divides L, so the
+// index (l kn) mod (lambda2 M) of sample l = base + j is eb + j kn reduced.
+struct FirPos {
+  long long base;
+  int bm, kn, eb;
+};
+
 template <typename C>
-__device__ __forceinline__ C fir_bin(const FirArgs<C>& A, const void* xsrc, long long xoff, long long base, int kn,
-                                     int k) {
-  const int M = A.M;
-  const long long PM = (long long)A.lam2 * M;
-  int jk = (k - int(base % M)) % M;
+__device__ __forceinline__ FirPos fir_pos(const FirArgs<C>& A, int n) {
+  FirPos q;
+  q.base = ((long long)n * A.a + A.start) % A.L;
+  q.bm = int(q.base % A.M);
+  q.kn = int(((long long)n * A.lam1) % A.lam2);
+  const long long PM = (long long)A.lam2 * A.M;
+  q.eb = int(((q.base % PM) * q.kn) % PM);
+  return q;
+}
+
+// Windowed, modulated and folded bin k of time position n: the sum over the
+// support samples j = jk + t M, jk = (k - base) mod M.
+template <typename C>
+__device__ __forceinline__ C fir_bin(const FirArgs<C>& A, const void* xsrc, long long xoff, const FirPos& q, int k) {
+  const int M = A.M, PM = A.lam2 * A.M, step = M * q.kn;   // step < PM
+  int jk = k - q.bm;
   if (jk < 0) jk += M;
+  int e = q.eb + jk * q.kn;                                // jk kn < PM
+  if (e >= PM) e -= PM;
   C acc = czero<C>();
+  long long idx = q.base + jk;
+  if (idx >= A.L) idx -= A.L;
   for (int j = jk; j < A.Lg; j += M) {
-    long long idx = base + j;
-    if (idx >= A.L) idx -= A.L;
     C v = cmul(load_sig<C>(xsrc, A.real_in, xoff + idx), A.gw[j]);
-    if (kn) v = cmul(v, A.ph[((idx % PM) * kn) % PM]);
+    if (q.kn) v = cmul(v, A.ph[e]);
     acc = cadd(acc, v);
+    idx += M;
+    if (idx >= A.L) idx -= A.L;
+    e += step;
+    if (e >= PM) e -= PM;
+  }
+  return acc;
+}
+
+// fir_bin with at most NT samples per bin (L_g <= NT M), fully unrolled so
+// that the loads of all bins of a lane are issued together.
+template <int NT, typename C>
+__device__ __forceinline__ C fir_bin_n(const FirArgs<C>& A, const void* xsrc, long long xoff, const FirPos& q,
+                                       int k) {
+  const int M = A.M, PM = A.lam2 * A.M, step = M * q.kn;
+  int jk = k - q.bm;
+  if (jk < 0) jk += M;
+  int e = q.eb + jk * q.kn;
+  if (e >= PM) e -= PM;
+  long long idx = q.base + jk;
+  if (idx >= A.L) idx -= A.L;
+  C acc = czero<C>();
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = jk + t * M;
+    if (j < A.Lg) {
+      C v = cmul(load_sig<C>(xsrc, A.real_in, xoff + idx), A.gw[j]);
+      if (q.kn) v = cmul(v, A.ph[e]);
+      acc = cadd(acc, v);
+    }
+    idx += M;
+    if (idx >= A.L) idx -= A.L;
+    e += step;
+    if (e >= PM) e -= PM;
   }
   return acc;
 }
@@ -64,7 +118,8 @@ __device__ __forceinline__ C fir_bin(const FirArgs<C>& A, const void* xsrc, long
 // grid (ceil(N / (8 TPW)), B), 512 threads.
 // HS: streaming stores of the coefficients.
 // ----------------------------------------------------------------------------
-template <typename C, int MI, bool HS>
+// NT: samples per bin (L_g <= NT M), 0 for any L_g.
+template <typename C, int MI, bool HS, int NT>
 __global__ void __launch_bounds__(kThreads) k_fir_fwd_w(FirArgs<C> A) {
   using I = WInfo<MI>;
   constexpr int E = I::E, T = I::T, TPW = I::TPW;
@@ -75,12 +130,15 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd_w(FirArgs<C> A) {
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = A.list ? 0 : bo * A.xs;
   const int n = (blockIdx.x * 8 + wave) * TPW + tt;
-  const int nn = n < A.N ? n : A.N - 1;
-  long long base = ((long long)nn * A.a + A.start) % A.L;
-  const int kn = int(((long long)nn * A.lam1) % A.lam2);
+  const FirPos q = fir_pos(A, n < A.N ? n : A.N - 1);
   C v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = fir_bin(A, xsrc, xoff, base, kn, l + T * e);
+  for (int e = 0; e < E; ++e) {
+    if constexpr (NT > 0)
+      v[e] = fir_bin_n<NT>(A, xsrc, xoff, q, l + T * e);
+    else
+      v[e] = fir_bin(A, xsrc, xoff, q, l + T * e);
+  }
   WTw<C, MI> tw;
   tw.load(A.twm, l);
   C* ex = lds + (wave * TPW + tt) * WEx<C, MI>::EX;
@@ -115,10 +173,7 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd(FirArgs<C> A) {
   for (int e = threadIdx.x; e < R * M; e += kThreads) {
     const int r = e / M, k = e - r * M, n = n0 + r;
     C v = czero<C>();
-    if (n < A.N) {
-      const long long base = ((long long)n * A.a + A.start) % A.L;
-      v = fir_bin(A, xsrc, xoff, base, int(((long long)n * A.lam1) % A.lam2), k);
-    }
+    if (n < A.N) v = fir_bin(A, xsrc, xoff, fir_pos(A, n), k);
     buf[r * Sm + k] = v;
   }
   __syncthreads();
@@ -167,22 +222,34 @@ __global__ void __launch_bounds__(kThreads) k_fir_adj_gather(FirArgs<C> A, const
   const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
   if (idx >= A.L) return;
   const long long bo = blockIdx.y;
-  const int M = A.M;
-  const long long PM = (long long)A.lam2 * M;
+  const int M = A.M, PM = A.lam2 * A.M;
   long long u = idx - A.start;
   if (u < 0) u += A.L;
   const long long nt = u / A.a;
   const int j0 = int(u - nt * A.a);
-  const int km = int(idx % M);
+  const int i0 = int(idx % PM), km = i0 % M;
+  // phase index (idx kn) mod PM for kn = n lambda1 mod lambda2 in [0, lambda2):
+  // stepping n down by one lowers kn by lambda1 (e by dl) and, where kn
+  // wraps, adds lambda2 (e by dw)
+  int kn = int((nt * A.lam1) % A.lam2);
+  int e = int(((long long)i0 * kn) % PM);
+  const int dl = int(((long long)i0 * A.lam1) % PM), dw = int(((long long)i0 * A.lam2) % PM);
   const C* Yb = Y + bo * ys;
   C acc = czero<C>();
-  for (int t = 0, j = j0; j < A.Lg; ++t, j += A.a) {
-    long long n = nt - t;
-    if (n < 0) n += A.N;
+  long long n = nt;
+  for (int j = j0; j < A.Lg; j += A.a) {
     C v = cmulc(Yb[n * M + km], A.gw[j]);      // times g(l - n a) = conj(gw[j])
-    const int kn = int((n * A.lam1) % A.lam2);
-    if (kn) v = cmulc(v, A.ph[((idx % PM) * kn) % PM]);
+    if (kn) v = cmulc(v, A.ph[e]);
     acc = cadd(acc, v);
+    n = n == 0 ? A.N - 1 : n - 1;
+    kn -= A.lam1;
+    e -= dl;
+    if (e < 0) e += PM;
+    if (kn < 0) {
+      kn += A.lam2;
+      e += dw;
+      if (e >= PM) e -= PM;
+    }
   }
   f[bo * A.L + idx] = acc;
 }

@@ -578,13 +578,23 @@ FirArgs<C> fir_args(const Plan& P) {
   return A;
 }
 
-template <typename C, int MI>
-int run_fir_fwd_w(const FirArgs<C>& A, const Plan& P, long long B, hipStream_t st) {
+template <typename C, int MI, bool HS>
+int run_fir_fwd_w2(const FirArgs<C>& A, const Plan& P, long long B, hipStream_t st) {
   using I = WInfo<MI>;
   dim3 grid(cdiv(P.N, 8 * I::TPW), unsigned(B));
   const size_t lds = sizeof(C) * 8 * I::TPW * WEx<C, MI>::EX;
-  if (stream_c(P, B, sizeof(C))) return launch(k_fir_fwd_w<C, MI, true>, grid, lds, st, A, "FIR DGT");
-  return launch(k_fir_fwd_w<C, MI, false>, grid, lds, st, A, "FIR DGT");
+  // samples per folded bin: unrolled for up to four
+  const long long nt = (P.fir_len + MI - 1) / MI;
+  if (nt <= 1) return launch(k_fir_fwd_w<C, MI, HS, 1>, grid, lds, st, A, "FIR DGT");
+  if (nt <= 2) return launch(k_fir_fwd_w<C, MI, HS, 2>, grid, lds, st, A, "FIR DGT");
+  if (nt <= 4) return launch(k_fir_fwd_w<C, MI, HS, 4>, grid, lds, st, A, "FIR DGT");
+  return launch(k_fir_fwd_w<C, MI, HS, 0>, grid, lds, st, A, "FIR DGT");
+}
+
+template <typename C, int MI>
+int run_fir_fwd_w(const FirArgs<C>& A, const Plan& P, long long B, hipStream_t st) {
+  if (stream_c(P, B, sizeof(C))) return run_fir_fwd_w2<C, MI, true>(A, P, B, st);
+  return run_fir_fwd_w2<C, MI, false>(A, P, B, st);
 }
 
 template <typename C>
