@@ -132,7 +132,7 @@ def crossover_bench(torch, dev, steps=5):
     return rows
 
 
-def fir_bench(torch, dev, steps=20):
+def fir_bench(torch, dev, steps=20, with_shear=True):
     """FIR-window algorithm versus the shear algorithm on the precision
     workload: L = 2^20, a = 128, M = 1024, lambda = 1/4, 16 real chirp
     signals (FP32), the periodic Hann window of length 2048 centred at 0
@@ -152,7 +152,8 @@ def fir_bench(torch, dev, steps=20):
     coeffs = w.batch * w.M * w.N
     out = {"workload": f"precision L={w.L} a={w.a} M={w.M} lambda={w.lam1}/{w.lam2} B={w.batch} real, "
                        "Hann window of length 2048"}
-    for name, kw in (("fir", {"algorithm": "fir", "support": (w.L - 1024, 2048)}), ("shear", {})):
+    algs = [("fir", {"algorithm": "fir", "support": (w.L - 1024, 2048)})] + ([("shear", {})] if with_shear else [])
+    for name, kw in algs:
         plan = Plan(*lat, dtype=torch.complex64, max_batch=w.batch, device=dev, **kw)
         plan.set_window(g)
         c = torch.empty((w.batch, w.N, w.M), dtype=torch.complex64, device=dev)
@@ -162,9 +163,10 @@ def fir_bench(torch, dev, steps=20):
         del plan, c
     fb = w.batch * (4 * w.L + 8 * w.M * w.N)
     out["fir"]["compulsory_GBps"] = round(fb / (out["fir"]["ms_per_step"] * 1e-3) / 1e9, 1)
-    out["fir_speedup"] = out["shear"]["ms_per_step"] / out["fir"]["ms_per_step"]
-    log(f"FIR {out['fir']['coeffs_per_s'] / 1e9:.1f} Gcoeff/s, shear {out['shear']['coeffs_per_s'] / 1e9:.1f} "
-        f"Gcoeff/s on the precision workload")
+    if with_shear:
+        out["fir_speedup"] = out["shear"]["ms_per_step"] / out["fir"]["ms_per_step"]
+        log(f"FIR {out['fir']['coeffs_per_s'] / 1e9:.1f} Gcoeff/s, shear {out['shear']['coeffs_per_s'] / 1e9:.1f} "
+            f"Gcoeff/s on the precision workload")
     return out
 
 
@@ -275,6 +277,8 @@ def main():
     ap.add_argument("--no-fir", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the FP32 forward loop (for rocprofv3)")
+    ap.add_argument("--profile-fir", action="store_true",
+                    help="run only the FIR forward loop of the precision workload (for rocprofv3)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -290,6 +294,13 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
+    if args.profile_fir:
+        import torch
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        r = fir_bench(torch, dev, steps=args.steps, with_shear=False)
+        log(f"FIR forward {r['fir']['ms_per_step']:.3f} ms/step")
+        return
 
     import numpy as np
     import torch
