@@ -232,8 +232,9 @@ int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, vo
  * gd_dev: complex128[L].  bounds_dev: 2 doubles on the device receiving the
  * optimal frame bounds (A, B); A == 0 means the system is not a frame and
  * gd_dev is then undefined (asynchronous calls cannot report
- * DGTNS_ENOTFRAME; callers check A).  Implemented for p = 1 of the sheared
- * lattice and for shear-algorithm plans (DGTNS_EUNSUPPORTED otherwise).
+ * DGTNS_ENOTFRAME; callers check A).  Implemented for p <= 8 of the sheared
+ * lattice (p x p blocks of the frame operator in the Zak domain), columns of
+ * at most 4096 values and shear-algorithm plans (DGTNS_EUNSUPPORTED otherwise).
  * Does not change the plan's window.  Workspace: DGTNS_OP_DUAL.
  */
 int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* bounds_dev,
@@ -243,8 +244,8 @@ int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* 
  * Canonical tight window S^{-1/2} g (Section 4.2): the window whose Gabor
  * system on the plan's lattice is a tight frame with bound 1, so that
  * f = C*_{gt} C_{gt} f.  Same steps, arguments, bounds output, workspace
- * (DGTNS_OP_DUAL) and restrictions as dgtns_dual_window, with the Zak-domain
- * division by the square root of the frame operator's diagonal.
+ * (DGTNS_OP_DUAL) and restrictions as dgtns_dual_window, with the inverse
+ * square root of the Zak-domain frame operator in place of its inverse.
  * gt_dev: complex128[L].
  */
 int dgtns_tight_window(dgtns_plan plan, const void* g_dev, void* gt_dev, double* bounds_dev,

@@ -305,8 +305,8 @@ static int dual_or_tight(dgtns_plan plan, const void* g_dev, void* out_dev, doub
   const Plan& P = plan->p;
   if (P.branch == kMultiwindow || P.branch == kFir)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are computed with shear-algorithm plans");
-  if (P.pi != 1)
-    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p = 1 of the sheared lattice");
+  if (P.pi > kDualMaxP)
+    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p <= 8 of the sheared lattice");
   if (P.longd)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for columns of at most 4096 values");
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -639,7 +639,9 @@ __global__ void __launch_bounds__(kThreads) k_zak_inv(ZakInvArgs A) {
     xb[(cc * p + j0) * Sd + nu] = r < Mi ? A.z[((long long)r * p + j0) * d + nu] : make_double2(0, 0);
   }
   __syncthreads();
-  fft_lds<double2, true>(xb, Sd, A.fd, W * p, tw);
+  // at most MaxE * kThreads values per transform call (4096 in FP64)
+  const int per = (MaxE<double2>::value * kThreads) / d;
+  for (int t0 = 0; t0 < W * p; t0 += per) fft_lds<double2, true>(xb + t0 * Sd, Sd, A.fd, min(per, W * p - t0), tw);
   const double inv_d = 1.0 / d;
   for (int e = threadIdx.x; e < W * b; e += kThreads) {
     const int j = e / W, cc = e - j * W, r = r0 + cc;
@@ -680,6 +682,140 @@ __global__ void __launch_bounds__(kThreads) k_dual_div(const double2* z, double2
     zd[i] = D > 0 ? make_double2(v.x / den, v.y / den) : make_double2(0, 0);
     mn = D * scale_bounds;
     mx = D * scale_bounds;
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = smin[0];
+    part[2 * blockIdx.x + 1] = smax[0];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Canonical dual and tight windows for p > 1 of the sheared lattice.  In the
+// Zak domain the analysis operator takes the p values Zf_{r,j0}(nu), j0 in
+// Z_p, of a signal to its q coefficients at (r, nu) through the q x p matrix
+//   A(n0, j0) = conj(Zg_{u,j1 mod p}(nu)) / d,  u + Mi j1 = r - n0 ai + Mi j0,
+// times exp(2 pi i nu / d) where j1 < 0 (the index wraps one period of the
+// window's polyphase sequence), so the frame operator is block diagonal with
+// p x p blocks S(r, nu) = Mi d^2 A^H A; for p = 1 this is the scalar D of
+// k_dual_div.  The dual window has Zak S^{-1} Zg, the tight window S^{-1/2} Zg
+// (Section 4.2), and the optimal frame bounds are the extreme eigenvalues of
+// the blocks.  Each thread diagonalises one Hermitian block by cyclic Jacobi
+// rotations; eigenvalues that are not positive (no frame) contribute zero.
+// ----------------------------------------------------------------------------
+constexpr int kDualMaxP = 8;
+
+template <int PM>
+__global__ void __launch_bounds__(kThreads) k_dual_block(const double2* z, double2* zd, double* part, int Mi, int d,
+                                                        int p, int ai, int q, double scale_bounds, int tight) {
+  __shared__ double smin[kThreads], smax[kThreads];
+  const long long tot = (long long)Mi * d;
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  double mn = 1e308, mx = 0;
+  if (i < tot) {
+    const int r = int(i / d), nu = int(i - (long long)r * d);
+    double2 S[PM][PM], V[PM][PM];
+    for (int j = 0; j < p; ++j)
+      for (int k = 0; k < p; ++k) {
+        S[j][k] = make_double2(0, 0);
+        V[j][k] = make_double2(j == k ? 1.0 : 0.0, 0);
+      }
+    double sw, cw;
+    sincospi(2.0 * nu / d, &sw, &cw);
+    const double2 wrap = make_double2(cw, sw);
+    // S = Mi d^2 A^H A = Mi sum_{n0} conj(a) a^T with a = d A(n0, .)
+    for (int n0 = 0; n0 < q; ++n0) {
+      double2 row[PM];
+      for (int j0 = 0; j0 < p; ++j0) {
+        const long long v = r - (long long)n0 * ai + (long long)Mi * j0;
+        long long u = v % Mi;
+        if (u < 0) u += Mi;
+        const long long j1 = (v - u) / Mi;
+        const long long jp = ((j1 % p) + p) % p;
+        double2 t = z[(u * p + jp) * d + nu];
+        t.y = -t.y;
+        if (j1 < 0) t = cmul(t, wrap);
+        row[j0] = t;
+      }
+      for (int j = 0; j < p; ++j)
+        for (int k = 0; k < p; ++k) {
+          const double2 a = row[j], b = row[k];
+          S[j][k].x += a.x * b.x + a.y * b.y;   // conj(a) b
+          S[j][k].y += a.x * b.y - a.y * b.x;
+        }
+    }
+    for (int j = 0; j < p; ++j)
+      for (int k = 0; k < p; ++k) S[j][k] = cscale(S[j][k], double(Mi));
+    // cyclic Jacobi: S <- U^H S U, V <- V U, U = diag(1, conj(e)) R(c, s) on (j, k)
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      double off = 0, dia = 0;
+      for (int j = 0; j < p; ++j) {
+        dia += S[j][j].x * S[j][j].x;
+        for (int k = j + 1; k < p; ++k) off += S[j][k].x * S[j][k].x + S[j][k].y * S[j][k].y;
+      }
+      if (off <= 1e-32 * dia) break;
+      for (int j = 0; j < p - 1; ++j)
+        for (int k = j + 1; k < p; ++k) {
+          const double2 h = S[j][k];
+          const double ah = hypot(h.x, h.y);
+          if (ah == 0) continue;
+          const double2 e = make_double2(h.x / ah, h.y / ah);
+          const double2 ec = make_double2(e.x, -e.y);
+          const double tau = (S[k][k].x - S[j][j].x) / (2 * ah);
+          const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1 + tau * tau));
+          const double c = 1 / sqrt(1 + t * t), s = t * c;
+          for (int m = 0; m < p; ++m) {   // columns j, k
+            const double2 x = S[m][j], y = cmul(S[m][k], ec);
+            S[m][j] = make_double2(c * x.x - s * y.x, c * x.y - s * y.y);
+            S[m][k] = make_double2(s * x.x + c * y.x, s * x.y + c * y.y);
+            const double2 vx = V[m][j], vy = cmul(V[m][k], ec);
+            V[m][j] = make_double2(c * vx.x - s * vy.x, c * vx.y - s * vy.y);
+            V[m][k] = make_double2(s * vx.x + c * vy.x, s * vx.y + c * vy.y);
+          }
+          for (int m = 0; m < p; ++m) {   // rows j, k
+            const double2 x = S[j][m], y = cmul(S[k][m], e);
+            S[j][m] = make_double2(c * x.x - s * y.x, c * x.y - s * y.y);
+            S[k][m] = make_double2(s * x.x + c * y.x, s * x.y + c * y.y);
+          }
+          S[j][k] = make_double2(0, 0);
+          S[k][j] = make_double2(0, 0);
+          S[j][j].y = 0;
+          S[k][k].y = 0;
+        }
+    }
+    // out = V diag(lambda^-1 or lambda^-1/2) V^H Zg(r, ., nu)
+    double2 w[PM];
+    for (int k = 0; k < p; ++k) {
+      double2 acc = make_double2(0, 0);
+      for (int j = 0; j < p; ++j) {
+        const double2 vj = V[j][k], g = z[((long long)r * p + j) * d + nu];
+        acc.x += vj.x * g.x + vj.y * g.y;   // conj(V) g
+        acc.y += vj.x * g.y - vj.y * g.x;
+      }
+      const double lam = S[k][k].x;
+      mn = fmin(mn, fmax(lam, 0.0) * scale_bounds);
+      mx = fmax(mx, lam * scale_bounds);
+      const double f = lam > 0 ? (tight ? 1 / sqrt(lam) : 1 / lam) : 0.0;
+      w[k] = cscale(acc, f);
+    }
+    for (int j = 0; j < p; ++j) {
+      double2 acc = make_double2(0, 0);
+      for (int k = 0; k < p; ++k) {
+        const double2 t = cmul(V[j][k], w[k]);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
+      zd[((long long)r * p + j) * d + nu] = acc;
+    }
   }
   smin[threadIdx.x] = mn;
   smax[threadIdx.x] = mx;

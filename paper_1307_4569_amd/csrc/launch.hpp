@@ -846,7 +846,8 @@ int window_zak(const Plan& P, const double2* g, CO* zc_out, double2* z64_out, ch
 
 // Canonical dual window in FP64 (Alg. 2, with the time shear undone at the
 // end): Zak of the sheared window, division by the diagonal of the frame
-// operator (p = 1), inverse Zak, and for s0 != 0 the inverse frequency shear.
+// operator (p = 1) or inversion of its p x p blocks (p > 1), inverse Zak, and
+// for s0 != 0 the inverse frequency shear.
 // tight: the canonical tight window S^{-1/2} g by the same steps (Section
 // 4.2), dividing by the square root of the diagonal; with a frequency shear
 // the window transform scaled by 1/L is undone by sqrt(L) instead of L, as
@@ -868,8 +869,14 @@ inline int dual_impl(const Plan& P, const double2* g_dev, double2* gd_dev, doubl
   const long long tot = P.Mi * P.di;
   const unsigned nb = cdiv(tot, kThreads);
   const double sb = P.branch == kFreqShear ? double(P.L) : 1.0;
-  rc = launch_raw(k_dual_div<>, dim3(nb), dim3(kThreads), 0, st, "dual division", Z, Zd, part, int(P.Mi),
-                  int(P.di), int(P.ai), int(P.qi), sb, tight ? 1 : 0);
+  if (P.pi == 1)
+    rc = launch_raw(k_dual_div<>, dim3(nb), dim3(kThreads), 0, st, "dual division", Z, Zd, part, int(P.Mi),
+                    int(P.di), int(P.ai), int(P.qi), sb, tight ? 1 : 0);
+  else {
+    auto kern = P.pi <= 2 ? k_dual_block<2> : P.pi <= 4 ? k_dual_block<4> : k_dual_block<kDualMaxP>;
+    rc = launch_raw(kern, dim3(nb), dim3(kThreads), 0, st, "dual block inversion", (const double2*)Z, Zd, part,
+                    int(P.Mi), int(P.di), int(P.pi), int(P.ai), int(P.qi), sb, tight ? 1 : 0);
+  }
   if (rc) return rc;
   rc = launch_raw(k_minmax_final<>, dim3(1), dim3(kThreads), 0, st, "frame bounds", (const double*)part, int(nb),
                   bounds_dev);
@@ -878,9 +885,9 @@ inline int dual_impl(const Plan& P, const double2* g_dev, double2* gd_dev, doubl
   Zi.z = Zd;
   Zi.twd = tab<double2>(P, P.off.tw_d64);
   Zi.Mi = int(P.Mi); Zi.d = int(P.di); Zi.p = int(P.pi); Zi.Sd = int(P.di | 1);
-  Zi.W = block_width(Zi.Sd, 16);
+  Zi.W = block_width(P.pi * Zi.Sd, 16);
   Zi.fd = sched(P.fd);
-  size_t lds = 16 * (P.di + size_t(Zi.W) * Zi.Sd);
+  size_t lds = 16 * (P.di + size_t(Zi.W) * P.pi * Zi.Sd);
   if (P.branch != kFreqShear) {
     Zi.chirp = P.branch == kSeparable ? no_chirp<double2>(P) : chirp_fly(P, P.sh.s1, 1);
     Zi.x = gd_dev;

@@ -72,9 +72,14 @@ def test_window_gradient_matches_oracle(dtype, kernel_path):
 
 DUAL_LATTICES = [(144, 6, 12, 1, 2), (16, 4, 8, 1, 2), (2048, 16, 64, 1, 2), (4096, 32, 128, 1, 2),
                  (1152, 8, 64, 2, 3), (576, 4, 32, 0, 1), (240, 6, 12, 1, 2)]
+# p > 1 of the sheared lattice (p x p frame-operator blocks): time shear,
+# frequency shear and separable plans, p = 2, 3, 5, 7, 8
+DUAL_LATTICES_BLOCK = [(48, 4, 6, 1, 2), (48, 4, 6, 1, 4), (48, 6, 8, 0, 1), (72, 6, 8, 1, 3),
+                       (120, 10, 12, 1, 2), (180, 10, 12, 1, 3), (224, 7, 8, 1, 2), (288, 8, 9, 1, 2),
+                       (1200, 40, 60, 1, 2)]
 
 
-@pytest.mark.parametrize("lat", DUAL_LATTICES)
+@pytest.mark.parametrize("lat", DUAL_LATTICES + DUAL_LATTICES_BLOCK)
 def test_dual_window_matches_oracle(lat):
     L, a, M, l1, l2 = lat
     plan = plan_for(lat, torch.complex64, 1)
@@ -94,7 +99,7 @@ def test_dual_window_matches_oracle(lat):
     assert rel(sg, g[pts]) < 1e-11
 
 
-@pytest.mark.parametrize("lat", DUAL_LATTICES + [(24, 2, 6, 1, 4), (18, 3, 6, 2, 3)])
+@pytest.mark.parametrize("lat", DUAL_LATTICES + DUAL_LATTICES_BLOCK + [(24, 2, 6, 1, 4), (18, 3, 6, 2, 3)])
 def test_tight_window_matches_oracle(lat):
     """Canonical tight window S^{-1/2} g (time shear, frequency shear and
     separable plans): oracle values, the frame bounds, and tightness S_gt = I
@@ -117,6 +122,38 @@ def test_tight_window_matches_oracle(lat):
     x = complex_normal(L, 9)
     st = oracle.frame_operator_apply(x, gt, a, M, l1, l2, pts)
     assert rel(st, x[pts]) < 1e-11
+
+
+def test_dual_and_tight_on_a_crossover_lattice():
+    """Fig. 2 shape a = 40, M = 60 at L = 302400, lambda = 1/2: the sheared
+    lattice has p = 2 and columns of 2520.  S g_d = g and S_gt = I at sampled
+    points, and both calls report the same frame bounds."""
+    lat = (302400, 40, 60, 1, 2)
+    L, a, M, l1, l2 = lat
+    plan = plan_for(lat, torch.complex64, 1)
+    assert plan.info.p == 2
+    g = gaussian_window(L, a, M)
+    gd, bd = plan.dual(torch.tensor(g))
+    gt, bt = plan.tight(torch.tensor(g))
+    bd, bt = bd.cpu().numpy(), bt.cpu().numpy()
+    assert 0 < bd[0] <= bd[1] and np.allclose(bd, bt, rtol=1e-12)
+    pts = np.linspace(0, L - 1, 4).astype(np.int64)
+    sg = oracle.frame_operator_apply(gd.cpu().numpy(), g, a, M, l1, l2, pts)
+    assert rel(sg, g[pts]) < 1e-11
+    x = complex_normal(L, 3)
+    st = oracle.frame_operator_apply(x, gt.cpu().numpy(), a, M, l1, l2, pts)
+    assert rel(st, x[pts]) < 1e-11
+
+
+def test_dual_refuses_p_above_eight():
+    from paper_1307_4569_amd import _binding as Bb
+    plan = plan_for((180, 9, 10, 0, 1), torch.complex64, 1)
+    assert plan.info.p == 9
+    g = torch.tensor(gaussian_window(180, 9, 10))
+    for fn in (plan.dual, plan.tight):
+        with pytest.raises(Bb.DgtnsError) as e:
+            fn(g)
+        assert e.value.status == Bb.DGTNS_EUNSUPPORTED
 
 
 def test_multiwindow_plans_refuse_dual_and_tight():
