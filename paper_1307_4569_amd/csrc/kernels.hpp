@@ -136,6 +136,7 @@ template <typename C> struct ColArgs {
   int qw;                      // time offsets per window (q = nw qw)
   long long zs;
   int hstream;                 // stream the h stores (st_h)
+  int ht;                      // h[n0][t][r] layout (fast forward kernels only)
   int nsplit;                  // wave kernel: work-groups sharing one column block (split of Z_q)
   FftSched fd;
 };
@@ -371,6 +372,7 @@ template <typename C> struct RowArgs {
   int Mi, Ni, R, Sm, q, d;
   int qw, nw;                  // time offsets per window, windows (row_time)
   int hstream;                 // stream the stores: h (adjoint) or the coefficients (forward)
+  int ht;                      // h[n0][t][r] layout (fast forward kernels only)
   FftSched fm;
   long long N, L, b, M, K1, K2, K3, K4, K5, C1n, C2n, Kt1, Kt6;
 };

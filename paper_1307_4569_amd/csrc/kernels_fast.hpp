@@ -28,6 +28,9 @@ template <typename C, int D, int KF = 0> struct FastCols {
   static constexpr int TILE = W * SD;
   static constexpr int EXW = TPW * WEx<C, D>::EX;  // exchange elements per wavefront
   static constexpr int LDS = (TILE > 8 * EXW ? TILE : 8 * EXW);
+  // forward with h[n0][t][r]: the [t][column] staging tile of stride W + 1
+  static constexpr int SW = W + 1;
+  static constexpr int LDS_T = (LDS > D * SW ? LDS : D * SW);
 };
 
 // Rows per work-group of the fast row kernels for length MI: half the element
@@ -59,7 +62,9 @@ template <typename C, int MI> struct FastRows {
 // (more work-groups for small batches).
 // ----------------------------------------------------------------------------
 // HS: streaming stores of h (chosen at launch from the size of h, stream_h).
-template <typename C, int D, bool HS>
+// HT: h is written as h[n0][t][r] (time-major), which lets the row kernel read
+// each row of Mi channels as one contiguous run; otherwise h[n0][r][t].
+template <typename C, int D, bool HS, bool HT>
 __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
   using F = FastCols<C, D>;
   using I = WInfo<D>;
@@ -100,6 +105,53 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
   C* ex = lds + wave * F::EXW + tt * WEx<C, D>::EX;
 #pragma unroll
   for (int k = 0; k < K; ++k) wave_fft<C, D, false>(X[k], ex, l, tw);
+  if constexpr (HT) {
+    // The W columns of each n0 are staged through LDS as [t][column] rows
+    // (stride SW) and leave as W contiguous values per time position.  A row
+    // index u = r - n0 ai below zero multiplies the window Zak by
+    // exp(2 pi i nu / d); after the inverse DFT that is the cyclic shift
+    // h(t) = y(t + 1), applied here as a shifted staging index.
+    constexpr int SW = F::SW;
+    C* stg = lds;
+    for (int n0 = n0_begin; n0 < n0_end; ++n0) {
+      int n0w;
+      const C* zc = window_of(A.zc, A.zs, A.qw, n0, &n0w);
+      C Y[K][E];
+      int sh[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int r = r0 + (wave * K + k) * I::TPW + tt;
+        const int v0 = r - n0w * A.ai;
+        const int u = v0 >= 0 ? v0 : v0 + Mi;
+        sh[k] = v0 < 0 ? D - 1 : 0;
+        const C* zrow = zc + (long long)(r < Mi ? u : 0) * D;
+#pragma unroll
+        for (int e = 0; e < E; ++e) Y[k][e] = cmul(X[k][e], zrow[l + T * e]);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) wave_fft<C, D, true>(Y[k], ex, l, tw);
+      __syncthreads();   // the exchange areas alias the staging tile
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int cc = (wave * K + k) * I::TPW + tt;
+#pragma unroll
+        for (int e = 0; e < E; ++e) stg[((l + T * e + sh[k]) & (D - 1)) * SW + cc] = Y[k][e];
+      }
+      __syncthreads();
+      C* hb = A.H + bo * A.hs + (long long)n0 * D * Mi + r0;
+      for (int e = tid; e < W * D; e += kThreads) {
+        const int t = e / W, c = e - t * W;
+        if (r0 + c < Mi) {
+          if constexpr (HS)
+            st_stream(hb + (long long)t * Mi + c, stg[t * SW + c]);
+          else
+            hb[(long long)t * Mi + c] = stg[t * SW + c];
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
   const C* tw_d = A.twd;
   for (int n0 = n0_begin; n0 < n0_end; ++n0) {
     int n0w;
@@ -210,7 +262,9 @@ __global__ void __launch_bounds__(kThreads, sizeof(C) == 8 ? 4 : 1) k_adj_cols_w
 // HS: streaming stores of the coefficients (a launch whose output cannot stay
 // in the last-level cache; otherwise its dirty lines are written back while
 // the next kernel runs).
-template <typename C, int MI, int MODE, bool HS>
+// HT: h[n0][t][r] (written by k_fwd_cols_w<.., true>): each wave transform
+// loads its row of MI channels straight into registers, with no LDS tile.
+template <typename C, int MI, int MODE, bool HS, bool HT>
 __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   using F = FastRows<C, MI>;
   using I = WInfo<MI>;
@@ -221,22 +275,34 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
   const int q = A.q, d = A.d;
   const int n0 = blockIdx.x % q, t0 = (blockIdx.x / q) * RB;
   const long long bo = blockIdx.y;
-  const C* hb = A.H + bo * A.hs + (long long)n0 * MI * d + t0;
-  for (int e = tid; e < RB * MI; e += kThreads) {
-    const int m = e / RB, i = e - m * RB;
-    lds[F::fwd_at(m, i)] = t0 + i < d ? hb[(long long)m * d + i] : czero<C>();
-  }
-  WTw<C, MI> tw;
-  tw.load(A.twm, l);
-  __syncthreads();
   C v[K][E];
+  WTw<C, MI> tw;
+  if constexpr (HT) {
+    const C* hb = A.H + bo * A.hs + (long long)n0 * MI * d;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = (wave * K + k) * I::TPW + tt;
+    for (int k = 0; k < K; ++k) {
+      const int t = t0 + (wave * K + k) * I::TPW + tt;
+      const C* hr = hb + (long long)(t < d ? t : 0) * MI;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[k][e] = lds[F::fwd_at(l + T * e, i)];
+      for (int e = 0; e < E; ++e) v[k][e] = hr[l + T * e];
+    }
+    tw.load(A.twm, l);
+  } else {
+    const C* hb = A.H + bo * A.hs + (long long)n0 * MI * d + t0;
+    for (int e = tid; e < RB * MI; e += kThreads) {
+      const int m = e / RB, i = e - m * RB;
+      lds[F::fwd_at(m, i)] = t0 + i < d ? hb[(long long)m * d + i] : czero<C>();
+    }
+    tw.load(A.twm, l);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = (wave * K + k) * I::TPW + tt;
+#pragma unroll
+      for (int e = 0; e < E; ++e) v[k][e] = lds[F::fwd_at(l + T * e, i)];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   C* ex = lds + wave * F::EXW + tt * WEx<C, MI>::EX;
   C* cb = A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs;
 #pragma unroll

@@ -237,6 +237,17 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
 // stage launchers (templated on precision)
 // ---------------------------------------------------------------------------
 
+// Wave-kernel sizes: powers of two from 32 to 1024.
+inline bool wave_len(long long n) { return n >= 32 && n <= 1024 && (n & (n - 1)) == 0; }
+
+// The forward runs the wave kernels in both stages, so h can take the
+// time-major layout h[n0][t][r] that only those two kernels use.
+template <typename C> bool h_time_major(const Plan& P) {
+  const bool cols = P.pi == 1 && !P.generic && !P.longd && P.di * long(sizeof(C)) <= 8192 && wave_len(P.di);
+  const bool rows = !P.generic && wave_len(P.Mi);
+  return cols && rows;
+}
+
 template <typename C, int D>
 int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t st) {
   using F = FastCols<C, D>;
@@ -248,8 +259,14 @@ int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t s
   ColArgs<C> A2 = A;
   A2.nsplit = int(ns);
   dim3 grid(unsigned(nblk * ns), unsigned(B));
-  if (A2.hstream) return launch(k_fwd_cols_w<C, D, true>, grid, sizeof(C) * F::LDS, st, A2, "factorisation kernel");
-  return launch(k_fwd_cols_w<C, D, false>, grid, sizeof(C) * F::LDS, st, A2, "factorisation kernel");
+  if (A2.ht) {
+    const size_t lds = sizeof(C) * F::LDS_T;
+    if (A2.hstream) return launch(k_fwd_cols_w<C, D, true, true>, grid, lds, st, A2, "factorisation kernel");
+    return launch(k_fwd_cols_w<C, D, false, true>, grid, lds, st, A2, "factorisation kernel");
+  }
+  const size_t lds = sizeof(C) * F::LDS;
+  if (A2.hstream) return launch(k_fwd_cols_w<C, D, true, false>, grid, lds, st, A2, "factorisation kernel");
+  return launch(k_fwd_cols_w<C, D, false, false>, grid, lds, st, A2, "factorisation kernel");
 }
 
 template <typename C, int D>
@@ -265,13 +282,23 @@ int run_rows_fast(const Plan& P, const RowArgs<C>& A, long long B, bool adjoint,
   dim3 grid(unsigned(P.qi) * cdiv(P.di, F::RB), unsigned(B));
   const size_t lds = sizeof(C) * F::LDS;
   const bool fs = P.branch == kFreqShear;
+  if (!adjoint && A.ht) {
+    // rows come straight from h[n0][t][r]: LDS only for the wave exchanges
+    const size_t lt = sizeof(C) * 8 * F::EXW;
+    if (A.hstream) {
+      if (fs) return launch(k_fwd_rows_w<C, MI, 1, true, true>, grid, lt, st, A, "channel DFT + shear post-processing");
+      return launch(k_fwd_rows_w<C, MI, 0, true, true>, grid, lt, st, A, "channel DFT + phase correction");
+    }
+    if (fs) return launch(k_fwd_rows_w<C, MI, 1, false, true>, grid, lt, st, A, "channel DFT + shear post-processing");
+    return launch(k_fwd_rows_w<C, MI, 0, false, true>, grid, lt, st, A, "channel DFT + phase correction");
+  }
   if (!adjoint) {
     if (A.hstream) {
-      if (fs) return launch(k_fwd_rows_w<C, MI, 1, true>, grid, lds, st, A, "channel DFT + shear post-processing");
-      return launch(k_fwd_rows_w<C, MI, 0, true>, grid, lds, st, A, "channel DFT + phase correction");
+      if (fs) return launch(k_fwd_rows_w<C, MI, 1, true, false>, grid, lds, st, A, "channel DFT + shear post-processing");
+      return launch(k_fwd_rows_w<C, MI, 0, true, false>, grid, lds, st, A, "channel DFT + phase correction");
     }
-    if (fs) return launch(k_fwd_rows_w<C, MI, 1, false>, grid, lds, st, A, "channel DFT + shear post-processing");
-    return launch(k_fwd_rows_w<C, MI, 0, false>, grid, lds, st, A, "channel DFT + phase correction");
+    if (fs) return launch(k_fwd_rows_w<C, MI, 1, false, false>, grid, lds, st, A, "channel DFT + shear post-processing");
+    return launch(k_fwd_rows_w<C, MI, 0, false, false>, grid, lds, st, A, "channel DFT + phase correction");
   }
   if (A.hstream) {
     if (fs) return launch(k_adj_rows_w<C, MI, 1, true>, grid, lds, st, A, "adjoint channel DFT (shear)");
@@ -398,6 +425,7 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.p = int(P.pi); A.q = int(P.qi);
   A.qw = int(P.qw); A.zs = P.L;
   A.hstream = stream_h(P, B, sizeof(C));
+  A.ht = h_time_major<C>(P);
   A.W = P.W; A.Sd = int(P.di | 1); A.fd = sched(P.fd);
   A.nsplit = 1;
   const size_t es = sizeof(C);
@@ -484,6 +512,7 @@ int run_rows(const Plan& P, const C* H, C* c, long long B, bool adjoint, hipStre
   RowArgs<C> A = row_args<C>(P, H, c);
   // the adjoint writes h, the forward the coefficients
   A.hstream = adjoint ? stream_h(P, B, sizeof(C)) : stream_c(P, B, sizeof(C));
+  A.ht = !adjoint && h_time_major<C>(P);
   if (clist) {
     A.list = 1;
     for (long long k = 0; k < B; ++k) A.cl[k] = static_cast<C*>(clist[k]);
