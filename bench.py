@@ -132,6 +132,54 @@ def crossover_bench(torch, dev, steps=5):
     return rows
 
 
+def gradient_bench(torch, dev, steps=20):
+    """One training step of the differentiation workload (L = 65536, a = 32,
+    M = 256, lambda = 1/2, 32 signals, FP32): c = DGT_g(f), loss
+    sum((|c|^2 - T)^2), then gradients for f (the adjoint) and for a
+    full-length trainable window g (the window gradient)."""
+    import numpy as np
+
+    from dgt_inputs import GRADIENT, complex_normal, complex_normal_batch, gaussian_window
+    from paper_1307_4569_amd import DGTFunction, Plan
+    from paper_1307_4569_amd import _binding as Bm
+    w = GRADIENT
+    plan = Plan(w.L, w.a, w.M, w.lam1, w.lam2, dtype=torch.complex64, max_batch=w.batch, device=dev)
+    g0 = gaussian_window(w.L, w.a, w.M)
+    plan.set_window(torch.tensor(g0))
+    T = plan.forward(torch.tensor(complex_normal(w.L, 4000).astype(np.complex64), device=dev)).abs() ** 2
+    f = torch.tensor(complex_normal_batch(w.batch, w.L, 4).astype(np.complex64), device=dev, requires_grad=True)
+    g = torch.tensor(g0.astype(np.complex64), device=dev, requires_grad=True)
+
+    def step():
+        f.grad = None
+        g.grad = None
+        c = DGTFunction.apply(f, g, plan)
+        loss = ((c.abs() ** 2 - T) ** 2).sum()
+        loss.backward()
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    Bm.dgtns_timing_reset()
+    Bm.dgtns_timing_enable(1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    Bm.dgtns_timing_enable(0)
+    kt = Bm.kernel_times()
+    ms = e0.elapsed_time(e1) / steps
+    coeffs = w.batch * w.M * w.N
+    lib_ms = sum(t for _, t in kt.values()) / steps
+    return {"workload": f"{w.name} FP32, loss sum((|c|^2 - T)^2), gradients for f and g",
+            "ms_per_step": round(ms, 4), "coeffs_per_s": coeffs / (ms * 1e-3),
+            "library_ms_per_step": round(lib_ms, 4),
+            "kernels": {k: {"launches_per_step": n / steps, "avg_ms": round(t / n, 4)} for k, (n, t) in kt.items()}}
+
+
 def fir_bench(torch, dev, steps=20, with_shear=True):
     """FIR-window algorithm versus the shear algorithm on the precision
     workload: L = 2^20, a = 128, M = 1024, lambda = 1/4, 16 real chirp
@@ -275,6 +323,7 @@ def main():
     ap.add_argument("--no-multiwindow", action="store_true")
     ap.add_argument("--no-crossover", action="store_true")
     ap.add_argument("--no-fir", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the FP32 forward loop (for rocprofv3)")
     ap.add_argument("--profile-fir", action="store_true",
@@ -449,6 +498,9 @@ def main():
     if not args.no_fir:
         log("FIR-window algorithm on the precision workload")
         out["fir"] = fir_bench(torch, dev)
+    if not args.no_gradient:
+        log("training step of the differentiation workload")
+        out["gradient"] = gradient_bench(torch, dev)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

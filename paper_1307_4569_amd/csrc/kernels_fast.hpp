@@ -253,6 +253,126 @@ __global__ void __launch_bounds__(kThreads, sizeof(C) == 8 ? 4 : 1) k_adj_cols_w
 }
 
 // ----------------------------------------------------------------------------
+// Window gradient, p = 1, compile-time d = D.
+// k_col_spectra_w: X_r = DFT_d of the (chirped) signal column r, stored as
+// one contiguous row X[r][nu] per column; grid (ceil(Mi / W), B).
+// k_grad_cols_w: for window column u and time offset n0 the signal column is
+// r = (u + n0 ai) mod Mi, and in the Zak domain
+//   grad Zg_u(nu) = (1/d) sum_n0 X_r(nu) conj(Hhat_{n0,r}(nu)) w(nu),
+// with Hhat the DFT over t' of the adjoint-row output h[n0][r][.] and
+// w(nu) = exp(2 pi i nu / d) where the column index wrapped (else 1); the
+// gradient column is the unnormalised inverse DFT of grad Zg_u.  One wave
+// transform per window column accumulates over n0 in registers; grid
+// (ceil(Mi / W), B), one partial per signal, summed in a fixed order after.
+// ----------------------------------------------------------------------------
+template <typename C, int D>
+__global__ void __launch_bounds__(kThreads) k_col_spectra_w(ColArgs<C> A) {
+  using F = FastCols<C, D>;
+  using I = WInfo<D>;
+  constexpr int E = I::E, T = I::T, K = F::K, W = F::W, SD = F::SD;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
+  const int Mi = A.Mi;
+  const int r0 = blockIdx.x * W;
+  const long long bo = blockIdx.y;
+  for (int e = tid; e < W * D; e += kThreads) {
+    const int t = e / W, cc = e - t * W, r = r0 + cc;
+    C v = czero<C>();
+    if (r < Mi) {
+      const long long li = r + (long long)t * Mi;
+      v = apply_chirp(A.chirp, load_sig<C>(A.x, A.real_in, bo * A.xs + li), li);
+    }
+    lds[cc * SD + t] = v;
+  }
+  WTw<C, D> tw;
+  tw.load(A.twd, l);
+  __syncthreads();
+  C X[K][E];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int cc = (wave * K + k) * I::TPW + tt;
+#pragma unroll
+    for (int e = 0; e < E; ++e) X[k][e] = lds[cc * SD + l + T * e];
+  }
+  __syncthreads();
+  C* ex = lds + wave * F::EXW + tt * WEx<C, D>::EX;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    wave_fft<C, D, false>(X[k], ex, l, tw);
+    const int r = r0 + (wave * K + k) * I::TPW + tt;
+    if (r < Mi) {
+      C* xo = A.H + bo * A.hs + (long long)r * D;
+#pragma unroll
+      for (int e = 0; e < E; ++e) xo[l + T * e] = X[k][e];
+    }
+  }
+}
+
+template <typename C> struct GradWArgs {
+  const C* X;          // column spectra X[r][nu], xs values per signal
+  long long xs;
+  const C* H;          // adjoint-row output h[n0][r][t'], hs values per signal
+  long long hs;
+  C* part;             // per-signal window gradient, ps values per signal
+  long long ps;
+  const C* twd;
+  int Mi, ai, q;
+};
+
+template <typename C, int D>
+__global__ void __launch_bounds__(kThreads, sizeof(C) == 8 ? 4 : 1) k_grad_cols_w(GradWArgs<C> A) {
+  using F = FastCols<C, D, 1>;
+  using I = WInfo<D>;
+  constexpr int E = I::E, T = I::T, W = F::W, SD = F::SD;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
+  const int Mi = A.Mi;
+  const int u0 = blockIdx.x * W;
+  const long long bo = blockIdx.y;
+  WTw<C, D> tw;
+  tw.load(A.twd, l);
+  C* ex = lds + wave * F::EXW + tt * WEx<C, D>::EX;
+  const int cc = wave * I::TPW + tt, u = u0 + cc;
+  const int uc = u < Mi ? u : 0;
+  C acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = czero<C>();
+  for (int n0 = 0; n0 < A.q; ++n0) {
+    int r = uc + n0 * A.ai;   // n0 ai < Mi for p = 1
+    const bool wrap = r >= Mi;
+    if (wrap) r -= Mi;
+    C Y[E];
+    const C* hb = A.H + bo * A.hs + ((long long)n0 * Mi + r) * D;
+#pragma unroll
+    for (int e = 0; e < E; ++e) Y[e] = hb[l + T * e];
+    wave_fft<C, D, false>(Y, ex, l, tw);
+    const C* xb = A.X + bo * A.xs + (long long)r * D;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int nu = l + T * e;
+      C pr = cmulc(xb[nu], Y[e]);
+      if (wrap) pr = cmulc(pr, A.twd[nu]);
+      acc[e] = cadd(acc[e], pr);
+    }
+  }
+  using R = decltype(C::x);
+  const R inv_d = R(1) / R(D);
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = cscale(acc[e], inv_d);
+  wave_fft<C, D, true>(acc, ex, l, tw);
+  __syncthreads();   // the exchange areas alias the output tile
+#pragma unroll
+  for (int e = 0; e < E; ++e) lds[cc * SD + l + T * e] = acc[e];
+  __syncthreads();
+  for (int e = tid; e < W * D; e += kThreads) {
+    const int t = e / W, c = e - t * W, uu = u0 + c;
+    if (uu < Mi) A.part[bo * A.ps + uu + (long long)t * Mi] = lds[c * SD + t];
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Row kernels, compile-time Mi = MI.  A work-group handles the RB
 // intermediate rows (n0, t0 + i), i in Z_RB, n0 = blockIdx.x mod q, whose
 // time positions are n = row_time(n0, t0 + i) (n0 + q (t0 + i) for the shear

@@ -212,6 +212,7 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
     case DGTNS_OP_WINDOW_GRAD:
       l.H = take(es * MN * B);
       l.part = take(es * L * B);
+      l.U = take(es * L * B);   // column spectra of the wave-kernel path
       if (fs) { l.F = take(es * L * B); l.Y = take(es * L * B); l.G = take(es * L); }
       break;
     case DGTNS_OP_SET_WINDOW:
@@ -739,6 +740,60 @@ int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const L
                           tab<C>(P, P.off.tw_2), st);
 }
 
+// Window gradient columns: wave kernels (column spectra, then one wave
+// transform per window column) or the runtime-schedule kernel.
+template <typename C, int D>
+int run_grad_cols_w(const Plan& P, const void* x, ChirpSrc<C> ch, const C* H, C* X, C* part, long long B,
+                    hipStream_t st) {
+  ColArgs<C> A;
+  std::memset(&A, 0, sizeof(A));
+  A.x = x; A.xs = P.L; A.real_in = 0; A.chirp = ch;
+  A.H = X; A.hs = P.L;
+  A.twd = tab<C>(P, P.off.tw_d);
+  A.Mi = int(P.Mi); A.d = int(P.di);
+  using F = FastCols<C, D>;
+  int rc = launch(k_col_spectra_w<C, D>, dim3(cdiv(P.Mi, F::W), unsigned(B)), sizeof(C) * F::LDS, st, A,
+                  "column spectra");
+  if (rc) return rc;
+  GradWArgs<C> G;
+  G.X = X; G.xs = P.L;
+  G.H = H; G.hs = h_per_signal(P);
+  G.part = part; G.ps = P.L;
+  G.twd = tab<C>(P, P.off.tw_d);
+  G.Mi = int(P.Mi); G.ai = int(P.ai); G.q = int(P.qi);
+  using F1 = FastCols<C, D, 1>;
+  return launch(k_grad_cols_w<C, D>, dim3(cdiv(P.Mi, F1::W), unsigned(B)), sizeof(C) * F1::LDS, st, G,
+                "window gradient");
+}
+
+template <typename C>
+int run_grad_cols_fast(const Plan& P, const void* x, ChirpSrc<C> ch, const C* H, C* X, C* part, long long B,
+                       hipStream_t st) {
+  switch (P.di) {
+    case 32: return run_grad_cols_w<C, 32>(P, x, ch, H, X, part, B, st);
+    case 64: return run_grad_cols_w<C, 64>(P, x, ch, H, X, part, B, st);
+    case 128: return run_grad_cols_w<C, 128>(P, x, ch, H, X, part, B, st);
+    case 256: return run_grad_cols_w<C, 256>(P, x, ch, H, X, part, B, st);
+    default: return run_grad_cols_w<C, 512>(P, x, ch, H, X, part, B, st);
+  }
+}
+
+template <typename C>
+int run_grad_cols_generic(const Plan& P, const void* x, ChirpSrc<C> ch, const C* H, C* part, long long B,
+                          hipStream_t st) {
+  GradArgs<C> A;
+  A.x = x; A.xs = P.L; A.real_in = 0; A.chirp = ch;
+  A.H = H; A.hs = h_per_signal(P);
+  A.part = part; A.ps = P.L;
+  A.twd = tab<C>(P, P.off.tw_d);
+  A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.q = int(P.qi);
+  A.Sd = int(P.di | 1);
+  A.W = block_width(2 * A.Sd, sizeof(C));
+  A.fd = sched(P.fd);
+  size_t lds = sizeof(C) * (P.di + 2 * size_t(A.W) * A.Sd);
+  return launch(k_grad_cols<C>, dim3(cdiv(P.Mi, A.W), unsigned(B)), lds, st, A, "window gradient");
+}
+
 template <typename C>
 int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* ws, const Layout& l,
               hipStream_t st) {
@@ -763,17 +818,12 @@ int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* 
     x = F;
     ch = no_chirp<C>(P);
   }
-  GradArgs<C> A;
-  A.x = x; A.xs = P.L; A.real_in = 0; A.chirp = ch;
-  A.H = H; A.hs = h_per_signal(P);
-  A.part = part; A.ps = P.L;
-  A.twd = tab<C>(P, P.off.tw_d);
-  A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.q = int(P.qi);
-  A.Sd = int(P.di | 1);
-  A.W = block_width(2 * A.Sd, sizeof(C));
-  A.fd = sched(P.fd);
-  size_t lds = sizeof(C) * (P.di + 2 * size_t(A.W) * A.Sd);
-  rc = launch(k_grad_cols<C>, dim3(cdiv(P.Mi, A.W), unsigned(B)), lds, st, A, "window gradient");
+  const bool wave = P.pi == 1 && !P.generic && wave_len(P.di) && P.di <= 512;
+  if (wave) {
+    rc = run_grad_cols_fast<C>(P, x, ch, H, reinterpret_cast<C*>(ws + l.U), part, B, st);
+  } else {
+    rc = run_grad_cols_generic<C>(P, x, ch, H, part, B, st);
+  }
   if (rc) return rc;
   if (!fs) {
     return launch_raw(k_batch_sum<C>, dim3(cdiv(P.L, kThreads)), dim3(kThreads), 0, st, "batch sum", part,
