@@ -242,6 +242,64 @@ __device__ void fft_lds(C* buf, int tstride, const FftSched& fs, int ntr, const 
   }
 }
 
+// ---- one wavefront, one transform: runtime-schedule Stockham in LDS ----
+// Pass of radix R over n <= 64 MV values at buf, executed by the 64 lanes of
+// one wavefront: every lane loads all its butterflies before storing any, so
+// the pass can run in place (a wavefront's LDS accesses complete in program
+// order) and needs no work-group barrier.  tw: the length-n twiddle table
+// exp(-2 pi i k / n) (global memory).
+template <typename C, int R, bool INV, int MV>
+__device__ __noinline__ void wrt_pass(C* buf, int n, int Ns, const C* tw, int lane) {
+  constexpr int KB = MV / R + 1;   // butterflies per lane: ceil(n / (64 R)) <= KB
+  const int nb = n / R;
+  const int twstep = n / (Ns * R);
+  C v[KB][R];
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    const int j = lane + 64 * i;
+    if (j < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[j + r * nb];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    const int j = lane + 64 * i;
+    if (j < nb) {
+      const int k = j % Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const C w = tw[r * k * twstep];
+          v[i][r] = INV ? cmulc(v[i][r], w) : cmul(v[i][r], w);
+        }
+      }
+      Bfly<C, R, INV>::run(v[i]);
+      C* dst = buf + (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[i][r];
+    }
+  }
+}
+
+template <typename C, bool INV, int MV>
+__device__ void fft_wave_rt(C* buf, const FftSched& fs, const C* tw, int lane) {
+  int Ns = 1;
+  for (int s = 0; s < fs.nst; ++s) {
+    const int R = fs.rad[s];
+    switch (R) {
+      case 8: wrt_pass<C, 8, INV, MV>(buf, fs.n, Ns, tw, lane); break;
+      case 4: wrt_pass<C, 4, INV, MV>(buf, fs.n, Ns, tw, lane); break;
+      case 2: wrt_pass<C, 2, INV, MV>(buf, fs.n, Ns, tw, lane); break;
+      case 3: wrt_pass<C, 3, INV, MV>(buf, fs.n, Ns, tw, lane); break;
+      case 5: wrt_pass<C, 5, INV, MV>(buf, fs.n, Ns, tw, lane); break;
+      case 7: wrt_pass<C, 7, INV, MV>(buf, fs.n, Ns, tw, lane); break;
+      default: break;
+    }
+    Ns *= R;
+  }
+}
+
 // exp(i pi e / N) for an exactly reduced integer e in [0, 2N): the argument
 // e / N is formed after shifting e into [-N, N), so its rounding error is at
 // most half an ulp of a number below 1.

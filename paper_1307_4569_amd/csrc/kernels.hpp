@@ -137,7 +137,7 @@ template <typename C> struct ColArgs {
   long long zs;
   int hstream;                 // stream the h stores (st_h)
   int ht;                      // h[n0][t][r] layout (fast forward kernels only)
-  int nsplit;                  // wave kernel: work-groups sharing one column block (split of Z_q)
+  int nsplit;                  // work-groups sharing one column block (split of Z_q)
   FftSched fd;
 };
 
@@ -160,6 +160,9 @@ __device__ __forceinline__ int row_time(int n0, int t, int qw, int nw) {
   return (n0 - mu * qw + qw * t) * nw + mu;
 }
 
+// Runtime-schedule factorisation: grid (ceil(Mi / W) * nsplit, B); the
+// nsplit work-groups of a column block each compute the column DFTs and a
+// share of the q offsets n0 (more work-groups for small batches).
 template <typename C, bool GENP>
 __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -168,7 +171,10 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
   C* xb = tw + d;
   C* yb = GENP ? xb + W * p * Sd : xb;
   for (int e = threadIdx.x; e < d; e += kThreads) tw[e] = A.twd[e];
-  const int r0 = blockIdx.x * W;
+  const int cb = blockIdx.x / A.nsplit, part = blockIdx.x - cb * A.nsplit;
+  const int qper = (A.q + A.nsplit - 1) / A.nsplit;
+  const int n0_begin = part * qper, n0_end = min(A.q, n0_begin + qper);
+  const int r0 = cb * W;
   const long long bo = blockIdx.y;
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = A.list ? 0 : bo * A.xs;
@@ -198,7 +204,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
       }
     }
   }
-  for (int n0 = 0; n0 < A.q; ++n0) {
+  for (int n0 = n0_begin; n0 < n0_end; ++n0) {
     int n0w;
     const C* zc = window_of(A.zc, A.zs, A.qw, n0, &n0w);
     __syncthreads();
@@ -261,6 +267,72 @@ template <typename C> struct ColAdjArgs {
   long long zs;
   FftSched fd;
 };
+
+// Factorisation for p = 1 and any 7-smooth d <= 64 MV, one column per
+// wavefront: the 8 columns of a work-group arrive through one coalesced LDS
+// tile, after which each wavefront transforms its own column in place
+// (fft_wave_rt) with no further work-group barrier.  The column spectrum
+// stays in registers (MV values per lane) across the q window products.
+// grid (ceil(Mi / 8) * nsplit, B), 512 threads.
+template <typename C, int MV>
+__global__ void __launch_bounds__(kThreads) k_fwd_cols_wr(ColArgs<C> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  constexpr int W = kThreads / 64;
+  const int d = A.d, Sd = A.Sd, Mi = A.Mi;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int cb = blockIdx.x / A.nsplit, part = blockIdx.x - cb * A.nsplit;
+  const int qper = (A.q + A.nsplit - 1) / A.nsplit;
+  const int n0_begin = part * qper, n0_end = min(A.q, n0_begin + qper);
+  const int r0 = cb * W;
+  const long long bo = blockIdx.y;
+  const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
+  const long long xoff = A.list ? 0 : bo * A.xs;
+  for (int e = tid; e < W * d; e += kThreads) {
+    const int t = e / W, cc = e - t * W, r = r0 + cc;
+    C v = czero<C>();
+    if (r < Mi) {
+      const long long l = r + (long long)t * Mi;
+      v = apply_chirp(A.chirp, load_sig<C>(xsrc, A.real_in, xoff + l), l);
+    }
+    lds[cc * Sd + t] = v;
+  }
+  __syncthreads();
+  const int r = r0 + wave;
+  const int rr = r < Mi ? r : 0;
+  C* buf = lds + wave * Sd;
+  fft_wave_rt<C, false, MV>(buf, A.fd, A.twd, lane);
+  C X[MV];
+#pragma unroll
+  for (int e = 0; e < MV; ++e) {
+    const int nu = lane + 64 * e;
+    X[e] = nu < d ? buf[nu] : czero<C>();
+  }
+  for (int n0 = n0_begin; n0 < n0_end; ++n0) {
+    int n0w;
+    const C* zc = window_of(A.zc, A.zs, A.qw, n0, &n0w);
+    const int v0 = rr - n0w * A.ai;
+    const C* zrow = zc + (long long)(v0 >= 0 ? v0 : v0 + Mi) * d;
+#pragma unroll
+    for (int e = 0; e < MV; ++e) {
+      const int nu = lane + 64 * e;
+      if (nu < d) {
+        C z = zrow[nu];
+        if (v0 < 0) z = cmulc(z, A.twd[nu]);
+        buf[nu] = cmul(X[e], z);
+      }
+    }
+    fft_wave_rt<C, true, MV>(buf, A.fd, A.twd, lane);
+    if (r < Mi) {
+      C* hb = A.H + bo * A.hs + ((long long)n0 * Mi + r) * d;
+#pragma unroll
+      for (int e = 0; e < MV; ++e) {
+        const int t = lane + 64 * e;
+        if (t < d) st_h(hb + t, buf[t], A.hstream);
+      }
+    }
+  }
+}
 
 template <typename C, bool GENP>
 __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {

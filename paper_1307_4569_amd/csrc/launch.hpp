@@ -442,12 +442,24 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
       default: break;
     }
   }
-  dim3 grid(cdiv(P.Mi, P.W), unsigned(B));
-  if (P.pi == 1) {
-    size_t lds = es * (P.di + size_t(P.W) * A.Sd);
-    return launch(k_fwd_cols<C, false>, grid, lds, st, A, "factorisation kernel");
+  // other 7-smooth d up to 1152 (p = 1): one wavefront per column
+  if (P.pi == 1 && !P.generic && P.di <= 1152) {
+    const size_t lw = es * 8 * size_t(A.Sd);
+    const long long nblk = cdiv(P.Mi, 8);
+    // small batches: split the q offsets until every work-group slot is used once
+    long long ns = (512 + nblk * B - 1) / (nblk * B);
+    if (ns > P.qi) ns = P.qi;
+    if (ns < 1) ns = 1;
+    A.nsplit = int(ns);
+    dim3 gw(unsigned(nblk * ns), unsigned(B));
+    if (P.di <= 320) return launch(k_fwd_cols_wr<C, 5>, gw, lw, st, A, "factorisation kernel");
+    if (P.di <= 576) return launch(k_fwd_cols_wr<C, 9>, gw, lw, st, A, "factorisation kernel");
+    return launch(k_fwd_cols_wr<C, 18>, gw, lw, st, A, "factorisation kernel");
   }
-  size_t lds = es * (P.di + size_t(P.W) * A.Sd * (P.pi + 1));
+  const size_t lds = P.pi == 1 ? es * (P.di + size_t(P.W) * A.Sd)
+                               : es * (P.di + size_t(P.W) * A.Sd * (P.pi + 1));
+  dim3 grid(cdiv(P.Mi, P.W), unsigned(B));
+  if (P.pi == 1) return launch(k_fwd_cols<C, false>, grid, lds, st, A, "factorisation kernel");
   return launch(k_fwd_cols<C, true>, grid, lds, st, A, "factorisation kernel (p > 1)");
 }
 
