@@ -45,7 +45,9 @@ def plan_for(lat, dtype, B):
 
 # lattices with p = 1 of the sheared lattice, both shear branches
 GRAD_LATTICES = [(144, 6, 12, 1, 2), (16, 4, 8, 1, 2), (72, 6, 12, 1, 3), (2048, 16, 64, 1, 2),
-                 (4096, 32, 128, 1, 2), (18432, 32, 256, 1, 2), (1152, 8, 64, 2, 3), (576, 4, 32, 0, 1)]
+                 (4096, 32, 128, 1, 2), (18432, 32, 256, 1, 2), (1152, 8, 64, 2, 3), (576, 4, 32, 0, 1),
+                 # d = 32 and 64 with Mi = 12: ragged work-groups of the wave-kernel gradient
+                 (384, 2, 12, 1, 2), (768, 2, 12, 0, 1)]
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
