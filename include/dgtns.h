@@ -67,14 +67,16 @@ enum dgtns_branch {
   DGTNS_TIME_SHEAR = 1, /* s0 = 0: time shear only (Alg. 1, first branch) */
   DGTNS_FREQ_SHEAR = 2, /* s0 != 0: frequency and time shear (Alg. 1, second branch) */
   DGTNS_MULTIWINDOW = 3, /* multiwindow algorithm: lambda2 coset windows (Prop. 4, Prop. 5) */
-  DGTNS_FIR = 4          /* FIR-window algorithm (dgtns_plan_create_fir) */
+  DGTNS_FIR = 4,         /* FIR-window algorithm (dgtns_plan_create_fir) */
+  DGTNS_SHEAR_OLA = 5    /* shear algorithm on overlap-added blocks (dgtns_plan_create_ola) */
 };
 
 /* Algorithm of a plan (dgtns_plan_create_alg). */
 enum dgtns_algorithm {
   DGTNS_ALG_SHEAR = 0,      /* shear algorithm, Alg. 1 (dgtns_plan_create) */
   DGTNS_ALG_MULTIWINDOW = 1, /* multiwindow algorithm, Section 3.1 (Prop. 4, Prop. 5) */
-  DGTNS_ALG_FIR = 2          /* FIR-window algorithm: use dgtns_plan_create_fir */
+  DGTNS_ALG_FIR = 2,         /* FIR-window algorithm: use dgtns_plan_create_fir */
+  DGTNS_ALG_SHEAR_OLA = 3    /* shear-OLA algorithm: use dgtns_plan_create_ola */
 };
 
 enum dgtns_op {
@@ -100,6 +102,9 @@ typedef struct {
   int64_t max_batch;
   size_t persistent_bytes; /* device bytes dgtns_plan_bind needs */
   int64_t windows;         /* windows of the separable lattice: 1, or lambda2 (multiwindow) */
+  /* shear-OLA plans: block length L_b and the length L_x of the DGT each
+     zero-extended block runs (0 for other plans) */
+  int64_t block, block_dgt_length;
 } dgtns_plan_info_t;
 
 /* Human-readable name of a status code (static storage). */
@@ -160,6 +165,30 @@ int dgtns_plan_create_alg(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int
  */
 int dgtns_plan_create_fir(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1,
                           int64_t lambda2, int dtype, int64_t max_batch, int64_t g_start, int64_t g_len);
+
+/*
+ * Create a plan for the shear-OLA algorithm (Section 4): the shear algorithm
+ * applied to blocks of the signal, combined by overlap-add, for a window of
+ * short support g_start, ..., g_start + g_len - 1 (mod L) as in
+ * dgtns_plan_create_fir.  The signal is cut into L / block blocks of block
+ * samples; each block, zero-extended, is transformed by the shear algorithm
+ * on the same lattice at a length L_x of about block + g_len (the least
+ * feasible one, reported as block_dgt_length), so the sheared window spans
+ * L_x samples instead of L.  The coefficients of each block are multiplied
+ * by the exact phase of its position and added into eq. (DGT)'s
+ * coefficients; the result equals eq. (DGT) with the truncated window.  The
+ * work grows by the factor rho = L_x / block (eq. (OLA-eff)).  block must
+ * divide L and be a multiple of lambda2 a, and max_batch * L / block must not
+ * exceed 65535.  Such a plan runs dgtns_forward only; dgtns_forward_batch,
+ * dgtns_adjoint, dgtns_window_grad, dgtns_dual_window and dgtns_tight_window
+ * return DGTNS_EUNSUPPORTED.  dgtns_plan_info reports branch
+ * DGTNS_SHEAR_OLA with the inner plan's s0, s1, b_r, c, d, p, q.  Errors as
+ * for dgtns_plan_create_fir, plus DGTNS_EINVAL for a bad block length and
+ * DGTNS_EUNSUPPORTED when no feasible block length below L exists.
+ */
+int dgtns_plan_create_ola(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1,
+                          int64_t lambda2, int dtype, int64_t max_batch, int64_t g_start, int64_t g_len,
+                          int64_t block);
 
 /* Fill *info (host only). */
 int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info);

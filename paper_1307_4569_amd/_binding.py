@@ -25,10 +25,12 @@ DGTNS_TIME_SHEAR = 1
 DGTNS_FREQ_SHEAR = 2
 DGTNS_MULTIWINDOW = 3
 DGTNS_FIR = 4
+DGTNS_SHEAR_OLA = 5
 
 DGTNS_ALG_SHEAR = 0
 DGTNS_ALG_MULTIWINDOW = 1
 DGTNS_ALG_FIR = 2
+DGTNS_ALG_SHEAR_OLA = 3
 
 DGTNS_OP_FORWARD = 0
 DGTNS_OP_ADJOINT = 1
@@ -47,6 +49,7 @@ class dgtns_plan_info_t(ctypes.Structure):
         ("branch", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("inner_a", c_i64), ("inner_M", c_i64), ("c", c_i64), ("d", c_i64), ("p", c_i64), ("q", c_i64),
         ("max_batch", c_i64), ("persistent_bytes", ctypes.c_size_t), ("windows", c_i64),
+        ("block", c_i64), ("block_dgt_length", c_i64),
     ]
 
 
@@ -70,6 +73,8 @@ SIGNATURES = [
      [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64, ctypes.c_int]),
     ("dgtns_plan_create_fir", ctypes.c_int,
      [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64, c_i64, c_i64]),
+    ("dgtns_plan_create_ola", ctypes.c_int,
+     [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64, c_i64, c_i64, c_i64]),
     ("dgtns_plan_info", ctypes.c_int, [c_vp, ctypes.POINTER(dgtns_plan_info_t)]),
     ("dgtns_plan_bind", ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_workspace_bytes", ctypes.c_int, [c_vp, ctypes.c_int, c_i64, ctypes.POINTER(ctypes.c_size_t)]),
@@ -133,6 +138,13 @@ def dgtns_plan_create_alg(L, a, M, lambda1, lambda2, dtype, max_batch, algorithm
 def dgtns_plan_create_fir(L, a, M, lambda1, lambda2, dtype, max_batch, g_start, g_len):
     h = c_vp()
     _call("dgtns_plan_create_fir", ctypes.byref(h), L, a, M, lambda1, lambda2, dtype, max_batch, g_start, g_len)
+    return h
+
+
+def dgtns_plan_create_ola(L, a, M, lambda1, lambda2, dtype, max_batch, g_start, g_len, block):
+    h = c_vp()
+    _call("dgtns_plan_create_ola", ctypes.byref(h), L, a, M, lambda1, lambda2, dtype, max_batch, g_start, g_len,
+          block)
     return h
 
 

@@ -130,13 +130,14 @@ int dgtns_plan_create(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t
 }
 
 static int create_plan(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
-                       int dtype, int64_t max_batch, int algorithm, int64_t g_start, int64_t g_len) {
+                       int dtype, int64_t max_batch, int algorithm, int64_t g_start, int64_t g_len,
+                       int64_t block = 0) {
   if (!plan) return fail(DGTNS_EINVAL, "null plan pointer");
   if (max_batch > 65535) return fail(DGTNS_EINVAL, "max_batch above 65535");
   dgtns_plan_s* h = new (std::nothrow) dgtns_plan_s();
   if (!h) return fail(DGTNS_EINVAL, "out of host memory");
   std::string err;
-  int rc = plan_make(L, a, M, lambda1, lambda2, dtype, max_batch, algorithm, &h->p, &err, g_start, g_len);
+  int rc = plan_make(L, a, M, lambda1, lambda2, dtype, max_batch, algorithm, &h->p, &err, g_start, g_len, block);
   if (rc) {
     delete h;
     return fail(rc, err);
@@ -148,12 +149,18 @@ static int create_plan(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_
 int dgtns_plan_create_alg(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
                           int dtype, int64_t max_batch, int algorithm) {
   if (algorithm == kAlgFir) return fail(DGTNS_EINVAL, "FIR plans are created with dgtns_plan_create_fir");
+  if (algorithm == kAlgShearOla) return fail(DGTNS_EINVAL, "shear-OLA plans are created with dgtns_plan_create_ola");
   return create_plan(plan, L, a, M, lambda1, lambda2, dtype, max_batch, algorithm, 0, 0);
 }
 
 int dgtns_plan_create_fir(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
                           int dtype, int64_t max_batch, int64_t g_start, int64_t g_len) {
   return create_plan(plan, L, a, M, lambda1, lambda2, dtype, max_batch, kAlgFir, g_start, g_len);
+}
+
+int dgtns_plan_create_ola(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
+                          int dtype, int64_t max_batch, int64_t g_start, int64_t g_len, int64_t block) {
+  return create_plan(plan, L, a, M, lambda1, lambda2, dtype, max_batch, kAlgShearOla, g_start, g_len, block);
 }
 
 int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info) {
@@ -167,6 +174,8 @@ int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info) {
   info->windows = P.nw;
   info->max_batch = P.max_batch;
   info->persistent_bytes = P.off.total;
+  info->block = P.ola_Lb;
+  info->block_dgt_length = P.ola_Lx;
   return DGTNS_OK;
 }
 
@@ -178,6 +187,46 @@ int dgtns_workspace_bytes(dgtns_plan plan, int op, int64_t B, size_t* bytes) {
   return DGTNS_OK;
 }
 
+// The plan's tables at byte offset base of the persistent image (a shear-OLA
+// plan: its inner plan's block at off.inner, then the block phases).
+static void fill_image(const Plan& P, std::vector<unsigned char>& img, size_t base) {
+  if (P.branch == kShearOla) {
+    fill_image(*P.inner, img, base + P.off.inner);
+    put_tab(img, base + P.off.fir_ph, P.fir_ph, P.dtype);
+    return;
+  }
+  const int dt = P.dtype;
+  put_tab(img, base + P.off.tw_d, P.tw_d, dt);
+  put_tab(img, base + P.off.tw_m, P.tw_m, dt);
+  if (P.off.fir_ph) put_tab(img, base + P.off.fir_ph, P.fir_ph, dt);
+  if (P.longd) {
+    put_tab(img, base + P.off.tw_d1, P.tw_d1, dt);
+    put_tab(img, base + P.off.tw_d2, P.tw_d2, dt);
+    if (dt == 0) {
+      put_tab(img, base + P.off.tw_d1_64, P.tw_d1, 1);
+      put_tab(img, base + P.off.tw_d2_64, P.tw_d2, 1);
+    }
+  }
+  if (P.off.chirp1) put_tab(img, base + P.off.chirp1, P.chirp1, dt);
+  if (P.branch == kFreqShear) {
+    put_tab(img, base + P.off.tw_1, P.tw_1, dt);
+    put_tab(img, base + P.off.tw_2, P.tw_2, dt);
+    put_tab(img, base + P.off.tw_L, P.tw_L, dt);
+    put_tab(img, base + P.off.chirp0, P.chirp0, dt);
+  } else {
+    put_tab(img, base + P.off.post_E, P.post_E, dt);
+    std::memcpy(img.data() + base + P.off.post_rho, P.post_rho.data(), P.post_rho.size() * sizeof(int32_t));
+  }
+  if (dt == 0) {
+    put_tab(img, base + P.off.tw_d64, P.tw_d, 1);
+    put_tab(img, base + P.off.tw_m64, P.tw_m, 1);
+    if (P.branch == kFreqShear) {
+      put_tab(img, base + P.off.tw_1_64, P.tw_1, 1);
+      put_tab(img, base + P.off.tw_2_64, P.tw_2, 1);
+    }
+  }
+}
+
 int dgtns_plan_bind(dgtns_plan plan, void* dev, size_t bytes, void* stream) {
   if (!plan || !dev) return fail(DGTNS_EINVAL, "null argument");
   Plan& P = plan->p;
@@ -185,36 +234,7 @@ int dgtns_plan_bind(dgtns_plan plan, void* dev, size_t bytes, void* stream) {
                                                              std::to_string(P.off.total) + " bytes");
   if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(DGTNS_EINVAL, "persistent memory must be 256-byte aligned");
   std::vector<unsigned char> img(P.off.total, 0);
-  const int dt = P.dtype;
-  put_tab(img, P.off.tw_d, P.tw_d, dt);
-  put_tab(img, P.off.tw_m, P.tw_m, dt);
-  if (P.off.fir_ph) put_tab(img, P.off.fir_ph, P.fir_ph, dt);
-  if (P.longd) {
-    put_tab(img, P.off.tw_d1, P.tw_d1, dt);
-    put_tab(img, P.off.tw_d2, P.tw_d2, dt);
-    if (dt == 0) {
-      put_tab(img, P.off.tw_d1_64, P.tw_d1, 1);
-      put_tab(img, P.off.tw_d2_64, P.tw_d2, 1);
-    }
-  }
-  if (P.off.chirp1) put_tab(img, P.off.chirp1, P.chirp1, dt);
-  if (P.branch == kFreqShear) {
-    put_tab(img, P.off.tw_1, P.tw_1, dt);
-    put_tab(img, P.off.tw_2, P.tw_2, dt);
-    put_tab(img, P.off.tw_L, P.tw_L, dt);
-    put_tab(img, P.off.chirp0, P.chirp0, dt);
-  } else {
-    put_tab(img, P.off.post_E, P.post_E, dt);
-    std::memcpy(img.data() + P.off.post_rho, P.post_rho.data(), P.post_rho.size() * sizeof(int32_t));
-  }
-  if (dt == 0) {
-    put_tab(img, P.off.tw_d64, P.tw_d, 1);
-    put_tab(img, P.off.tw_m64, P.tw_m, 1);
-    if (P.branch == kFreqShear) {
-      put_tab(img, P.off.tw_1_64, P.tw_1, 1);
-      put_tab(img, P.off.tw_2_64, P.tw_2, 1);
-    }
-  }
+  fill_image(P, img, 0);
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = check_hip(hipMemcpyAsync(dev, img.data(), img.size(), hipMemcpyHostToDevice, st), "plan upload");
   if (rc) return rc;
@@ -222,6 +242,10 @@ int dgtns_plan_bind(dgtns_plan plan, void* dev, size_t bytes, void* stream) {
   if (rc) return rc;
   P.dev = dev;
   P.window_set = false;
+  if (P.inner) {
+    P.inner->dev = static_cast<char*>(dev) + P.off.inner;
+    P.inner->window_set = false;
+  }
   return DGTNS_OK;
 }
 
@@ -237,6 +261,7 @@ int dgtns_set_window(dgtns_plan plan, const void* g_dev, void* ws, size_t ws_byt
   rc = P.dtype == 0 ? set_window_c64(P, g, w, l, st) : set_window_c128(P, g, w, l, st);
   if (rc) return rc;
   P.window_set = true;
+  if (P.inner) P.inner->window_set = true;
   return DGTNS_OK;
 }
 
@@ -259,6 +284,7 @@ int dgtns_forward_batch(dgtns_plan plan, const void* const* f_list, int real_inp
   int rc = check_call(plan, B, ws, ws_bytes, DGTNS_OP_FORWARD, &l);
   if (rc) return rc;
   if (!f_list || !c_list) return fail(DGTNS_EINVAL, "null pointer list");
+  if (plan->p.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "shear-OLA plans have no list-batched forward");
   if (B > DGTNS_MAX_LIST_BATCH) return fail(DGTNS_EINVAL, "list batch above DGTNS_MAX_LIST_BATCH");
   for (int64_t k = 0; k < B; ++k)
     if (!f_list[k] || !c_list[k]) return fail(DGTNS_EINVAL, "null signal or coefficient pointer in list");
@@ -276,6 +302,7 @@ int dgtns_adjoint(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, vo
   if (rc) return rc;
   if (!f_dev || !c_dev) return fail(DGTNS_EINVAL, "null signal or coefficient pointer");
   const Plan& P = plan->p;
+  if (P.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "shear-OLA plans compute the forward transform only");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   if (P.dtype == 0) return adjoint_c64(P, c_dev, f_dev, B, w, l, st);
@@ -289,6 +316,7 @@ int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, vo
   if (rc) return rc;
   if (!f_dev || !gc_dev || !gg_dev) return fail(DGTNS_EINVAL, "null argument");
   const Plan& P = plan->p;
+  if (P.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "shear-OLA plans compute the forward transform only");
   if (P.pi != 1) return fail(DGTNS_EUNSUPPORTED, "window gradient is implemented for p = 1 of the sheared lattice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
@@ -303,7 +331,7 @@ static int dual_or_tight(dgtns_plan plan, const void* g_dev, void* out_dev, doub
   if (rc) return rc;
   if (!g_dev || !out_dev || !bounds_dev) return fail(DGTNS_EINVAL, "null argument");
   const Plan& P = plan->p;
-  if (P.branch == kMultiwindow || P.branch == kFir)
+  if (P.branch == kMultiwindow || P.branch == kFir || P.branch == kShearOla)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are computed with shear-algorithm plans");
   if (P.pi > kDualMaxP)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p <= 8 of the sheared lattice");

@@ -1,0 +1,92 @@
+// Shear-OLA algorithm (Section 4): the shear algorithm on blocks of the
+// signal, combined by overlap-add.  For a window supported on
+// n a + s + [0, L_g) (mod L) the coefficients of eq. (DGT) split by blocks of
+// L_b samples:
+//     c(m, n) = sum_b sum_{l in block b} f(l) conj(g(l - n a)) exp(-2 pi i l (m + w(n)) / M).
+// Block b is zero-extended into a signal x_b of length L_x whose sample j is
+// global sample o_b + j, o_b = b L_b - J0, the block itself at j in
+// [J0, J0 + L_b).  Its DGT on the same lattice at length L_x, with the window
+// g_loc(i) = g(s + i) for i < L_g (0 up to L_x), gives at local position n'
+// (global n = b L_b / a - P0 + n') exactly the block's share of c(m, n)
+// times exp(2 pi i o_b (m + w(n)) / M), since P0 and L_b / a are multiples of
+// lambda2 (so w(n') = w(n)) and J0 >= L_g - a keeps windows that wrap around
+// L_x off the block's samples.
+#pragma once
+#include "kernels.hpp"
+
+namespace dgtns {
+
+template <typename C> struct OlaArgs {
+  const void* x;       // signals, xs samples apart
+  long long xs;
+  int real_in;
+  C* X;                // zero-extended blocks [B Nb][Lx]
+  const C* cl;         // block coefficients [B Nb][Nx][M]
+  C* c;                // coefficients [B][N][M], cs values apart
+  long long cs;
+  const C* ph;         // exp(-2 pi i e / (lambda2 M)), e in Z_{lambda2 M}
+  long long L, Lb, Lx, J0;
+  int a, M, N, Nb, Nx, P0, lam1, lam2;
+};
+
+// X[k Nb + b][j] = f_k(b L_b - J0 + j) for j in [J0, J0 + L_b), else 0.
+// grid (ceil(Lx / kThreads), B Nb).
+template <typename C>
+__global__ void __launch_bounds__(kThreads) k_ola_gather(OlaArgs<C> A) {
+  const long long j = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (j >= A.Lx) return;
+  const long long kb = blockIdx.y;
+  const long long k = kb / A.Nb, b = kb - k * A.Nb;
+  C v = czero<C>();
+  if (j >= A.J0 && j < A.J0 + A.Lb) v = load_sig<C>(A.x, A.real_in, k * A.xs + b * A.Lb + (j - A.J0));
+  A.X[kb * A.Lx + j] = v;
+}
+
+// c_k(m, n) = sum over the blocks b whose local positions n' = (n + P0 -
+// b L_b / a) mod N lie in Z_Nx of exp(-2 pi i o_b (m lambda2 + kn) /
+// (lambda2 M)) cl[k Nb + b][n'][m], kn = n lambda1 mod lambda2, in a fixed
+// order (no atomics).  grid (ceil(N M / kThreads), B).
+template <typename C>
+__global__ void __launch_bounds__(kThreads) k_ola_combine(OlaArgs<C> A) {
+  const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long NM = (long long)A.N * A.M;
+  if (idx >= NM) return;
+  const int n = int(idx / A.M), m = int(idx - (long long)n * A.M);
+  const long long k = blockIdx.y;
+  const int Q = int(A.Lb / A.a);
+  int t = n + A.P0;
+  if (t >= A.N) t -= A.N;
+  const int bh = t / Q, n00 = t - bh * Q;
+  const long long PM = (long long)A.lam2 * A.M;
+  const long long mk = (long long)m * A.lam2 + ((long long)n * A.lam1) % A.lam2;
+  C acc = czero<C>();
+  for (int i = 0;; ++i) {
+    const int np = n00 + i * Q;   // np < Nx < N = Nb Q, so i < Nb
+    if (np >= A.Nx) break;
+    int b = bh - i;
+    if (b < 0) b += A.Nb;
+    long long ob = ((long long)b * A.Lb - A.J0) % PM;
+    if (ob < 0) ob += PM;
+    const C w = A.ph[(ob * mk) % PM];
+    acc = cadd(acc, cmul(w, A.cl[((k * A.Nb + b) * A.Nx + np) * (long long)A.M + m]));
+  }
+  A.c[k * A.cs + idx] = acc;
+}
+
+// Block window g_loc(i) = g((s + i) mod L) for i < L_g, 0 for i in [L_g, L_x)
+// (FP64).  grid ceil(Lx / kThreads).
+template <int Unused = 0>
+__global__ void __launch_bounds__(kThreads) k_ola_window(const double2* g, double2* gl, long long L, long long s,
+                                                        long long Lg, long long Lx) {
+  const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= Lx) return;
+  double2 v = make_double2(0, 0);
+  if (i < Lg) {
+    long long l = (s + i) % L;
+    if (l < 0) l += L;
+    v = g[l];
+  }
+  gl[i] = v;
+}
+
+}  // namespace dgtns

@@ -15,6 +15,7 @@
 #include "kernels_fast.hpp"
 #include "kernels_long.hpp"
 #include "kernels_fir.hpp"
+#include "kernels_ola.hpp"
 #include "plan.hpp"
 
 namespace dgtns {
@@ -168,6 +169,8 @@ inline int block_width(long long n, int es, int maxw = 16) {
 
 struct Layout {
   size_t H = 0, F = 0, Y = 0, part = 0, G = 0, U = 0, V = 0, total = 0;
+  // shear-OLA: zero-extended blocks, their coefficients, the inner workspace
+  size_t ola_x = 0, ola_c = 0, inner = 0;
 };
 
 // Values of the intermediate h per signal: q offsets x Mi columns x d
@@ -193,6 +196,20 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = al256(o + bytes); return r; };
   const bool fs = P.branch == kFreqShear;
+  if (P.branch == kShearOla) {
+    // blocks and block coefficients, then the inner plan's own workspace
+    const long long Bi = B * P.ola_Nb;
+    if (op == DGTNS_OP_FORWARD) {
+      l.ola_x = take(es * size_t(P.ola_Lx) * Bi);
+      l.ola_c = take(es * size_t(P.ola_Nx) * size_t(P.M) * Bi);
+      l.inner = take(ws_layout(*P.inner, op, Bi).total);
+    } else if (op == DGTNS_OP_SET_WINDOW) {
+      l.ola_x = take(16 * size_t(P.ola_Lx));   // the block window, FP64
+      l.inner = take(ws_layout(*P.inner, op, 1).total);
+    }
+    l.total = o < 256 ? 256 : o;
+    return l;
+  }
   switch (op) {
     case DGTNS_OP_FORWARD:
     case DGTNS_OP_ADJOINT:
@@ -680,9 +697,17 @@ int run_fir_adj(const Plan& P, const C* c, C* f, long long B, C* Y, hipStream_t 
 }
 
 template <typename C>
+int run_ola_fwd(const Plan& P, const void* f, int real_in, C* c, long long B, char* ws, const Layout& l,
+                hipStream_t st);
+
+template <typename C>
 int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, char* ws, const Layout& l,
                  hipStream_t st, const void* const* flist = nullptr, void* const* clist = nullptr) {
   if (P.branch == kFir) return run_fir_fwd<C>(P, f, real_in, c, B, st, flist, clist);
+  if (P.branch == kShearOla) {
+    if (flist || clist) return fail(DGTNS_EUNSUPPORTED, "shear-OLA plans have no list-batched forward");
+    return run_ola_fwd<C>(P, f, real_in, c, B, ws, l, st);
+  }
   C* H = reinterpret_cast<C*>(ws + l.H);
   int rc;
   // the workspace layout of this batch size decides the path (ws_layout):
@@ -720,6 +745,39 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
   }
   if (rc) return rc;
   return run_rows<C>(P, H, c, B, false, st, clist);
+}
+
+// Shear-OLA block window g_loc (FP64, L_x values at gl) from the length-L
+// window g.
+inline int ola_block_window(const Plan& P, const double2* g, double2* gl, hipStream_t st) {
+  return launch_raw(k_ola_window<>, dim3(cdiv(P.ola_Lx, kThreads)), dim3(kThreads), 0, st, "OLA block window", g, gl,
+                    (long long)P.L, (long long)P.ola_s, (long long)P.fir_len, (long long)P.ola_Lx);
+}
+
+// Shear-OLA forward (kernels_ola.hpp): zero-extended blocks, the shear
+// algorithm on all of them as one batch of the inner plan, overlap-add.
+template <typename C>
+int run_ola_fwd(const Plan& P, const void* f, int real_in, C* c, long long B, char* ws, const Layout& l,
+                hipStream_t st) {
+  const Plan& Q = *P.inner;
+  OlaArgs<C> A;
+  std::memset(&A, 0, sizeof(A));
+  A.x = f; A.xs = P.L; A.real_in = real_in;
+  A.X = reinterpret_cast<C*>(ws + l.ola_x);
+  A.cl = reinterpret_cast<C*>(ws + l.ola_c);
+  A.c = c; A.cs = P.M * P.N;
+  A.ph = tab<C>(P, P.off.fir_ph);
+  A.L = P.L; A.Lb = P.ola_Lb; A.Lx = P.ola_Lx; A.J0 = P.ola_J0;
+  A.a = int(P.a); A.M = int(P.M); A.N = int(P.N); A.Nb = int(P.ola_Nb); A.Nx = int(P.ola_Nx);
+  A.P0 = int(P.ola_P0); A.lam1 = int(P.lam1); A.lam2 = int(P.lam2);
+  const long long Bi = B * P.ola_Nb;
+  int rc = launch_raw(k_ola_gather<C>, dim3(cdiv(P.ola_Lx, kThreads), unsigned(Bi)), dim3(kThreads), 0, st,
+                      "OLA blocks", A);
+  if (rc) return rc;
+  rc = forward_impl<C>(Q, A.X, 0, const_cast<C*>(A.cl), Bi, ws + l.inner, ws_layout(Q, DGTNS_OP_FORWARD, Bi), st);
+  if (rc) return rc;
+  return launch_raw(k_ola_combine<C>, dim3(cdiv(P.N * P.M, kThreads), unsigned(B)), dim3(kThreads), 0, st,
+                    "OLA overlap-add", A);
 }
 
 template <typename C>

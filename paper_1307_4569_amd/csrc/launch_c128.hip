@@ -25,6 +25,12 @@ int grad_c128(const Plan& P, const void* f, const void* gc, void* gg, long long 
 }
 
 int set_window_c128(const Plan& P, const double2* g, char* ws, const Layout& l, hipStream_t st) {
+  if (P.branch == kShearOla) {
+    double2* gl = reinterpret_cast<double2*>(ws + l.ola_x);
+    const int rc = ola_block_window(P, g, gl, st);
+    if (rc) return rc;
+    return set_window_c128(*P.inner, gl, ws + l.inner, ws_layout(*P.inner, DGTNS_OP_SET_WINDOW, 1), st);
+  }
   return window_zak<double2>(P, g, mtab<double2>(P, P.off.zc), nullptr, ws, l, st);
 }
 

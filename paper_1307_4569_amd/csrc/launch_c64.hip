@@ -25,6 +25,12 @@ int grad_c64(const Plan& P, const void* f, const void* gc, void* gg, long long B
 }
 
 int set_window_c64(const Plan& P, const double2* g, char* ws, const Layout& l, hipStream_t st) {
+  if (P.branch == kShearOla) {
+    double2* gl = reinterpret_cast<double2*>(ws + l.ola_x);
+    const int rc = ola_block_window(P, g, gl, st);
+    if (rc) return rc;
+    return set_window_c64(*P.inner, gl, ws + l.inner, ws_layout(*P.inner, DGTNS_OP_SET_WINDOW, 1), st);
+  }
   return window_zak<float2>(P, g, mtab<float2>(P, P.off.zc), nullptr, ws, l, st);
 }
 

@@ -1,6 +1,7 @@
 // Lattice planner: normal form checks, shear factorisation and tables.
 #include "plan.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <map>
@@ -210,12 +211,14 @@ static void fill_chirp(int64_t L, int64_t s, std::vector<double>* v) {
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int dtype,
-              int64_t max_batch, int algorithm, Plan* P, std::string* err, int64_t fir_start, int64_t fir_len) {
+              int64_t max_batch, int algorithm, Plan* P, std::string* err, int64_t fir_start, int64_t fir_len,
+              int64_t ola_block) {
   // status codes mirror include/dgtns.h
   const int kEInval = 1, kELattice = 2, kEUnsupported = 4;
   if (dtype != 0 && dtype != 1) { *err = "dtype must be DGTNS_C64 or DGTNS_C128"; return kEInval; }
-  if (algorithm != kAlgShear && algorithm != kAlgMultiwindow && algorithm != kAlgFir) {
-    *err = "algorithm must be DGTNS_ALG_SHEAR, DGTNS_ALG_MULTIWINDOW or DGTNS_ALG_FIR";
+  if (algorithm != kAlgShear && algorithm != kAlgMultiwindow && algorithm != kAlgFir &&
+      algorithm != kAlgShearOla) {
+    *err = "algorithm must be DGTNS_ALG_SHEAR, DGTNS_ALG_MULTIWINDOW, DGTNS_ALG_FIR or DGTNS_ALG_SHEAR_OLA";
     return kEInval;
   }
   if (L < 1 || a < 1 || M < 1 || max_batch < 1) { *err = "L, a, M and max_batch must be positive"; return kEInval; }
@@ -240,6 +243,66 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   {
     const char* gen = std::getenv("DGTNS_GENERIC");
     p.generic = gen && gen[0] == '1';
+  }
+  if (algorithm == kAlgShearOla) {
+    // Shear-OLA (Section 4): blocks of ola_block samples, each zero-extended
+    // and transformed by the shear algorithm at a length L_x on the same
+    // lattice, then overlap-added with the phase of the block's position
+    if (fir_len < 1 || fir_len > L) { *err = "window support length must be in [1, L]"; return kEInval; }
+    const int64_t Lb = ola_block;
+    if (Lb < 1 || L % Lb) { *err = "block length must divide L"; return kEInval; }
+    if (Lb % (lam2 * a)) { *err = "block length must be a multiple of lambda2 a"; return kEInval; }
+    const int64_t Nb = L / Lb;
+    if (max_batch * Nb > 65535) { *err = "max_batch * L / block above 65535"; return kEInval; }
+    // signed window start s: the support of position n is n a + s + [0, g_len)
+    int64_t sg = fmod64(fir_start, L);
+    if (2 * sg >= L) sg -= L;
+    // local positions before the block, P0 (a multiple of lambda2 so that the
+    // offsets w(n) of the block's DGT are the global ones); the block starts
+    // at local sample J0 = P0 a - s >= g_len - a, so no window that wraps
+    // around the block DGT's length reaches the block's samples
+    const int64_t need = std::max<int64_t>(fir_len - a, 0) + sg;
+    int64_t P0 = need > 0 ? (need + a - 1) / a : 0;
+    P0 = (P0 + lam2 - 1) / lam2 * lam2;
+    const int64_t J0 = P0 * a - sg;
+    // the least feasible length L_x = N_x a >= J0 + L_b of the block DGT
+    const int64_t step = lam2 * lcm64(a, M) / a;   // N_x steps between feasible lengths
+    int64_t Nx = (J0 + Lb + a - 1) / a;
+    Nx = (Nx + step - 1) / step * step;
+    auto in = std::make_shared<Plan>();
+    bool ok = false;
+    std::string e2;
+    // L_x + g_len <= L: a window offset in (-L_x, L_x) cannot alias the
+    // support of the global window modulo L
+    for (int k = 0; k < 64 && Nx * a + fir_len <= L; ++k, Nx += step) {
+      if (plan_make(Nx * a, a, M, lam1, lam2, dtype, max_batch * Nb, kAlgShear, in.get(), &e2) == 0) {
+        ok = true;
+        break;
+      }
+    }
+    if (!ok) {
+      *err = "no feasible block DGT length below L for this block length (" + e2 + ")";
+      return kEUnsupported;
+    }
+    p.branch = kShearOla;
+    p.sh = in->sh;
+    p.ai = in->ai; p.Mi = in->Mi; p.bi = in->bi; p.Ni = in->Ni;
+    p.ci = in->ci; p.pi = in->pi; p.qw = in->qw; p.qi = in->qi; p.di = in->di;
+    p.fir_start = fmod64(fir_start, L);
+    p.fir_len = fir_len;
+    p.ola_Lb = Lb; p.ola_Nb = Nb; p.ola_Nx = Nx; p.ola_Lx = Nx * a; p.ola_P0 = P0; p.ola_J0 = J0; p.ola_s = sg;
+    p.fir_ph.resize(2 * lam2 * M);
+    for (int64_t e = 0; e < lam2 * M; ++e) unit_root(-e, lam2 * M, &p.fir_ph[2 * e], &p.fir_ph[2 * e + 1]);
+    const size_t es = dtype == 0 ? 8 : 16;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    p.off = Plan::Off();
+    p.off.inner = take(in->off.total);
+    p.off.fir_ph = take(es * lam2 * M);
+    p.off.bounds = take(16);
+    p.off.total = o;
+    p.inner = in;
+    return 0;
   }
   if (algorithm == kAlgFir) {
     // FIR-window algorithm: per time position the windowed samples folded

@@ -15,6 +15,7 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -52,8 +53,8 @@ int64_t lcm64(int64_t a, int64_t b);
 bool fft_schedule(int64_t n, FftSchedule* out);
 Shear shearfind(int64_t L, int64_t a, int64_t M, int64_t s, int64_t b, std::string* err);
 
-enum Branch { kSeparable = 0, kTimeShear = 1, kFreqShear = 2, kMultiwindow = 3, kFir = 4 };
-enum Algorithm { kAlgShear = 0, kAlgMultiwindow = 1, kAlgFir = 2 };
+enum Branch { kSeparable = 0, kTimeShear = 1, kFreqShear = 2, kMultiwindow = 3, kFir = 4, kShearOla = 5 };
+enum Algorithm { kAlgShear = 0, kAlgMultiwindow = 1, kAlgFir = 2, kAlgShearOla = 3 };
 
 struct Plan {
   // lattice
@@ -82,6 +83,15 @@ struct Plan {
   bool longd = false;
   // FIR-window algorithm: window support start, ..., start + fir_len - 1 (mod L)
   int64_t fir_start = 0, fir_len = 0;
+  // Shear-OLA (Section 4): ola_Nb blocks of ola_Lb samples, each zero-extended
+  // into a DGT of length ola_Lx = ola_Nx a on the same lattice (the inner
+  // plan).  Block b covers local time positions n' in Z_{ola_Nx}, global
+  // position n = b ola_Lb / a - ola_P0 + n' (ola_P0 a multiple of lambda2), and
+  // local sample j is global sample (b ola_Lb - ola_J0 + j) mod L; the block's
+  // own samples sit at j in [ola_J0, ola_J0 + ola_Lb).  ola_s: signed window
+  // start.
+  int64_t ola_Lb = 0, ola_Nb = 0, ola_Lx = 0, ola_Nx = 0, ola_P0 = 0, ola_J0 = 0, ola_s = 0;
+  std::shared_ptr<Plan> inner;
   int64_t d1 = 0, d2 = 0;
   FftSchedule fd1, fd2;
   int Wl = 1, Wm = 1;
@@ -95,7 +105,8 @@ struct Plan {
     size_t tw_d, tw_m, tw_1, tw_2, tw_L, chirp1, chirp0, post_E, post_rho, zc;   // plan dtype
     size_t tw_d64, tw_m64, tw_1_64, tw_2_64, tw_L64;                             // FP64 copies
     size_t tw_d1, tw_d2, tw_d1_64, tw_d2_64;                                     // long columns
-    size_t fir_ph;                                                               // FIR: lambda2 M phases
+    size_t fir_ph;                                                               // FIR, OLA: lambda2 M phases
+    size_t inner;                                                                // OLA: inner plan's block
     size_t bounds;  // 2 doubles
     size_t total;
   } off;
@@ -111,7 +122,7 @@ struct Plan {
 // Returns 0 on success, else an error status with a message in *err.
 int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int dtype,
               int64_t max_batch, int algorithm, Plan* p, std::string* err, int64_t fir_start = 0,
-              int64_t fir_len = 0);
+              int64_t fir_len = 0, int64_t ola_block = 0);
 
 // Coset window mu of the multiwindow algorithm: g_mu(l) = exp(2 pi i l sigma / L)
 // g(l - mu a) with sigma = (mu s) mod b (Prop. 5).

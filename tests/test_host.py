@@ -214,6 +214,45 @@ def test_fir_plans(lib):
     assert e.value.status == B.DGTNS_EINVAL
 
 
+def test_shear_ola_plans(lib):
+    """Shear-OLA plans (Section 4): the block DGT length is the least feasible
+    one of at least block + window support, the inner plan's constants are
+    reported, and the errors."""
+    from math import gcd
+    L, a, M, l1, l2 = 1048576, 128, 1024, 1, 4
+    for block in (32768, 65536, 131072):
+        h = B.dgtns_plan_create_ola(L, a, M, l1, l2, 0, 4, L - 1024, 2048, block)
+        i = B.dgtns_plan_info(h)
+        B.dgtns_plan_destroy(h)
+        Lx = i.block_dgt_length
+        assert i.branch == B.DGTNS_SHEAR_OLA and i.block == block
+        step = l2 * a * M // gcd(a, M)
+        assert Lx % step == 0 and Lx >= block + 2048
+        # the least such length: shorter candidates have no shear plan
+        for cand in range(-(-(block + 2048) // step) * step, Lx, step):
+            with pytest.raises(B.DgtnsError):
+                B.dgtns_plan_create(cand, a, M, l1, l2, 0, 1)
+        # the inner plan is a shear plan at that length
+        hi = B.dgtns_plan_create(Lx, a, M, l1, l2, 0, 1)
+        ii = B.dgtns_plan_info(hi)
+        B.dgtns_plan_destroy(hi)
+        assert (ii.s0, ii.s1, ii.c, ii.d, ii.p, ii.q) == (i.s0, i.s1, i.c, i.d, i.p, i.q)
+    h = B.dgtns_plan_create_fir(L, a, M, l1, l2, 0, 1, 0, 10)
+    assert B.dgtns_plan_info(h).block == 0
+    B.dgtns_plan_destroy(h)
+    for args, status in (((L, a, M, l1, l2, 0, 4, 0, 2048, 3000), B.DGTNS_EINVAL),      # does not divide L
+                         ((L, a, M, l1, l2, 0, 4, 0, 2048, 256), B.DGTNS_EINVAL),       # not a multiple of 4 a
+                         ((L, a, M, l1, l2, 0, 4, 0, 0, 32768), B.DGTNS_EINVAL),        # empty support
+                         ((L, a, M, l1, l2, 0, 40000, 0, 2048, 512), B.DGTNS_EINVAL),   # batch x blocks
+                         ((4096, 8, 32, 1, 2, 0, 1, 0, 64, 4096), B.DGTNS_EUNSUPPORTED)):  # one block
+        with pytest.raises(B.DgtnsError) as e:
+            B.dgtns_plan_create_ola(*args)
+        assert e.value.status == status, args
+    with pytest.raises(B.DgtnsError) as e:
+        B.dgtns_plan_create_alg(144, 6, 12, 1, 2, 0, 1, B.DGTNS_ALG_SHEAR_OLA)
+    assert e.value.status == B.DGTNS_EINVAL
+
+
 def test_error_paths_without_device(lib):
     with pytest.raises(B.DgtnsError) as e:
         B.dgtns_plan_create(100, 6, 12, 1, 2, 0, 1)
