@@ -200,7 +200,12 @@ def fir_bench(torch, dev, steps=20, with_shear=True):
     coeffs = w.batch * w.M * w.N
     out = {"workload": f"precision L={w.L} a={w.a} M={w.M} lambda={w.lam1}/{w.lam2} B={w.batch} real, "
                        "Hann window of length 2048"}
-    algs = [("fir", {"algorithm": "fir", "support": (w.L - 1024, 2048)})] + ([("shear", {})] if with_shear else [])
+    algs = [("fir", {"algorithm": "fir", "support": (w.L - 1024, 2048)})]
+    if with_shear:
+        algs += [("shear", {})]
+        # the shear algorithm on overlap-added blocks (Section 4)
+        algs += [(f"shear_ola_block{blk}", {"algorithm": "shear-ola", "support": (w.L - 1024, 2048), "block": blk})
+                 for blk in (32768, 131072)]
     for name, kw in algs:
         plan = Plan(*lat, dtype=torch.complex64, max_batch=w.batch, device=dev, **kw)
         plan.set_window(g)
@@ -208,6 +213,10 @@ def fir_bench(torch, dev, steps=20, with_shear=True):
         ms, _, kt = time_forward(plan, xr, c, steps, 3, torch, Bm)
         out[name] = {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3),
                      "kernels": {k: round(t / n, 4) for k, (n, t) in kt.items()}}
+        if kw.get("algorithm") == "shear-ola":
+            Lx = plan.info.block_dgt_length
+            out[name]["block_dgt_length"] = Lx
+            out[name]["rho"] = Lx / kw["block"]
         del plan, c
     fb = w.batch * (4 * w.L + 8 * w.M * w.N)
     out["fir"]["compulsory_GBps"] = round(fb / (out["fir"]["ms_per_step"] * 1e-3) / 1e9, 1)

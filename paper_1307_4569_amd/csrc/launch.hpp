@@ -520,7 +520,9 @@ RowArgs<C> row_args(const Plan& P, const C* H, C* c) {
   A.twm = tab<C>(P, P.off.tw_m);
   A.Mi = int(P.Mi); A.Ni = int(P.Ni);
   A.qw = int(P.qw); A.nw = int(P.nw);
-  A.R = block_width(P.Mi | 1, sizeof(C));
+  // rows per work-group of the runtime-schedule row kernels: enough rows that
+  // a work-group has work for its 512 threads when Mi is small
+  A.R = block_width(P.Mi | 1, sizeof(C), P.Mi < 32 ? 256 : 64);
   A.Sm = int(P.Mi | 1);
   A.fm = sched(P.fm);
   A.q = int(P.qi);
@@ -541,7 +543,9 @@ int run_rows(const Plan& P, const C* H, C* c, long long B, bool adjoint, hipStre
              void* const* clist = nullptr) {
   RowArgs<C> A = row_args<C>(P, H, c);
   // the adjoint writes h, the forward the coefficients
-  A.hstream = adjoint ? stream_h(P, B, sizeof(C)) : stream_c(P, B, sizeof(C));
+  // the forward of the frequency-shear branch scatters single coefficients
+  // (Alg. 1's output permutation): plain stores let the cache merge them
+  A.hstream = adjoint ? stream_h(P, B, sizeof(C)) : (P.branch == kFreqShear ? 0 : stream_c(P, B, sizeof(C)));
   A.ht = !adjoint && h_time_major<C>(P);
   if (clist) {
     A.list = 1;
