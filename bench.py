@@ -305,6 +305,9 @@ def serve_bench(nreq, torch, dev):
         torch.cuda.synchronize()
         log(f"serve {name}: capacity {mu:.0f} req/s, p50/p99 at 0.8 mu: "
             f"{res['load_0.8']['p50_ms']:.3f}/{res['load_0.8']['p99_ms']:.3f} ms")
+        failed = {k: v["failed"] for k, v in res.items() if v["failed"]}
+        if failed:
+            log(f"WARNING: serve {name}: failed requests {failed}")
         return res
 
     out["fp32_batched"] = run_server("fp32", torch.complex64, 4, 8, 2, sig32)

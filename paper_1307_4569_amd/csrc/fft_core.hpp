@@ -247,9 +247,9 @@ __device__ void fft_lds(C* buf, int tstride, const FftSched& fs, int ntr, const 
 // one wavefront: every lane loads all its butterflies before storing any, so
 // the pass can run in place (a wavefront's LDS accesses complete in program
 // order) and needs no work-group barrier.  tw: the length-n twiddle table
-// exp(-2 pi i k / n) (global memory).
+// exp(-2 pi i k / n) (in LDS for the factorisation kernel).
 template <typename C, int R, bool INV, int MV>
-__device__ __noinline__ void wrt_pass(C* buf, int n, int Ns, const C* tw, int lane) {
+__device__ __forceinline__ void wrt_pass(C* buf, int n, int Ns, const C* tw, int lane) {
   constexpr int KB = MV / R + 1;   // butterflies per lane: ceil(n / (64 R)) <= KB
   const int nb = n / R;
   const int twstep = n / (Ns * R);

@@ -273,8 +273,9 @@ template <typename C> struct ColAdjArgs {
 // tile, after which each wavefront transforms its own column in place
 // (fft_wave_rt) with no further work-group barrier.  The column spectrum
 // stays in registers (MV values per lane) across the q window products.
+// TWL: the twiddle table is copied into LDS after the tile (when it fits).
 // grid (ceil(Mi / 8) * nsplit, B), 512 threads.
-template <typename C, int MV>
+template <typename C, int MV, bool TWL>
 __global__ void __launch_bounds__(kThreads) k_fwd_cols_wr(ColArgs<C> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
@@ -297,11 +298,17 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_wr(ColArgs<C> A) {
     }
     lds[cc * Sd + t] = v;
   }
+  const C* twl = A.twd;
+  if constexpr (TWL) {
+    C* t = lds + W * Sd;
+    for (int e = tid; e < d; e += kThreads) t[e] = A.twd[e];
+    twl = t;
+  }
   __syncthreads();
   const int r = r0 + wave;
   const int rr = r < Mi ? r : 0;
   C* buf = lds + wave * Sd;
-  fft_wave_rt<C, false, MV>(buf, A.fd, A.twd, lane);
+  fft_wave_rt<C, false, MV>(buf, A.fd, twl, lane);
   C X[MV];
 #pragma unroll
   for (int e = 0; e < MV; ++e) {
@@ -318,11 +325,11 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_wr(ColArgs<C> A) {
       const int nu = lane + 64 * e;
       if (nu < d) {
         C z = zrow[nu];
-        if (v0 < 0) z = cmulc(z, A.twd[nu]);
+        if (v0 < 0) z = cmulc(z, twl[nu]);
         buf[nu] = cmul(X[e], z);
       }
     }
-    fft_wave_rt<C, true, MV>(buf, A.fd, A.twd, lane);
+    fft_wave_rt<C, true, MV>(buf, A.fd, twl, lane);
     if (r < Mi) {
       C* hb = A.H + bo * A.hs + ((long long)n0 * Mi + r) * d;
 #pragma unroll

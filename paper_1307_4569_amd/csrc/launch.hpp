@@ -461,7 +461,9 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
   }
   // other 7-smooth d up to 1152 (p = 1): one wavefront per column
   if (P.pi == 1 && !P.generic && P.di <= 1152) {
-    const size_t lw = es * 8 * size_t(A.Sd);
+    // the twiddle table joins the tile in LDS when both fit in 160 KiB
+    const size_t lt = es * 8 * size_t(A.Sd), lw = lt + es * size_t(P.di);
+    const bool twl = lw <= 160 * 1024;
     const long long nblk = cdiv(P.Mi, 8);
     // small batches: split the q offsets until every work-group slot is used once
     long long ns = (512 + nblk * B - 1) / (nblk * B);
@@ -469,9 +471,10 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
     if (ns < 1) ns = 1;
     A.nsplit = int(ns);
     dim3 gw(unsigned(nblk * ns), unsigned(B));
-    if (P.di <= 320) return launch(k_fwd_cols_wr<C, 5>, gw, lw, st, A, "factorisation kernel");
-    if (P.di <= 576) return launch(k_fwd_cols_wr<C, 9>, gw, lw, st, A, "factorisation kernel");
-    return launch(k_fwd_cols_wr<C, 18>, gw, lw, st, A, "factorisation kernel");
+    if (!twl) return launch(k_fwd_cols_wr<C, 18, false>, gw, lt, st, A, "factorisation kernel");
+    if (P.di <= 320) return launch(k_fwd_cols_wr<C, 5, true>, gw, lw, st, A, "factorisation kernel");
+    if (P.di <= 576) return launch(k_fwd_cols_wr<C, 9, true>, gw, lw, st, A, "factorisation kernel");
+    return launch(k_fwd_cols_wr<C, 18, true>, gw, lw, st, A, "factorisation kernel");
   }
   const size_t lds = P.pi == 1 ? es * (P.di + size_t(P.W) * A.Sd)
                                : es * (P.di + size_t(P.W) * A.Sd * (P.pi + 1));

@@ -276,3 +276,27 @@ def test_pipelined_batches_match_single_launch(dtype, monkeypatch):
                           g.numpy().astype(np.complex64).astype(np.complex128) if dtype == torch.complex64 else g.numpy(),
                           w.a, w.M, w.lam1, w.lam2, columns=[0, 1000, 4095])
     assert rel(out["pipeline"][0][B - 1, [0, 1000, 4095]].cpu().numpy(), ref) < TOL[dtype]
+
+
+# Column lengths d = 9 2^k (72 to 1152) of the serving plans: the one-wavefront
+# runtime-schedule factorisation (FP64 at d = 1152 keeps its twiddle table in
+# global memory, as the LDS tile then fills the work-group's 160 KiB).
+SERVING_D = [(36864, 64, 512, 1, 3), (73728, 64, 512, 2, 3), (147456, 64, 512, 1, 3), (294912, 64, 512, 2, 3),
+             (294912, 32, 256, 1, 3), (294912, 32, 256, 1, 2)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_serving_column_lengths_sampled(dtype, kernel_path):
+    single = dtype == torch.complex64
+    B = 2
+    for lat in SERVING_D:
+        L, a, M, l1, l2 = lat
+        plan = make_plan(*lat, dtype, B)
+        f, g = inputs(L, a, M, B, single, seed=7)
+        plan.set_window(torch.tensor(g))
+        c = plan.forward(torch.tensor(f)).cpu().numpy()
+        N = L // a
+        cols = list(range(0, N, max(1, N // 24))) + [N - 1]
+        e = max(rel(c[k, cols], oracle.dgt_fold(f[k], g, a, M, l1, l2, columns=cols)) for k in range(B))
+        print("serving d", kernel_path, dtype, lat, plan.info.branch, plan.info.d, e)
+        assert e < TOL[dtype], (lat, e)
