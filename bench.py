@@ -415,7 +415,7 @@ def main():
             traffic = ent["bytes_per_launch"]
 
     out = {
-        "metric": "nonsep DGT coeffs/s FP32 vs FP64 (rel err <=1e-5); serve p50/p99 latency",
+        "metric": "nonsep DGT coeffs/s FP32 vs FP64 (rel err \u22641e-5); serve p50/p99 latency",
         "value": value,
         "unit": "coeffs/s",
         "n_gpus": 1,
