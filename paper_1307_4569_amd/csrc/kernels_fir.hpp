@@ -156,6 +156,114 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd_w(FirArgs<C> A) {
 }
 
 // ----------------------------------------------------------------------------
+// Forward, power-of-two M = MI, with the work-group's signal span and the
+// window staged in LDS.  The P = 8 TPW positions of a work-group read the
+// S = (P - 1) a + L_g samples from (n_first a + start) mod L on, so the span
+// is loaded once, coalesced, and every wave folds from LDS.  The phase
+// exp(-2 pi i (eb + j kn) / (lambda2 M)) of sample j = jk + t M of bin k
+// splits into the bin factor exp(-2 pi i (eb + jk kn) / (lambda2 M)), applied
+// once to the folded sum, and the tap factor exp(-2 pi i t kn / lambda2),
+// the same for every bin of a transform.  The span and window alias the FFT
+// exchange areas: a barrier separates the fold from the transforms.
+// grid (ceil(N / (8 TPW)), B), 512 threads; LDS max(exchange, (S + L_g) C).
+// ----------------------------------------------------------------------------
+template <typename C, int MI, bool HS, int NT>
+__global__ void __launch_bounds__(kThreads, 4) k_fir_fwd_ws(FirArgs<C> A) {
+  using I = WInfo<MI>;
+  constexpr int E = I::E, T = I::T, TPW = I::TPW, P = 8 * TPW;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
+  const long long bo = blockIdx.y;
+  const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
+  const long long xoff = A.list ? 0 : bo * A.xs;
+  const int nf = blockIdx.x * P, S = (P - 1) * A.a + A.Lg;
+  // 1. span f((base0 + i) mod L), i < S, and window gw[j], j < L_g
+  {
+    const long long base0 = ((long long)nf * A.a + A.start) % A.L;
+    C* span = lds;
+    for (int i = tid; i < S; i += kThreads) {
+      long long idx = base0 + i;
+      if (idx >= A.L) idx %= A.L;
+      span[i] = load_sig<C>(xsrc, A.real_in, xoff + idx);
+    }
+    C* win = lds + S;
+    for (int j = tid; j < A.Lg; j += kThreads) win[j] = A.gw[j];
+  }
+  __syncthreads();
+  // 2. fold: bin k = l + T e of position n
+  const int p = wave * TPW + tt, n = nf + p;
+  const FirPos q = fir_pos(A, n < A.N ? n : A.N - 1);
+  const int M = A.M, PM = A.lam2 * A.M, tstep = M * q.kn;   // tap phase step, < PM
+  const C* sp = lds + p * A.a;
+  const C* win = lds + S;
+  C v[E];
+  if constexpr (NT > 0) {
+    C wt[NT];
+    wt[0] = mk<C>(1, 0);
+    {
+      int te = 0;
+#pragma unroll
+      for (int t = 1; t < NT; ++t) {
+        te += tstep;
+        if (te >= PM) te -= PM;
+        wt[t] = q.kn ? A.ph[te] : mk<C>(1, 0);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int jk = (l + T * e - q.bm) & (MI - 1);
+      C acc = jk < A.Lg ? cmul(sp[jk], win[jk]) : czero<C>();
+#pragma unroll
+      for (int t = 1; t < NT; ++t) {
+        const int j = jk + t * MI;
+        if (j < A.Lg) acc = cadd(acc, cmul(cmul(sp[j], win[j]), wt[t]));
+      }
+      v[e] = acc;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int jk = (l + T * e - q.bm) & (MI - 1);
+      C acc = czero<C>();
+      int te = 0;
+      for (int j = jk; j < A.Lg; j += MI) {
+        C u = cmul(sp[j], win[j]);
+        if (te) u = cmul(u, A.ph[te]);
+        acc = cadd(acc, u);
+        te += tstep;
+        if (te >= PM) te -= PM;
+      }
+      v[e] = acc;
+    }
+  }
+  if (q.kn) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int jk = (l + T * e - q.bm) & (MI - 1);
+      int be = q.eb + jk * q.kn;                          // jk kn < PM
+      if (be >= PM) be -= PM;
+      v[e] = cmul(v[e], A.ph[be]);
+    }
+  }
+  WTw<C, MI> tw;
+  tw.load(A.twm, l);
+  __syncthreads();   // the exchange areas alias the span and the window
+  C* ex = lds + (wave * TPW + tt) * WEx<C, MI>::EX;
+  wave_fft<C, MI, false>(v, ex, l, tw);
+  if (n < A.N) {
+    C* row = (A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs) + (long long)n * MI;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if constexpr (HS)
+        st_stream(row + l + T * e, v[e]);
+      else
+        row[l + T * e] = v[e];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Forward, any in-LDS M: R time positions per work-group, LDS transforms.
 // grid (ceil(N / R), B), 512 threads.
 // ----------------------------------------------------------------------------

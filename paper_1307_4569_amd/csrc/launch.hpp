@@ -651,6 +651,15 @@ int run_fir_fwd_w2(const FirArgs<C>& A, const Plan& P, long long B, hipStream_t 
   const size_t lds = sizeof(C) * 8 * I::TPW * WEx<C, MI>::EX;
   // samples per folded bin: unrolled for up to four
   const long long nt = (P.fir_len + MI - 1) / MI;
+  // span and window in LDS when they fit beside the exchange areas' size
+  const size_t need = sizeof(C) * size_t((8 * I::TPW - 1) * P.a + 2 * P.fir_len);
+  if (need <= std::max(lds, size_t(40960))) {
+    const size_t lw = std::max(lds, need);
+    if (nt <= 1) return launch(k_fir_fwd_ws<C, MI, HS, 1>, grid, lw, st, A, "FIR DGT");
+    if (nt <= 2) return launch(k_fir_fwd_ws<C, MI, HS, 2>, grid, lw, st, A, "FIR DGT");
+    if (nt <= 4) return launch(k_fir_fwd_ws<C, MI, HS, 4>, grid, lw, st, A, "FIR DGT");
+    return launch(k_fir_fwd_ws<C, MI, HS, 0>, grid, lw, st, A, "FIR DGT");
+  }
   if (nt <= 1) return launch(k_fir_fwd_w<C, MI, HS, 1>, grid, lds, st, A, "FIR DGT");
   if (nt <= 2) return launch(k_fir_fwd_w<C, MI, HS, 2>, grid, lds, st, A, "FIR DGT");
   if (nt <= 4) return launch(k_fir_fwd_w<C, MI, HS, 4>, grid, lds, st, A, "FIR DGT");

@@ -144,3 +144,32 @@ def test_fir_list_batch_and_refusals():
         with pytest.raises(Bb.DgtnsError) as e:
             fn()
         assert e.value.status == Bb.DGTNS_EUNSUPPORTED
+
+
+# Power-of-two M: the forward stages the work-group's signal span and the
+# window in LDS when they fit (one, two, up to four or any number of samples
+# per folded bin), else every wave reads them from global memory.
+FORMS = [((8192, 32, 256, 1, 2), (8000, 200), False),     # span form, 1 sample per bin, wrapping
+         ((8192, 32, 256, 1, 2), (5, 511), False),        # span form, 2 samples per bin
+         ((8192, 32, 256, 3, 4), (8100, 1000), True),     # span form, 4 samples per bin, lambda = 3/4
+         ((4096, 16, 64, 1, 2), (0, 2048), False),        # span form, 32 samples per bin
+         ((8192, 32, 256, 1, 2), (100, 8000), True),      # global form: span beyond the LDS budget
+         ((16384, 64, 1024, 1, 4), (16000, 3000), True)]  # M = 1024, span form
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("lat,support,real", FORMS)
+def test_fir_forward_forms(lat, support, real, dtype):
+    L, a, M, l1, l2 = lat
+    single = dtype == torch.complex64
+    B = 3
+    f = round_to(complex_normal_batch(B, L, 31), single)
+    if real:
+        f = f.real.copy()
+    g = round_to(complex_normal(L, 32), single)
+    plan = fir_plan(lat, support, dtype, B)
+    plan.set_window(torch.tensor(g))
+    c = plan.forward(torch.tensor(f)).cpu().numpy()
+    gt = truncate(g, *support)
+    err = max(rel(c[k], oracle.dgt_fold(f[k].astype(complex), gt, a, M, l1, l2)) for k in range(B))
+    assert err < TOL[dtype], (lat, support, err)
