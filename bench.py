@@ -86,6 +86,23 @@ def time_forward(plan, f, c, steps, warmup, torch, B_mod):
     return e0.elapsed_time(e1) / steps, wall / steps * 1e3, kt
 
 
+def time_adjoint(plan, c, fa, steps, torch, B_mod, warmup=3):
+    """Milliseconds per adjoint of the batch c into fa, and per-kernel times."""
+    for _ in range(warmup):
+        plan.adjoint(c, out=fa)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    B_mod.dgtns_timing_reset()
+    B_mod.dgtns_timing_enable(1)
+    e0.record()
+    for _ in range(steps):
+        plan.adjoint(c, out=fa)
+    e1.record()
+    torch.cuda.synchronize()
+    B_mod.dgtns_timing_enable(0)
+    return e0.elapsed_time(e1) / steps, B_mod.kernel_times()
+
+
 def crossover_bench(torch, dev, steps=5):
     """Shear versus multiwindow algorithm as the lattice complexity lambda2
     grows (the experiment of Section 4.4, Fig. 2): lambda = 1/lambda2,
@@ -180,7 +197,7 @@ def gradient_bench(torch, dev, steps=20):
             "kernels": {k: {"launches_per_step": n / steps, "avg_ms": round(t / n, 4)} for k, (n, t) in kt.items()}}
 
 
-def fir_bench(torch, dev, steps=20, with_shear=True):
+def fir_bench(torch, dev, steps=20, with_shear=True, with_adjoint=True):
     """FIR-window algorithm versus the shear algorithm on the precision
     workload: L = 2^20, a = 128, M = 1024, lambda = 1/4, 16 real chirp
     signals (FP32), the periodic Hann window of length 2048 centred at 0
@@ -213,6 +230,13 @@ def fir_bench(torch, dev, steps=20, with_shear=True):
         ms, _, kt = time_forward(plan, xr, c, steps, 3, torch, Bm)
         out[name] = {"ms_per_step": ms, "coeffs_per_s": coeffs / (ms * 1e-3),
                      "kernels": {k: round(t / n, 4) for k, (n, t) in kt.items()}}
+        if kw.get("algorithm") == "fir" and with_adjoint:
+            # adjoint of the FIR transform: inverse DFTs of the columns, then the gather
+            fa = torch.empty((w.batch, w.L), dtype=torch.complex64, device=dev)
+            ams, akt = time_adjoint(plan, c, fa, steps, torch, Bm)
+            out[name]["adjoint"] = {"ms_per_step": ams, "coeffs_per_s": coeffs / (ams * 1e-3),
+                                    "kernels": {k: round(t / n, 4) for k, (n, t) in akt.items()}}
+            del fa
         if kw.get("algorithm") == "shear-ola":
             Lx = plan.info.block_dgt_length
             out[name]["block_dgt_length"] = Lx
@@ -359,7 +383,7 @@ def main():
         import torch
         dev = torch.device("cuda", 0)
         torch.cuda.set_device(dev)
-        r = fir_bench(torch, dev, steps=args.steps, with_shear=False)
+        r = fir_bench(torch, dev, steps=args.steps, with_shear=False, with_adjoint=False)
         log(f"FIR forward {r['fir']['ms_per_step']:.3f} ms/step")
         return
 

@@ -294,6 +294,36 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd(FirArgs<C> A) {
 }
 
 // ----------------------------------------------------------------------------
+// Adjoint, first pass for power-of-two M = MI in [32, 1024]: one inverse wave
+// transform per time position, Y[n][k] = sum_m c(m, n) exp(2 pi i k m / M).
+// grid (ceil(N / (8 TPW)), B), 512 threads.
+// ----------------------------------------------------------------------------
+template <typename C, int MI>
+__global__ void __launch_bounds__(kThreads) k_fir_adj_rows_w(FirArgs<C> A, C* Y, long long ys) {
+  using I = WInfo<MI>;
+  constexpr int E = I::E, T = I::T, TPW = I::TPW;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
+  const long long bo = blockIdx.y;
+  const int n = (blockIdx.x * 8 + wave) * TPW + tt;
+  const bool ok = n < A.N;
+  const C* row = A.c + bo * A.cs + (long long)(ok ? n : 0) * MI;
+  C v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = row[l + T * e];
+  WTw<C, MI> tw;
+  tw.load(A.twm, l);
+  C* ex = lds + (wave * TPW + tt) * WEx<C, MI>::EX;
+  wave_fft<C, MI, true>(v, ex, l, tw);
+  if (ok) {
+    C* yr = Y + bo * ys + (long long)n * MI;
+#pragma unroll
+    for (int e = 0; e < E; ++e) yr[l + T * e] = v[e];
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Adjoint, first pass: Y[n][k] = sum_m c(m, n) exp(2 pi i k m / M).
 // grid (ceil(N / R), B), 512 threads.
 // ----------------------------------------------------------------------------
@@ -330,34 +360,38 @@ __global__ void __launch_bounds__(kThreads) k_fir_adj_gather(FirArgs<C> A, const
   const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
   if (idx >= A.L) return;
   const long long bo = blockIdx.y;
-  const int M = A.M, PM = A.lam2 * A.M;
+  const int M = A.M, PM = A.lam2 * A.M, l2 = A.lam2;
   long long u = idx - A.start;
   if (u < 0) u += A.L;
   const long long nt = u / A.a;
   const int j0 = int(u - nt * A.a);
   const int i0 = int(idx % PM), km = i0 % M;
-  // phase index (idx kn) mod PM for kn = n lambda1 mod lambda2 in [0, lambda2):
-  // stepping n down by one lowers kn by lambda1 (e by dl) and, where kn
-  // wraps, adds lambda2 (e by dw)
-  int kn = int((nt * A.lam1) % A.lam2);
-  int e = int(((long long)i0 * kn) % PM);
-  const int dl = int(((long long)i0 * A.lam1) % PM), dw = int(((long long)i0 * A.lam2) % PM);
-  const C* Yb = Y + bo * ys;
+  const C* Yb = Y + bo * ys + km;
+  const long long N = A.N, step = (long long)l2 * M, wrap = N * M;
+  // taps t = 0, 1, ... (position n = nt - t mod N, window sample j = j0 + t a)
+  // in lambda2 classes t = cl mod lambda2: lambda2 divides N, so a class has
+  // one kn = (n lambda1) mod lambda2 and one phase exp(2 pi i l kn / (lambda2 M))
   C acc = czero<C>();
-  long long n = nt;
-  for (int j = j0; j < A.Lg; j += A.a) {
-    C v = cmulc(Yb[n * M + km], A.gw[j]);      // times g(l - n a) = conj(gw[j])
-    if (kn) v = cmulc(v, A.ph[e]);
-    acc = cadd(acc, v);
-    n = n == 0 ? A.N - 1 : n - 1;
-    kn -= A.lam1;
-    e -= dl;
-    if (e < 0) e += PM;
-    if (kn < 0) {
-      kn += A.lam2;
-      e += dw;
-      if (e >= PM) e -= PM;
+  for (int cl = 0; cl < l2; ++cl) {
+    int j = j0 + cl * A.a;
+    if (j >= A.Lg) break;
+    long long n = nt - cl;
+    if (n < 0) n += N;
+    const int kn = int((n * A.lam1) % l2);
+    long long o = n * M;
+    C s = czero<C>();
+    const int ja = l2 * A.a;
+#pragma unroll 4
+    for (; j < A.Lg; j += ja) {
+      s = cadd(s, cmulc(Yb[o], A.gw[j]));      // times g(l - n a) = conj(gw[j])
+      o -= step;
+      if (o < 0) o += wrap;
     }
+    if (kn) {
+      const int e = int(((long long)i0 * kn) % PM);
+      s = cmulc(s, A.ph[e]);
+    }
+    acc = cadd(acc, s);
   }
   f[bo * A.L + idx] = acc;
 }

@@ -124,8 +124,10 @@ int launch_raw(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, cons
   return rc;
 }
 
-template <typename K, typename A>
-int launch(K kernel, dim3 grid, size_t lds, hipStream_t st, const A& args, const char* name) {
+// 512-thread launch with any kernel arguments: empty grids are no-ops, LDS
+// requests above 64 KiB are granted up to the 160 KiB of a compute unit.
+template <typename K, typename... A>
+int launch_v(K kernel, dim3 grid, size_t lds, hipStream_t st, const char* name, A... args) {
   if (grid.x == 0 || grid.y == 0) return DGTNS_OK;
   if (lds > 160 * 1024) return fail(DGTNS_EUNSUPPORTED, std::string(name) + ": LDS request above 160 KiB");
   if (lds > 64 * 1024) {
@@ -133,7 +135,12 @@ int launch(K kernel, dim3 grid, size_t lds, hipStream_t st, const A& args, const
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return check_hip(e, name);
   }
-  return launch_raw(kernel, grid, dim3(kThreads), lds, st, name, args);
+  return launch_raw(kernel, grid, dim3(kThreads), lds, st, name, args...);
+}
+
+template <typename K, typename A>
+int launch(K kernel, dim3 grid, size_t lds, hipStream_t st, const A& args, const char* name) {
+  return launch_v(kernel, grid, lds, st, name, args);
 }
 
 inline unsigned cdiv(long long a, long long b) { return unsigned((a + b - 1) / b); }
@@ -699,14 +706,38 @@ int run_fir_fwd(const Plan& P, const void* f, int real_in, C* c, long long B, hi
   return launch(k_fir_fwd<C>, dim3(cdiv(P.N, A.R), unsigned(B)), lds, st, A, "FIR DGT");
 }
 
+template <typename C, int MI>
+int run_fir_adj_rows_w(const FirArgs<C>& A, const Plan& P, long long B, C* Y, long long ys, hipStream_t st) {
+  using I = WInfo<MI>;
+  const size_t lds = sizeof(C) * 8 * I::TPW * WEx<C, MI>::EX;
+  return launch_v(k_fir_adj_rows_w<C, MI>, dim3(cdiv(P.N, 8 * I::TPW), unsigned(B)), lds, st,
+                       "FIR adjoint, inverse DFTs", A, Y, ys);
+}
+
+template <typename C>
+int run_fir_adj_rows(const FirArgs<C>& A, const Plan& P, long long B, C* Y, long long ys, hipStream_t st) {
+  if (!P.generic && P.M * long(sizeof(C)) <= 8192) {
+    switch (P.M) {
+      case 32: return run_fir_adj_rows_w<C, 32>(A, P, B, Y, ys, st);
+      case 64: return run_fir_adj_rows_w<C, 64>(A, P, B, Y, ys, st);
+      case 128: return run_fir_adj_rows_w<C, 128>(A, P, B, Y, ys, st);
+      case 256: return run_fir_adj_rows_w<C, 256>(A, P, B, Y, ys, st);
+      case 512: return run_fir_adj_rows_w<C, 512>(A, P, B, Y, ys, st);
+      case 1024: return run_fir_adj_rows_w<C, 1024>(A, P, B, Y, ys, st);
+      default: break;
+    }
+  }
+  const size_t lds = sizeof(C) * (P.M + size_t(A.R) * A.Sm);
+  return launch_v(k_fir_adj_rows<C>, dim3(cdiv(P.N, A.R), unsigned(B)), lds, st,
+                       "FIR adjoint, inverse DFTs", A, Y, ys);
+}
+
 template <typename C>
 int run_fir_adj(const Plan& P, const C* c, C* f, long long B, C* Y, hipStream_t st) {
   FirArgs<C> A = fir_args<C>(P);
   A.c = const_cast<C*>(c); A.cs = P.M * P.N;
   const long long ys = P.M * P.N;
-  const size_t lds = sizeof(C) * (P.M + size_t(A.R) * A.Sm);
-  int rc = launch_raw(k_fir_adj_rows<C>, dim3(cdiv(P.N, A.R), unsigned(B)), dim3(kThreads), lds, st,
-                      "FIR adjoint, inverse DFTs", A, Y, ys);
+  int rc = run_fir_adj_rows<C>(A, P, B, Y, ys, st);
   if (rc) return rc;
   return launch_raw(k_fir_adj_gather<C>, dim3(cdiv(P.L, kThreads), unsigned(B)), dim3(kThreads), 0, st,
                     "FIR adjoint, gather", A, (const C*)Y, ys, f);
