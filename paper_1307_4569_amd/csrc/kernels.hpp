@@ -347,7 +347,9 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
   C* tw = reinterpret_cast<C*>(smem_raw);
   const int d = A.d, p = GENP ? A.p : 1, W = A.W, Sd = A.Sd, Mi = A.Mi;
   C* xb = tw + d;
-  C* yb = xb + W * p * Sd;
+  // p = 1 accumulates in registers and fills xb only after the loop over n0,
+  // so the h columns can take the same LDS
+  C* yb = GENP ? xb + W * p * Sd : xb;
   for (int e = threadIdx.x; e < d; e += kThreads) tw[e] = A.twd[e];
   const int r0 = blockIdx.x * W;
   const long long bo = blockIdx.y;
@@ -961,15 +963,20 @@ template <typename C> struct GradArgs {
   FftSched fd;
 };
 
-template <typename C>
+// TWG: twiddles read from global memory, which leaves the whole LDS to the
+// 2 W column transforms (FP64 columns above 3412 values).
+template <typename C, bool TWG>
 __global__ void __launch_bounds__(kThreads) k_grad_cols(GradArgs<C> A) {
   using T = decltype(C::x);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  C* tw = reinterpret_cast<C*>(smem_raw);
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  C* twl = lds;
+  const C* tw = TWG ? A.twd : twl;
   const int d = A.d, W = A.W, Sd = A.Sd, Mi = A.Mi;
-  C* xb = tw + d;       // W transforms of the signal columns, then W of h*
+  C* xb = TWG ? lds : lds + d;   // W transforms of the signal columns, then W of h*
   C* yb = xb + W * Sd;
-  for (int e = threadIdx.x; e < d; e += kThreads) tw[e] = A.twd[e];
+  if (!TWG)
+    for (int e = threadIdx.x; e < d; e += kThreads) twl[e] = A.twd[e];
   const int u0 = blockIdx.x * W;
   const long long bo = blockIdx.y;
   const int WD = W * d;
@@ -1001,7 +1008,13 @@ __global__ void __launch_bounds__(kThreads) k_grad_cols(GradArgs<C> A) {
       yb[cc * Sd + t] = h;
     }
     __syncthreads();
-    fft_lds<C, false>(xb, Sd, A.fd, 2 * W, tw);
+    // one call transforms at most MaxE * kThreads values
+    if (2 * WD <= MaxE<C>::value * kThreads) {
+      fft_lds<C, false>(xb, Sd, A.fd, 2 * W, tw);
+    } else {
+      fft_lds<C, false>(xb, Sd, A.fd, W, tw);
+      fft_lds<C, false>(yb, Sd, A.fd, W, tw);
+    }
 #pragma unroll
     for (int i = 0; i < KX; ++i) {
       const int e = threadIdx.x + i * kThreads;

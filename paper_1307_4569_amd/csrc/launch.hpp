@@ -516,7 +516,7 @@ int run_adj_cols(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, h
     }
   }
   dim3 grid(cdiv(P.Mi, P.W), unsigned(B));
-  size_t lds = es * (P.di + size_t(P.W) * A.Sd * (P.pi + 1));
+  size_t lds = es * (P.di + size_t(P.W) * A.Sd * (P.pi > 1 ? P.pi + 1 : 1));
   if (P.pi == 1) return launch(k_adj_cols<C, false>, grid, lds, st, A, "adjoint factorisation kernel");
   return launch(k_adj_cols<C, true>, grid, lds, st, A, "adjoint factorisation kernel (p > 1)");
 }
@@ -907,8 +907,10 @@ int run_grad_cols_generic(const Plan& P, const void* x, ChirpSrc<C> ch, const C*
   A.Sd = int(P.di | 1);
   A.W = block_width(2 * A.Sd, sizeof(C));
   A.fd = sched(P.fd);
-  size_t lds = sizeof(C) * (P.di + 2 * size_t(A.W) * A.Sd);
-  return launch(k_grad_cols<C>, dim3(cdiv(P.Mi, A.W), unsigned(B)), lds, st, A, "window gradient");
+  const size_t lds = sizeof(C) * (P.di + 2 * size_t(A.W) * A.Sd), lcols = sizeof(C) * 2 * size_t(A.W) * A.Sd;
+  const dim3 grid(cdiv(P.Mi, A.W), unsigned(B));
+  if (lds <= 160 * 1024) return launch(k_grad_cols<C, false>, grid, lds, st, A, "window gradient");
+  return launch(k_grad_cols<C, true>, grid, lcols, st, A, "window gradient");
 }
 
 template <typename C>

@@ -153,6 +153,40 @@ def test_ragged_blocks_and_batch_sizes():
         assert rel(c5[k], oracle.dgt_fold(f[k], g, a, M, l1, l2)) < 1e-12
 
 
+# The largest in-LDS transforms: rows of M = 4096 channels, columns of
+# d = 4096, and a frequency-shear plan with M = 8192 channels (its rows run on
+# the N_r inner channels).
+MAXIMA = [(65536, 64, 4096, 0, 1), (65536, 16, 16, 1, 2), (32768, 8, 8, 0, 1), (65536, 64, 4096, 1, 2),
+          (131072, 64, 8192, 1, 2)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("lat", MAXIMA)
+def test_maximum_in_lds_sizes(lat, dtype):
+    L, a, M, l1, l2 = lat
+    plan, f, g, c = run_forward(lat, dtype, B=2, g=complex_normal(L, 78), seed=40)
+    for k in range(2):
+        e = rel(c[k], oracle.dgt_fold(f[k], g, a, M, l1, l2))
+        assert e < TOL[dtype], (lat, k, e)
+    cin = round_to(complex_normal(L // a * M, 541).reshape(1, L // a, M), dtype == torch.complex64)
+    fa = plan.adjoint(torch.tensor(cin)).cpu().numpy()
+    e = rel(fa[0], oracle.idgt_adjoint(cin[0], g, a, M, l1, l2))
+    assert e < TOL[dtype], ("adjoint", lat, e)
+    if plan.info.d == 4096:
+        gg = plan.window_grad(torch.tensor(f), torch.tensor(round_to(
+            np.stack([complex_normal(L // a * M, 542 + k).reshape(L // a, M) for k in range(2)]),
+            dtype == torch.complex64))).cpu().numpy()
+        Gs = round_to(np.stack([complex_normal(L // a * M, 542 + k).reshape(L // a, M) for k in range(2)]),
+                      dtype == torch.complex64)
+        ref = sum(oracle.window_gradient(f[k], Gs[k], a, M, l1, l2) for k in range(2))
+        assert rel(gg, ref) < 5 * TOL[dtype], ("window gradient", lat, rel(gg, ref))
+        gw = gaussian_window(L, a, M)
+        gd, _ = plan.dual(torch.tensor(gw))
+        pts = np.linspace(0, L - 1, 16).astype(np.int64)
+        sg = oracle.frame_operator_apply(gd.cpu().numpy(), gw, a, M, l1, l2, pts)
+        assert rel(sg, gw[pts]) < 1e-11, ("dual", lat, rel(sg, gw[pts]))
+
+
 def test_real_input_matches_complex():
     lat = (240, 6, 12, 1, 2)
     L, a, M, l1, l2 = lat

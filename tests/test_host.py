@@ -196,6 +196,20 @@ def test_long_column_plans(lib):
     assert e.value.status == B.DGTNS_EUNSUPPORTED
 
 
+def test_channel_count_limit(lib):
+    """Rows are in-LDS transforms of at most 4096 channels: a separable or
+    time-shear lattice with M = 8192 is refused, while a frequency-shear plan
+    with M = 8192 runs its rows on the N_r inner channels."""
+    for dt in (0, 1):
+        with pytest.raises(B.DgtnsError) as e:
+            B.dgtns_plan_create(131072, 64, 8192, 0, 1, dt, 1)
+        assert e.value.status == B.DGTNS_EUNSUPPORTED
+        h = B.dgtns_plan_create(131072, 64, 8192, 1, 2, dt, 1)
+        i = B.dgtns_plan_info(h)
+        B.dgtns_plan_destroy(h)
+        assert (i.branch, i.d) == (2, 128)
+
+
 def test_fir_plans(lib):
     """FIR-window plans: branch, no factorisation constants, and the errors."""
     h = B.dgtns_plan_create_fir(144, 6, 12, 1, 2, 0, 2, 140, 20)
