@@ -249,7 +249,9 @@ int dgtns_adjoint(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, vo
  * respect to the coefficients (convention dLoss/dRe + i dLoss/dIm), writes
  * gg_dev[L] (plan dtype) with gg(j) = sum_k sum_n f_k(j + n a) conj(y_{k,n}(j + n a)),
  * y_{k,n}(l) = sum_m gc_k(m, n) exp(2 pi i l (m + w(n)) / M).
- * Deterministic (no atomics).  Workspace: DGTNS_OP_WINDOW_GRAD.
+ * Deterministic (no atomics).  Implemented for shear-algorithm plans with
+ * p = 1 whose columns fit one in-LDS transform (DGTNS_EUNSUPPORTED
+ * otherwise).  Workspace: DGTNS_OP_WINDOW_GRAD.
  */
 int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, void* gg_dev,
                       int64_t B, void* ws, size_t ws_bytes, void* stream);
@@ -262,8 +264,10 @@ int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, vo
  * optimal frame bounds (A, B); A == 0 means the system is not a frame and
  * gd_dev is then undefined (asynchronous calls cannot report
  * DGTNS_ENOTFRAME; callers check A).  Implemented for p <= 8 of the sheared
- * lattice (p x p blocks of the frame operator in the Zak domain), columns of
- * at most 4096 values and shear-algorithm plans (DGTNS_EUNSUPPORTED otherwise).
+ * lattice (p x p blocks of the frame operator in the Zak domain), plans whose
+ * columns fit one in-LDS transform (p d within 8192 values in FP32 or 4096 in
+ * FP64, and 16 (d + p d) bytes within 160 KiB; longer columns run as two
+ * passes) and shear-algorithm plans (DGTNS_EUNSUPPORTED otherwise).
  * Does not change the plan's window.  Workspace: DGTNS_OP_DUAL.
  */
 int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* bounds_dev,

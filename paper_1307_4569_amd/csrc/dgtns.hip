@@ -336,7 +336,7 @@ static int dual_or_tight(dgtns_plan plan, const void* g_dev, void* out_dev, doub
   if (P.pi > kDualMaxP)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p <= 8 of the sheared lattice");
   if (P.longd)
-    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for columns of at most 4096 values");
+    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows need columns held by one in-LDS transform (this plan splits them in two passes)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   return dual_c128(P, static_cast<const double2*>(g_dev), static_cast<double2*>(out_dev), bounds_dev, w, l, tight,

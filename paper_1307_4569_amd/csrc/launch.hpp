@@ -919,7 +919,7 @@ int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* 
   if (P.branch == kMultiwindow || P.branch == kFir)
     return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for shear-algorithm plans only");
   if (P.longd)
-    return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for columns of at most 4096 values");
+    return fail(DGTNS_EUNSUPPORTED, "the window gradient needs columns held by one in-LDS transform (this plan splits them in two passes)");
   C* H = reinterpret_cast<C*>(ws + l.H);
   C* part = reinterpret_cast<C*>(ws + l.part);
   int rc = run_rows<C>(P, H, const_cast<C*>(gc), B, true, st);

@@ -187,6 +187,48 @@ def test_maximum_in_lds_sizes(lat, dtype):
         assert rel(sg, gw[pts]) < 1e-11, ("dual", lat, rel(sg, gw[pts]))
 
 
+# p > 1 (p sub-columns per column) at the LDS element budget: p d = 4096 is
+# the FP64 in-LDS limit, p d = 8192 the FP32 one; beyond it the columns take
+# the two-level passes (d = d1 d2).
+BLOCK_BUDGET = [(49152, 8, 12, 0, 1), (49152, 8, 12, 1, 2), (98304, 8, 12, 1, 2), (36864, 12, 8, 0, 1),
+                (73728, 12, 8, 0, 1)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("lat", BLOCK_BUDGET)
+def test_block_columns_at_the_budget(lat, dtype):
+    from paper_1307_4569_amd import _binding as Bb
+    L, a, M, l1, l2 = lat
+    plan, f, g, c = run_forward(lat, dtype, B=2, g=complex_normal(L, 79), seed=60)
+    assert plan.info.p > 1
+    N = L // a
+    cols = sorted(set(range(0, N, N // 40)) | {N - 1})      # sampled time positions
+    for k in range(2):
+        e = rel(c[k][cols], oracle.dgt_fold(f[k], g, a, M, l1, l2, columns=cols))
+        assert e < TOL[dtype], (lat, k, e)
+    # adjoint: <C f, c'> = <f, C* c'> with the forward checked above
+    cin = round_to(complex_normal(N * M, 561).reshape(1, N, M), dtype == torch.complex64)
+    fa = plan.adjoint(torch.tensor(cin)).cpu().numpy()
+    lhs = np.vdot(c[0].astype(np.complex128), cin[0].astype(np.complex128))
+    rhs = np.vdot(f[0].astype(np.complex128), fa[0].astype(np.complex128))
+    scale = np.linalg.norm(c[0]) * np.linalg.norm(cin[0])
+    assert abs(lhs - rhs) < TOL[dtype] * scale, ("adjoint", lat, abs(lhs - rhs) / scale)
+    # columns in one in-LDS transform: p d within the element budget and the
+    # FP64 window Zak's 16 (d + p d) bytes within 160 KiB
+    budget = 8192 if dtype == torch.complex64 else 4096
+    p, d = plan.info.p, plan.info.d
+    gw = gaussian_window(L, a, M)
+    if p * d <= budget and 16 * (d + p * (d | 1)) <= 160 * 1024:
+        gd, _ = plan.dual(torch.tensor(gw))
+        pts = np.linspace(0, L - 1, 4).astype(np.int64)
+        sg = oracle.frame_operator_apply(gd.cpu().numpy(), gw, a, M, l1, l2, pts)
+        assert rel(sg, gw[pts]) < 1e-11, ("dual", lat, rel(sg, gw[pts]))
+    else:                                   # two-level columns: no dual window
+        with pytest.raises(Bb.DgtnsError) as err:
+            plan.dual(torch.tensor(gw))
+        assert err.value.status == Bb.DGTNS_EUNSUPPORTED
+
+
 def test_real_input_matches_complex():
     lat = (240, 6, 12, 1, 2)
     L, a, M, l1, l2 = lat
