@@ -173,3 +173,27 @@ def test_fir_forward_forms(lat, support, real, dtype):
     gt = truncate(g, *support)
     err = max(rel(c[k], oracle.dgt_fold(f[k].astype(complex), gt, a, M, l1, l2)) for k in range(B))
     assert err < TOL[dtype], (lat, support, err)
+
+
+# M = 4096 (the longest in-LDS channel DFT) and FP64 with M = 1024, both on
+# the work-group transform form of the FIR kernels.
+FIR_WIDE = [((65536, 64, 4096, 1, 2), (63536, 4000)), ((65536, 64, 1024, 1, 2), (65000, 2048))]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("lat,support", FIR_WIDE)
+def test_fir_wide_channel_counts(lat, support, dtype):
+    L, a, M, l1, l2 = lat
+    N = L // a
+    single = dtype == torch.complex64
+    f = round_to(complex_normal_batch(2, L, 33), single)
+    g = round_to(complex_normal(L, 34), single)
+    plan = fir_plan(lat, support, dtype, 2)
+    plan.set_window(torch.tensor(g))
+    gt = truncate(g, *support)
+    c = plan.forward(torch.tensor(f)).cpu().numpy()
+    ef = max(rel(c[k], oracle.dgt_fold(f[k], gt, a, M, l1, l2)) for k in range(2))
+    cin = round_to(complex_normal(N * M, 35).reshape(1, N, M), single)
+    fa = plan.adjoint(torch.tensor(cin)).cpu().numpy()
+    ea = rel(fa[0], oracle.idgt_adjoint(cin[0], gt, a, M, l1, l2))
+    assert ef < TOL[dtype] and ea < TOL[dtype], (lat, ef, ea)

@@ -178,3 +178,15 @@ def test_multiwindow_list_batch_pipeline_and_window_grad(monkeypatch):
     with pytest.raises(Bb.DgtnsError) as e:
         plan.window_grad(f, c)
     assert e.value.status == Bb.DGTNS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_multiwindow_largest_columns(dtype):
+    """p_mw d_mw = 4096 on the (lambda2 a, M) lattice: the FP64 in-LDS limit
+    of the multiwindow factorisation, forward and adjoint against the oracle."""
+    lat = (32768, 8, 8, 1, 2)
+    i = mw_info(lat)
+    assert i.p * i.d == 4096
+    ef, ea = check_lattice(lat, dtype, 870)
+    tol = 1e-12 if dtype == torch.complex128 else 1e-5
+    assert ef < tol and ea < tol, (ef, ea)
