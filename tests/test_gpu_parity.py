@@ -376,3 +376,34 @@ def test_serving_column_lengths_sampled(dtype, kernel_path):
         e = max(rel(c[k, cols], oracle.dgt_fold(f[k], g, a, M, l1, l2, columns=cols)) for k in range(B))
         print("serving d", kernel_path, dtype, lat, plan.info.branch, plan.info.d, e)
         assert e < TOL[dtype], (lat, e)
+
+
+# Real input (4 bytes per FP32 sample) on every route that reads the signal:
+# the factorisation loads of each column kernel, the length-L transform of
+# the frequency shear, the two-level column passes, the multiwindow, FIR and
+# shear-OLA algorithms.  The result must equal that of the same samples
+# passed as complex numbers with zero imaginary part, bit for bit.
+REAL_ROUTES = [((262144, 64, 512, 1, 2), {}),                      # time shear, wave columns d = 512
+               ((73728, 64, 512, 1, 3), {}),                       # time shear, d = 144 (one wavefront per column)
+               ((36864, 32, 256, 1, 2), {}),                       # frequency shear, d = 576
+               ((20160, 3, 6, 1, 3), {}),                          # frequency shear, two-level columns
+               ((1 << 20, 32, 64, 1, 2), {}),                      # time shear, two-level columns
+               ((65536, 32, 32, 1, 2), {"algorithm": "multiwindow"}),
+               ((8192, 32, 256, 1, 2), {"algorithm": "fir", "support": (8000, 200)}),
+               ((65536, 64, 1024, 1, 2), {"algorithm": "fir", "support": (65000, 2048)}),
+               ((6144, 16, 64, 1, 2), {"algorithm": "shear-ola", "support": (6000, 300), "block": 1024})]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("lat,kw", REAL_ROUTES)
+def test_real_input_on_every_route(lat, kw, dtype, kernel_path):
+    from paper_1307_4569_amd import Plan
+    L, a, M, l1, l2 = lat
+    single = dtype == torch.complex64
+    x = np.stack([chirp_mixture(L, 71 + k) for k in range(2)]).real
+    x = x.astype(np.float32 if single else np.float64)
+    plan = Plan(*lat, dtype=dtype, max_batch=2, **kw)
+    plan.set_window(torch.tensor(round_to(gaussian_window(L, a, M), single)))
+    cr = plan.forward(torch.tensor(x)).cpu().numpy()
+    cc = plan.forward(torch.tensor(x.astype(np.complex64 if single else np.complex128))).cpu().numpy()
+    assert np.array_equal(cr, cc), (lat, kw, float(np.abs(cr - cc).max()))
