@@ -407,3 +407,33 @@ def test_real_input_on_every_route(lat, kw, dtype, kernel_path):
     cr = plan.forward(torch.tensor(x)).cpu().numpy()
     cc = plan.forward(torch.tensor(x.astype(np.complex64 if single else np.complex128))).cpu().numpy()
     assert np.array_equal(cr, cc), (lat, kw, float(np.abs(cr - cc).max()))
+
+
+@pytest.mark.parametrize("lat,kw", REAL_ROUTES)
+def test_list_batch_on_every_route(lat, kw, kernel_path):
+    """dgtns_forward_batch (signals and outputs at separate addresses, up to
+    16 per launch) gives the batched forward's coefficients bit for bit on
+    every route; shear-OLA plans refuse it."""
+    from paper_1307_4569_amd import Plan
+    from paper_1307_4569_amd import _binding as Bb
+    L, a, M, l1, l2 = lat
+    B = 3
+    plan = Plan(*lat, dtype=torch.complex64, max_batch=B, **kw)
+    plan.set_window(torch.tensor(round_to(gaussian_window(L, a, M), True)))
+    fs = [torch.tensor(complex_normal(L, 90 + k).astype(np.complex64)).cuda() for k in range(B)]
+    c = plan.forward(torch.stack(fs))
+    outs = [torch.empty_like(c[0]) for _ in range(B)]
+    wsb = Bb.dgtns_workspace_bytes(plan._h, Bb.DGTNS_OP_FORWARD, B)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    call = lambda: Bb.dgtns_forward_batch(plan._h, [x.data_ptr() for x in fs], 0,   # noqa: E731
+                                          [o.data_ptr() for o in outs], ws.data_ptr(), wsb, st)
+    if kw.get("algorithm") == "shear-ola":
+        with pytest.raises(Bb.DgtnsError) as e:
+            call()
+        assert e.value.status == Bb.DGTNS_EUNSUPPORTED
+        return
+    call()
+    torch.cuda.synchronize()
+    for k in range(B):
+        assert torch.equal(outs[k], c[k]), (lat, kw, k)
