@@ -34,3 +34,9 @@ def feasible_lattices(max_L=120, max_lam2=4, require_p1=False):
                             continue
                         out.append((L, a, M, lam1, lam2))
     return out
+
+
+# Degenerate lattices: one time position (a = L), one channel (M = 1), a = 1,
+# M = L, p = L / gcd(L, 1) = 48 with columns of one value, and L = 1.
+DEGENERATE_LATTICES = [(48, 48, 12, 0, 1), (48, 4, 1, 0, 1), (48, 1, 12, 0, 1), (48, 1, 48, 0, 1),
+                       (96, 2, 48, 1, 2), (1, 1, 1, 0, 1), (48, 48, 1, 0, 1), (48, 1, 1, 0, 1)]

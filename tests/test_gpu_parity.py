@@ -9,7 +9,7 @@ import pytest
 import oracle
 from dgt_inputs import (GRADIENT, LARGE, PRECISION, SMALL, chirp_mixture, complex_normal, complex_normal_batch,
                         gaussian_window, hann_window, round_to)
-from tests.conftest import feasible_lattices
+from tests.conftest import DEGENERATE_LATTICES, feasible_lattices
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -437,3 +437,19 @@ def test_list_batch_on_every_route(lat, kw, kernel_path):
     torch.cuda.synchronize()
     for k in range(B):
         assert torch.equal(outs[k], c[k]), (lat, kw, k)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_degenerate_lattices(dtype, kernel_path):
+    """a = L (one time position), M = 1, a = 1, M = L, p = 48 with columns of
+    one value, and L = 1: forward and adjoint against the oracle."""
+    for lat in DEGENERATE_LATTICES:
+        L, a, M, l1, l2 = lat
+        plan, f, g, c = run_forward(lat, dtype, B=2, g=complex_normal(L, 81), seed=80)
+        for k in range(2):
+            e = rel(c[k], oracle.dgt_fold(f[k], g, a, M, l1, l2))
+            assert e < TOL[dtype], (lat, k, e)
+        cin = round_to(complex_normal(L // a * M, 591).reshape(1, L // a, M), dtype == torch.complex64)
+        fa = plan.adjoint(torch.tensor(cin)).cpu().numpy()
+        e = rel(fa[0], oracle.idgt_adjoint(cin[0], g, a, M, l1, l2))
+        assert e < TOL[dtype], ("adjoint", lat, e)

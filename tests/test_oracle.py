@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from dgt_inputs import complex_normal, gaussian_window
-from tests.conftest import feasible_lattices
+from tests.conftest import DEGENERATE_LATTICES, feasible_lattices
 
 RNG = np.random.default_rng(20240611)
 
@@ -71,6 +71,21 @@ def test_direct_and_fold_match_brute_force(lat):
     assert rel(oracle.dgt_direct(f, g, a, M, l1, l2), c_bf) < 1e-13
     assert rel(oracle.dgt_fold(f, g, a, M, l1, l2), c_bf) < 1e-13
     assert rel(oracle.dgt_multiwindow(f, g, a, M, l1, l2), c_bf) < 1e-13
+
+
+@pytest.mark.parametrize("lat", DEGENERATE_LATTICES)
+def test_degenerate_lattices_match_brute_force(lat):
+    """One time position, one channel, a = 1, M = L and L = 1: both
+    evaluation orders against the explicit atoms, and the adjoint identity."""
+    L, a, M, l1, l2 = lat
+    f, g = rand_c(L), rand_c(L)
+    A = brute_force_atoms(g, L, a, M, l1, l2)
+    c_bf = np.einsum("l,lnm->nm", f, np.conj(A))
+    assert rel(oracle.dgt_direct(f, g, a, M, l1, l2), c_bf) < 1e-13
+    assert rel(oracle.dgt_fold(f, g, a, M, l1, l2), c_bf) < 1e-13
+    c = rand_c(L // a * M).reshape(L // a, M)
+    fa = oracle.idgt_adjoint(c, g, a, M, l1, l2)
+    assert rel(fa, np.einsum("nm,lnm->l", c, A)) < 1e-13
 
 
 def test_plus_one_reading_is_rejected():
