@@ -453,3 +453,32 @@ def test_degenerate_lattices(dtype, kernel_path):
         fa = plan.adjoint(torch.tensor(cin)).cpu().numpy()
         e = rel(fa[0], oracle.idgt_adjoint(cin[0], g, a, M, l1, l2))
         assert e < TOL[dtype], ("adjoint", lat, e)
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_degenerate_lattices_other_algorithms(dtype, kernel_path):
+    """The multiwindow and FIR algorithms on the degenerate lattices (the FIR
+    window on the first half of the samples, wrapping from L - 1 for L = 1):
+    forward and adjoint against the oracle on the same (truncated) window."""
+    from paper_1307_4569_amd import Plan
+    single = dtype == torch.complex64
+    for lat in DEGENERATE_LATTICES:
+        L, a, M, l1, l2 = lat
+        N = L // a
+        f = round_to(np.stack([complex_normal(L, 600 + k) for k in range(2)]), single)
+        g = round_to(complex_normal(L, 610), single)
+        support = (L - 1, max(1, L // 2))
+        gt = np.zeros_like(g)
+        idx = (support[0] + np.arange(support[1])) % L
+        gt[idx] = g[idx]
+        for kw, gw in (({"algorithm": "multiwindow"}, g), ({"algorithm": "fir", "support": support}, gt)):
+            plan = Plan(*lat, dtype=dtype, max_batch=2, **kw)
+            plan.set_window(torch.tensor(g))
+            c = plan.forward(torch.tensor(f)).cpu().numpy()
+            for k in range(2):
+                e = rel(c[k], oracle.dgt_fold(f[k], gw, a, M, l1, l2))
+                assert e < TOL[dtype], (lat, kw, k, e)
+            cin = round_to(complex_normal(N * M, 620).reshape(1, N, M), single)
+            fa = plan.adjoint(torch.tensor(cin)).cpu().numpy()
+            e = rel(fa[0], oracle.idgt_adjoint(cin[0], gw, a, M, l1, l2))
+            assert e < TOL[dtype], ("adjoint", lat, kw, e)
