@@ -482,3 +482,31 @@ def test_degenerate_lattices_other_algorithms(dtype, kernel_path):
             fa = plan.adjoint(torch.tensor(cin)).cpu().numpy()
             e = rel(fa[0], oracle.idgt_adjoint(cin[0], gw, a, M, l1, l2))
             assert e < TOL[dtype], ("adjoint", lat, kw, e)
+
+
+def test_degenerate_lattices_dual_and_tight():
+    """Dual and tight windows on the degenerate lattices: the oracle's windows
+    and frame bounds where the Gaussian gives a frame, a lower bound of zero
+    (not a frame) for the undercomplete ones, and the refusal for p > 8."""
+    from paper_1307_4569_amd import Plan
+    from paper_1307_4569_amd import _binding as Bb
+    for lat in DEGENERATE_LATTICES:
+        L, a, M, l1, l2 = lat
+        g = gaussian_window(L, a, M)
+        plan = Plan(*lat, dtype=torch.complex128, max_batch=1)
+        if plan.info.p > 8:
+            with pytest.raises(Bb.DgtnsError) as e:
+                plan.dual(torch.tensor(g))
+            assert e.value.status == Bb.DGTNS_EUNSUPPORTED
+            continue
+        lo, hi = oracle.frame_bounds(g, a, M, l1, l2)
+        gd, bounds = plan.dual(torch.tensor(g))
+        gt, _ = plan.tight(torch.tensor(g))
+        A, B = bounds.cpu().numpy()
+        assert abs(B - hi) < 1e-10 * hi, (lat, B, hi)
+        if lo < 1e-9 * hi:                     # a = L or M = 1 with fewer atoms than samples
+            assert A < 1e-9 * hi, (lat, A)
+            continue
+        assert abs(A - lo) < 1e-10 * hi, (lat, A, lo)
+        assert rel(gd.cpu().numpy(), oracle.dual_window(g, a, M, l1, l2)) < 1e-12, lat
+        assert rel(gt.cpu().numpy(), oracle.tight_window(g, a, M, l1, l2)) < 1e-12, lat
