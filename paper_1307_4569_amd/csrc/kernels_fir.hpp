@@ -373,14 +373,14 @@ __global__ void __launch_bounds__(kThreads) k_fir_adj_gather(FirArgs<C> A, const
   // one kn = (n lambda1) mod lambda2 and one phase exp(2 pi i l kn / (lambda2 M))
   C acc = czero<C>();
   for (int cl = 0; cl < l2; ++cl) {
-    int j = j0 + cl * A.a;
+    long long j = j0 + (long long)cl * A.a;     // 64-bit: l2 a may exceed 2^31 - L_g
     if (j >= A.Lg) break;
     long long n = nt - cl;
     if (n < 0) n += N;
     const int kn = int((n * A.lam1) % l2);
     long long o = n * M;
     C s = czero<C>();
-    const int ja = l2 * A.a;
+    const long long ja = (long long)l2 * A.a;
 #pragma unroll 4
     for (; j < A.Lg; j += ja) {
       s = cadd(s, cmulc(Yb[o], A.gw[j]));      // times g(l - n a) = conj(gw[j])
