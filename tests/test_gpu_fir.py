@@ -197,3 +197,20 @@ def test_fir_wide_channel_counts(lat, support, dtype):
     fa = plan.adjoint(torch.tensor(cin)).cpu().numpy()
     ea = rel(fa[0], oracle.idgt_adjoint(cin[0], gt, a, M, l1, l2))
     assert ef < TOL[dtype] and ea < TOL[dtype], (lat, ef, ea)
+
+
+def test_fir_start_is_taken_mod_L():
+    """The support start is reduced modulo L: starts -24, L - 24 and 2 L - 24
+    give the same coefficients, bit for bit, and match the oracle."""
+    lat = (4096, 32, 128, 1, 2)
+    L, a, M, l1, l2 = lat
+    f = round_to(complex_normal_batch(2, L, 36), True)
+    g = round_to(complex_normal(L, 37), True)
+    out = []
+    for start in (-24, L - 24, 2 * L - 24):
+        plan = fir_plan(lat, (start, 48), torch.complex64, 2)
+        plan.set_window(torch.tensor(g))
+        out.append(plan.forward(torch.tensor(f)).cpu().numpy())
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[1], out[2])
+    gt = truncate(g, L - 24, 48)
+    assert rel(out[0][1], oracle.dgt_fold(f[1], gt, a, M, l1, l2)) < 1e-5
