@@ -150,13 +150,15 @@ def dgt_multiwindow(f, g, a, M, lam1, lam2):
     return c
 
 
-def idgt_adjoint(c, g, a, M, lam1, lam2):
+def idgt_adjoint(c, g, a, M, lam1, lam2, samples=None):
     """Adjoint (synthesis) operator of eq. (DGT):
     f(l) = sum_{m,n} c(m, n) g(l - n a) exp(+2 pi i l (m + w(n)) / M).
 
     Per column: y_n(l) = sum_m c(m, n) exp(2 pi i l (m + w(n))/M) is an
     M-periodic inverse DFT times the offset modulation, then the windowed
-    columns are summed."""
+    columns are summed.  ``samples`` restricts the evaluation to the given
+    sample indices l (the result then has one value per requested sample);
+    each value is the same sum over all N columns."""
     c = np.asarray(c, dtype=np.complex128)
     g = np.asarray(g, dtype=np.complex128)
     N, M_ = c.shape
@@ -167,6 +169,14 @@ def idgt_adjoint(c, g, a, M, lam1, lam2):
     b = L // M
     K = M * lam2
     off = offsets(N, lam1, lam2)
+    if samples is not None:
+        l = np.asarray(samples, dtype=np.int64)
+        y = M * np.fft.ifft(c, axis=1)           # y[n, r] = sum_m c(m, n) e^{2 pi i r m / M}
+        mods = [_unit_root(l * o, K, +1) for o in range(lam2)]
+        f = np.zeros(len(l), dtype=np.complex128)
+        for n in range(N):
+            f += g[(l - n * a) % L] * y[n, l % M] * mods[off[n]]
+        return f
     l = np.arange(L, dtype=np.int64)
     mods = [_unit_root(l * o, K, +1) for o in range(lam2)]
     f = np.zeros(L, dtype=np.complex128)

@@ -195,6 +195,10 @@ def test_adjoint(lat):
     c = rand_c(N, M)
     ref = np.einsum("lnm,nm->l", A, c)          # synthesis = sum c(m,n) atom
     assert rel(oracle.idgt_adjoint(c, g, a, M, l1, l2), ref) < 1e-13
+    # the evaluation at chosen samples (any order, repeats allowed) against
+    # the same brute-force synthesis
+    pts = RNG.integers(0, L, size=L // 2 + 3)
+    assert rel(oracle.idgt_adjoint(c, g, a, M, l1, l2, samples=pts), ref[pts]) < 1e-13
     f = rand_c(L)
     lhs = np.vdot(c, oracle.dgt_fold(f, g, a, M, l1, l2))       # <Cf, c>^*
     rhs = np.vdot(oracle.idgt_adjoint(c, g, a, M, l1, l2), f)
