@@ -144,6 +144,27 @@ def serving_plans() -> List[Tuple[int, int, int, int, int]]:
     return plans
 
 
+# Fig. 2 shapes (Section 4.4): L = lcm(a, M) 2520 for these (a, M), and
+# lambda = 1/lambda2 for lambda2 = 1..10 (lambda2 = 1 is the separable 0/1).
+CROSSOVER_AM = ((32, 64), (40, 60), (60, 80))
+
+
+def crossover_lattices() -> List[Tuple[int, int, int, int, int]]:
+    """The 30 (L, a, M, lam1, lam2) lattices of the crossover experiment;
+    2520 = lcm(1, ..., 10) makes every lambda2 feasible."""
+    out = []
+    for a, M in CROSSOVER_AM:
+        L = a * M // math.gcd(a, M) * 2520
+        for lam2 in range(1, 11):
+            out.append((L, a, M, 1 if lam2 > 1 else 0, lam2))
+    return out
+
+
+def crossover_batch(L: int) -> int:
+    """Signals per batch of the crossover experiment: about 2^22 samples."""
+    return max(1, (1 << 22) // L)
+
+
 def serving_requests(n: int = SERVE_REQUESTS, seed: int = seed_for(5, 0)):
     """Seeded request stream: for each request a plan index (uniform over the
     24 plans) and a signal seed."""

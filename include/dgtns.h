@@ -30,12 +30,18 @@
  *     dgtns_workspace_bytes.
  *   - Device work is enqueued asynchronously on `stream` (a hipStream_t; NULL
  *     means the default stream).  Calls return after enqueueing.
- *   - Argument and state errors are detected synchronously before any work is
- *     enqueued; outputs are then left untouched.  Launch failures return
- *     DGTNS_EDEVICE.  No call throws across the ABI.  A message for the last
- *     error of the calling thread is available from dgtns_last_error().
- *   - A plan is immutable once its window is set; calls on one plan may run
- *     concurrently on different streams if each uses its own workspace.
+ *   - Argument, state and size errors (DGTNS_EINVAL, DGTNS_ESTATE,
+ *     DGTNS_EWORKSPACE, DGTNS_EUNSUPPORTED) are detected synchronously before
+ *     any work of the call is enqueued: every call first checks each of its
+ *     launches (LDS request, transform sizes) without enqueueing, and
+ *     dgtns_check_op runs the same checks on the host alone.  Outputs are then
+ *     left untouched.  Launch failures return DGTNS_EDEVICE.  No call throws
+ *     across the ABI.  A message for the last error of the calling thread is
+ *     available from dgtns_last_error().
+ *   - Between two dgtns_set_window calls a plan is immutable: calls on one plan
+ *     may run concurrently on different streams if each uses its own
+ *     workspace.  dgtns_set_window rewrites the plan's window tables and must
+ *     not overlap other calls on the plan.
  */
 #ifndef DGTNS_H
 #define DGTNS_H
@@ -283,6 +289,18 @@ int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* 
  */
 int dgtns_tight_window(dgtns_plan plan, const void* g_dev, void* gt_dev, double* bounds_dev,
                        void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Host-only check (no device work, the plan need not be bound): returns
+ * DGTNS_OK if operation `op` (enum dgtns_op; DGTNS_OP_DUAL covers both
+ * dgtns_dual_window and dgtns_tight_window) on a batch of B is implemented for
+ * the plan, else the status the call itself would return before enqueueing
+ * anything (DGTNS_EUNSUPPORTED for an algorithm or size the kernels do not
+ * cover, with the reason in dgtns_last_error(); DGTNS_EINVAL for a bad op or
+ * B outside [1, max_batch]).  It runs the same per-launch checks every device
+ * call runs first.
+ */
+int dgtns_check_op(dgtns_plan plan, int op, int64_t B);
 
 /*
  * Kernel timing for profiling and benchmarks.  While enabled (process-wide),

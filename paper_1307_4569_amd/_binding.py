@@ -86,6 +86,7 @@ SIGNATURES = [
     ("dgtns_window_grad", ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_dual_window", ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_tight_window", ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    ("dgtns_check_op", ctypes.c_int, [c_vp, ctypes.c_int, c_i64]),
     ("dgtns_plan_destroy", ctypes.c_int, [c_vp]),
     ("dgtns_shearfind", ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.POINTER(c_i64)]),
     ("dgtns_noshear_factor", ctypes.c_int, [c_i64, c_i64, c_i64, c_i64, ctypes.POINTER(c_i64)]),
@@ -196,6 +197,10 @@ def dgtns_dual_window(plan, g_ptr, gd_ptr, bounds_ptr, ws_ptr, ws_bytes, stream)
 
 def dgtns_tight_window(plan, g_ptr, gt_ptr, bounds_ptr, ws_ptr, ws_bytes, stream):
     _call("dgtns_tight_window", plan, g_ptr, gt_ptr, bounds_ptr, ws_ptr, ws_bytes, stream)
+
+
+def dgtns_check_op(plan, op, B):
+    _call("dgtns_check_op", plan, op, B)
 
 
 def dgtns_plan_destroy(plan):

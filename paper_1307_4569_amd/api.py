@@ -9,6 +9,7 @@ streams, libdgtns does all the computation.
 """
 from __future__ import annotations
 
+import weakref
 from typing import Dict, Optional, Tuple
 
 import torch
@@ -79,6 +80,10 @@ class Plan:
             B.dgtns_plan_bind(self._h, self._pptr, nbytes, _stream_handle(self.device))
         self._ws: Dict[Tuple[int, int], torch.Tensor] = {}
         self.window: Optional[torch.Tensor] = None
+        # the tensor (and its in-place version) the resident window was set
+        # from, and a serial number that changes with every set_window
+        self._window_src = None
+        self.window_serial = 0
 
     # ------------------------------------------------------------------
     def __del__(self):
@@ -117,6 +122,14 @@ class Plan:
         ws, wsb = self.workspace(B.DGTNS_OP_SET_WINDOW, 1, st)
         B.dgtns_set_window(self._h, g64.data_ptr(), ws, wsb, st)
         self.window = g64
+        self._window_src = (weakref.ref(g), g._version)
+        self.window_serial += 1
+
+    def window_is(self, g: torch.Tensor) -> bool:
+        """True if the resident window was set from this very tensor and the
+        tensor has not been modified in place since."""
+        src = self._window_src
+        return src is not None and src[0]() is g and src[1] == g._version
 
     def _signals(self, f: torch.Tensor):
         if f.dim() == 1:
@@ -204,13 +217,22 @@ class DGTFunction(torch.autograd.Function):
 
     Backward: grad_f = C_g^* grad_c (the synthesis operator) and
     grad_g(j) = sum_k sum_n f_k(j + n a) conj(y_{k,n}(j + n a)), both computed
-    by libdgtns."""
+    by libdgtns.
+
+    The plan's resident window is prepared (dgtns_set_window) only when g is
+    not the tensor it was last set from, or was modified in place since: once
+    per training step when the optimiser updates g, not again in backward.
+    The function sets the window of the plan it is given, so one plan must
+    not serve two graphs with different windows on different streams at once
+    (give each its own plan)."""
 
     @staticmethod
     def forward(ctx, f, g, plan: Plan):
-        plan.set_window(g)
+        if not plan.window_is(g):
+            plan.set_window(g)
         c = plan.forward(f)
         ctx.plan = plan
+        ctx.serial = plan.window_serial
         ctx.save_for_backward(f, g)
         return c
 
@@ -218,7 +240,10 @@ class DGTFunction(torch.autograd.Function):
     def backward(ctx, gc):
         f, g = ctx.saved_tensors
         plan = ctx.plan
-        plan.set_window(g)
+        # autograd has checked that g is unchanged since forward; the window
+        # is prepared again only if another window was set in between
+        if plan.window_serial != ctx.serial:
+            plan.set_window(g)
         gf = gg = None
         if ctx.needs_input_grad[0]:
             gf = plan.adjoint(gc)

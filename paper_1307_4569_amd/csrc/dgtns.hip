@@ -23,8 +23,10 @@ namespace dgtns {
 namespace host {
 
 thread_local std::string g_err;
+thread_local bool g_dry = false;
 
 void set_last_error(const std::string& msg) { g_err = msg; }
+bool dry_run() { return g_dry; }
 
 Timing& timing() {
   static Timing t;
@@ -80,6 +82,17 @@ void give_sync_event(hipEvent_t e) {
 
 namespace {
 
+// Runs a call's body once dry (every launch checked, nothing enqueued), then
+// for real: a refusal always comes before the first kernel of the call.
+template <typename F>
+int run_checked(F body) {
+  g_dry = true;
+  int rc = body();
+  g_dry = false;
+  if (rc) return rc;
+  return body();
+}
+
 int check_call(dgtns_plan plan, int64_t B, void* ws, size_t ws_bytes, int op, Layout* lay) {
   if (!plan) return fail(DGTNS_EINVAL, "null plan");
   const Plan& P = plan->p;
@@ -102,6 +115,46 @@ void put_tab(std::vector<unsigned char>& img, size_t off, const std::vector<doub
     float* d = reinterpret_cast<float*>(img.data() + off);
     for (size_t i = 0; i < v.size(); ++i) d[i] = float(v[i]);
   }
+}
+
+// Bodies of the device calls after argument validation: refusals for the
+// plan's algorithm and sizes, then the launches.  Each runs dry first
+// (run_checked) and can be checked alone by dgtns_check_op.
+int forward_body(const Plan& P, const void* f, int real_input, void* c, int64_t B, char* w, const Layout& l,
+                 hipStream_t st) {
+  if (P.dtype == 0) return forward_c64(P, f, real_input ? 1 : 0, c, B, w, l, st);
+  return forward_c128(P, f, real_input ? 1 : 0, c, B, w, l, st);
+}
+
+int adjoint_body(const Plan& P, const void* c, void* f, int64_t B, char* w, const Layout& l, hipStream_t st) {
+  if (P.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "shear-OLA plans compute the forward transform only");
+  if (P.dtype == 0) return adjoint_c64(P, c, f, B, w, l, st);
+  return adjoint_c128(P, c, f, B, w, l, st);
+}
+
+int grad_body(const Plan& P, const void* f, const void* gc, void* gg, int64_t B, char* w, const Layout& l,
+              hipStream_t st) {
+  if (P.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "shear-OLA plans compute the forward transform only");
+  if (P.branch == kMultiwindow || P.branch == kFir)
+    return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for shear-algorithm plans only");
+  if (P.pi != 1) return fail(DGTNS_EUNSUPPORTED, "window gradient is implemented for p = 1 of the sheared lattice");
+  if (P.dtype == 0) return grad_c64(P, f, gc, gg, B, w, l, st);
+  return grad_c128(P, f, gc, gg, B, w, l, st);
+}
+
+int set_window_body(const Plan& P, const double2* g, char* w, const Layout& l, hipStream_t st) {
+  return P.dtype == 0 ? set_window_c64(P, g, w, l, st) : set_window_c128(P, g, w, l, st);
+}
+
+int dual_body(const Plan& P, const double2* g, double2* out, double* bounds, char* w, const Layout& l, bool tight,
+              hipStream_t st) {
+  if (P.branch == kMultiwindow || P.branch == kFir || P.branch == kShearOla)
+    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are computed with shear-algorithm plans");
+  if (P.pi > kDualMaxP)
+    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p <= 8 of the sheared lattice");
+  if (P.longd)
+    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows need columns held by one in-LDS transform (this plan splits them in two passes)");
+  return dual_c128(P, g, out, bounds, w, l, tight, st);
 }
 
 }  // namespace
@@ -258,7 +311,7 @@ int dgtns_set_window(dgtns_plan plan, const void* g_dev, void* ws, size_t ws_byt
   hipStream_t st = static_cast<hipStream_t>(stream);
   const double2* g = static_cast<const double2*>(g_dev);
   char* w = static_cast<char*>(ws);
-  rc = P.dtype == 0 ? set_window_c64(P, g, w, l, st) : set_window_c128(P, g, w, l, st);
+  rc = run_checked([&] { return set_window_body(P, g, w, l, st); });
   if (rc) return rc;
   P.window_set = true;
   if (P.inner) P.inner->window_set = true;
@@ -274,8 +327,7 @@ int dgtns_forward(dgtns_plan plan, const void* f_dev, int real_input, void* c_de
   const Plan& P = plan->p;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  if (P.dtype == 0) return forward_c64(P, f_dev, real_input ? 1 : 0, c_dev, B, w, l, st);
-  return forward_c128(P, f_dev, real_input ? 1 : 0, c_dev, B, w, l, st);
+  return run_checked([&] { return forward_body(P, f_dev, real_input, c_dev, B, w, l, st); });
 }
 
 int dgtns_forward_batch(dgtns_plan plan, const void* const* f_list, int real_input, void* const* c_list, int64_t B,
@@ -291,8 +343,10 @@ int dgtns_forward_batch(dgtns_plan plan, const void* const* f_list, int real_inp
   const Plan& P = plan->p;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  if (P.dtype == 0) return forward_list_c64(P, f_list, real_input ? 1 : 0, c_list, B, w, l, st);
-  return forward_list_c128(P, f_list, real_input ? 1 : 0, c_list, B, w, l, st);
+  return run_checked([&] {
+    if (P.dtype == 0) return forward_list_c64(P, f_list, real_input ? 1 : 0, c_list, B, w, l, st);
+    return forward_list_c128(P, f_list, real_input ? 1 : 0, c_list, B, w, l, st);
+  });
 }
 
 int dgtns_adjoint(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, void* ws, size_t ws_bytes,
@@ -302,11 +356,9 @@ int dgtns_adjoint(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, vo
   if (rc) return rc;
   if (!f_dev || !c_dev) return fail(DGTNS_EINVAL, "null signal or coefficient pointer");
   const Plan& P = plan->p;
-  if (P.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "shear-OLA plans compute the forward transform only");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  if (P.dtype == 0) return adjoint_c64(P, c_dev, f_dev, B, w, l, st);
-  return adjoint_c128(P, c_dev, f_dev, B, w, l, st);
+  return run_checked([&] { return adjoint_body(P, c_dev, f_dev, B, w, l, st); });
 }
 
 int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, void* gg_dev, int64_t B, void* ws,
@@ -316,12 +368,9 @@ int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, vo
   if (rc) return rc;
   if (!f_dev || !gc_dev || !gg_dev) return fail(DGTNS_EINVAL, "null argument");
   const Plan& P = plan->p;
-  if (P.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "shear-OLA plans compute the forward transform only");
-  if (P.pi != 1) return fail(DGTNS_EUNSUPPORTED, "window gradient is implemented for p = 1 of the sheared lattice");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  if (P.dtype == 0) return grad_c64(P, f_dev, gc_dev, gg_dev, B, w, l, st);
-  return grad_c128(P, f_dev, gc_dev, gg_dev, B, w, l, st);
+  return run_checked([&] { return grad_body(P, f_dev, gc_dev, gg_dev, B, w, l, st); });
 }
 
 static int dual_or_tight(dgtns_plan plan, const void* g_dev, void* out_dev, double* bounds_dev, void* ws,
@@ -331,16 +380,12 @@ static int dual_or_tight(dgtns_plan plan, const void* g_dev, void* out_dev, doub
   if (rc) return rc;
   if (!g_dev || !out_dev || !bounds_dev) return fail(DGTNS_EINVAL, "null argument");
   const Plan& P = plan->p;
-  if (P.branch == kMultiwindow || P.branch == kFir || P.branch == kShearOla)
-    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are computed with shear-algorithm plans");
-  if (P.pi > kDualMaxP)
-    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p <= 8 of the sheared lattice");
-  if (P.longd)
-    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows need columns held by one in-LDS transform (this plan splits them in two passes)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
-  return dual_c128(P, static_cast<const double2*>(g_dev), static_cast<double2*>(out_dev), bounds_dev, w, l, tight,
-                   st);
+  return run_checked([&] {
+    return dual_body(P, static_cast<const double2*>(g_dev), static_cast<double2*>(out_dev), bounds_dev, w, l, tight,
+                     st);
+  });
 }
 
 int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* bounds_dev, void* ws,
@@ -351,6 +396,35 @@ int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* 
 int dgtns_tight_window(dgtns_plan plan, const void* g_dev, void* gt_dev, double* bounds_dev, void* ws,
                        size_t ws_bytes, void* stream) {
   return dual_or_tight(plan, g_dev, gt_dev, bounds_dev, ws, ws_bytes, stream, true);
+}
+
+int dgtns_check_op(dgtns_plan plan, int op, int64_t B) {
+  if (!plan) return fail(DGTNS_EINVAL, "null plan");
+  if (op < 0 || op > DGTNS_OP_DUAL) return fail(DGTNS_EINVAL, "unknown operation");
+  const Plan& P = plan->p;
+  if (B < 1 || B > P.max_batch) return fail(DGTNS_EINVAL, "batch must be in [1, max_batch]");
+  const Layout l = ws_layout(P, op, (op == DGTNS_OP_SET_WINDOW || op == DGTNS_OP_DUAL) ? 1 : B);
+  // placeholder addresses: a dry run computes launch arguments but never
+  // dereferences or enqueues them
+  char* w = reinterpret_cast<char*>(uintptr_t(1) << 12);
+  void* x = w;
+  int rc = DGTNS_OK;
+  g_dry = true;
+  switch (op) {
+    case DGTNS_OP_FORWARD: rc = forward_body(P, x, 0, x, B, w, l, nullptr); break;
+    case DGTNS_OP_ADJOINT: rc = adjoint_body(P, x, x, B, w, l, nullptr); break;
+    case DGTNS_OP_WINDOW_GRAD: rc = grad_body(P, x, x, x, B, w, l, nullptr); break;
+    case DGTNS_OP_SET_WINDOW: rc = set_window_body(P, static_cast<const double2*>(x), w, l, nullptr); break;
+    default: {
+      rc = dual_body(P, static_cast<const double2*>(x), static_cast<double2*>(x), static_cast<double*>(x), w, l,
+                     false, nullptr);
+      if (!rc)
+        rc = dual_body(P, static_cast<const double2*>(x), static_cast<double2*>(x), static_cast<double*>(x), w, l,
+                       true, nullptr);
+    }
+  }
+  g_dry = false;
+  return rc;
 }
 
 int dgtns_timing_enable(int on) {

@@ -36,6 +36,12 @@ inline int check_hip(hipError_t e, const char* what) {
 
 inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Dry run of a call (per thread): every launcher checks its launch (LDS
+// request, workspace pointers, supported sizes) and returns without
+// enqueueing anything.  Each entry point runs its body dry first, so every
+// refusal is reported before the first kernel of the call is enqueued.
+bool dry_run();
+
 // ---------------------------------------------------------------------------
 // Two-stream pipeline over chunks of the batch (time-shear branch): stage 1
 // of chunk k runs on the caller's stream into h buffer k mod 2, stage 2 of
@@ -54,13 +60,22 @@ inline bool pipelined(const Plan& P, long long B, int op) {
 
 template <typename S1, typename S2>
 int run_pipeline(long long B, long long chunk, hipStream_t st, S1 stage1, S2 stage2) {
+  const long long nch = (B + chunk - 1) / chunk;
+  if (dry_run()) {   // the stages of every chunk, no streams or events
+    for (long long k = 0; k < nch; ++k) {
+      const long long b0 = k * chunk, nb = B - b0 < chunk ? B - b0 : chunk;
+      int rc = stage1(b0, nb, int(k & 1), st);
+      if (!rc) rc = stage2(b0, nb, int(k & 1), st);
+      if (rc) return rc;
+    }
+    return DGTNS_OK;
+  }
   hipStream_t hs = helper_stream();
   if (!hs) return fail(DGTNS_EDEVICE, "could not create the helper stream");
   hipEvent_t eA[2] = {take_sync_event(), take_sync_event()};
   hipEvent_t eB[2] = {take_sync_event(), take_sync_event()};
   int rc = DGTNS_OK;
   long long last = -1;
-  const long long nch = (B + chunk - 1) / chunk;
   for (long long k = 0; k < nch && rc == DGTNS_OK; ++k) {
     const long long b0 = k * chunk, nb = B - b0 < chunk ? B - b0 : chunk;
     const int buf = int(k & 1);
@@ -106,6 +121,7 @@ inline hipEvent_t take_event(Timing& t) {
 
 template <typename K, typename... A>
 int launch_raw(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, const char* name, A... args) {
+  if (dry_run()) return DGTNS_OK;
   Timing& t = timing();
   hipEvent_t ea = nullptr, eb = nullptr;
   if (t.on) {
@@ -130,6 +146,7 @@ template <typename K, typename... A>
 int launch_v(K kernel, dim3 grid, size_t lds, hipStream_t st, const char* name, A... args) {
   if (grid.x == 0 || grid.y == 0) return DGTNS_OK;
   if (lds > 160 * 1024) return fail(DGTNS_EUNSUPPORTED, std::string(name) + ": LDS request above 160 KiB");
+  if (dry_run()) return DGTNS_OK;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -145,11 +162,13 @@ int launch(K kernel, dim3 grid, size_t lds, hipStream_t st, const A& args, const
 
 inline unsigned cdiv(long long a, long long b) { return unsigned((a + b - 1) / b); }
 
+// Device address of a table in the plan's persistent block (integer
+// arithmetic: a dry run of an unbound plan computes addresses it never uses).
 template <typename C> const C* tab(const Plan& P, size_t off) {
-  return reinterpret_cast<const C*>(static_cast<const char*>(P.dev) + off);
+  return reinterpret_cast<const C*>(reinterpret_cast<uintptr_t>(P.dev) + off);
 }
 template <typename C> C* mtab(const Plan& P, size_t off) {
-  return reinterpret_cast<C*>(static_cast<char*>(P.dev) + off);
+  return reinterpret_cast<C*>(reinterpret_cast<uintptr_t>(P.dev) + off);
 }
 
 inline FftSched sched(const FftSchedule& s) {
@@ -1005,7 +1024,7 @@ int window_zak(const Plan& P, const double2* g, CO* zc_out, double2* z64_out, ch
     while (W > 1 && (W * P.pi * P.d2 > 4096 || 16 * (P.d2 + size_t(W) * P.pi * S) > (64u << 10))) --W;
     const size_t zl = 16 * (P.d2 + size_t(W) * P.pi * S);
     if (zl > 160 * 1024) return fail(DGTNS_EUNSUPPORTED, "window Zak: LDS request above 160 KiB");
-    if (zl > 64 * 1024) {
+    if (zl > 64 * 1024 && !dry_run()) {
       rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_long_zak<CO>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(zl)),
                      "window Zak");

@@ -68,7 +68,7 @@ def test_window_gradient_matches_oracle(dtype, kernel_path):
         ref = sum(oracle.window_gradient(f[k], G[k], a, M, l1, l2) for k in range(B))
         e = rel(gg, ref)
         print("window gradient", kernel_path, dtype, lat, e)
-        assert e < TOL[dtype] * 5, (lat, e)
+        assert e < TOL[dtype], (lat, e)
     assert {1, 2} <= seen
 
 
@@ -249,6 +249,37 @@ def test_autograd_matches_oracle_gradients(lat):
     assert abs(loss.item() - l_ref) < 1e-12 * l_ref
     assert rel(ft.grad.cpu().numpy(), np.stack(gf_ref)) < 1e-12
     assert rel(gt.grad.cpu().numpy(), gg_ref) < 1e-12
+    # the window was prepared once for the forward and backward of this step
+    assert plan.window_serial == 1
+
+
+def test_autograd_prepares_the_window_once_per_step():
+    """DGTFunction prepares the plan's window only when the window tensor is
+    new or was updated in place (an optimiser step), and prepares it again
+    in backward only if another window was set after the forward."""
+    from paper_1307_4569_amd import DGTFunction
+    lat = (144, 6, 12, 1, 2)
+    plan = plan_for(lat, torch.complex128, 1)
+    f = torch.tensor(complex_normal(144, 70), device="cuda", requires_grad=True)
+    g = torch.tensor(gaussian_window(144, 6, 12), device="cuda", requires_grad=True)
+    opt = torch.optim.SGD([g], lr=1e-3)
+    for step in range(3):
+        opt.zero_grad()
+        c = DGTFunction.apply(f, g, plan)
+        (c.abs() ** 2).sum().backward()
+        assert plan.window_serial == step + 1
+        opt.step()
+    # a window set between forward and backward is replaced by the saved one
+    c = DGTFunction.apply(f, g, plan)
+    other = torch.tensor(complex_normal(144, 71), device="cuda")
+    plan.set_window(other)
+    g.grad = None
+    (c.abs() ** 2).sum().backward()
+    assert plan.window_serial == 6
+    f_np, g_np = f.detach().cpu().numpy(), g.detach().cpu().numpy()
+    c_ref = oracle.dgt_fold(f_np, g_np, 6, 12, 1, 2)
+    gg_ref = oracle.window_gradient(f_np, 2 * c_ref, 6, 12, 1, 2)
+    assert rel(g.grad.cpu().numpy(), gg_ref) < 1e-12
 
 
 def test_gradient_workload():
@@ -280,7 +311,7 @@ def test_gradient_workload():
         _, gf, _ = oracle.loss_and_grads(f32[k], g32, Tn, w.a, w.M, w.lam1, w.lam2)
         gf_err.append(rel(ft.grad[k].cpu().numpy(), gf))
     print("gradient workload grad_f rel err vs oracle", gf_err)
-    assert max(gf_err) < 1e-4
+    assert max(gf_err) < 1e-5
     sub = torch.tensor(f32[:2].astype(np.complex64), device="cuda", requires_grad=True)
     gsub = torch.tensor(g0.astype(np.complex64), device="cuda", requires_grad=True)
     plan2 = plan_for(lat, torch.complex64, 2)
@@ -289,7 +320,7 @@ def test_gradient_workload():
     gg_ref = sum(oracle.loss_and_grads(f32[k], g32, Tn, w.a, w.M, w.lam1, w.lam2)[2] for k in range(2))
     e_gg = rel(gsub.grad.cpu().numpy(), gg_ref)
     print("gradient workload grad_g rel err vs oracle", e_gg)
-    assert e_gg < 1e-4
+    assert e_gg < 1e-5
     # FP64 central differences on the full batch
     plan64 = plan_for(lat, torch.complex128, w.batch)
     f64 = torch.tensor(f, device="cuda", requires_grad=True)
@@ -303,7 +334,7 @@ def test_gradient_workload():
     L0.backward()
     rng = np.random.default_rng(123)
     h = 1e-6
-    for i in range(3):
+    for i in range(16):
         df = torch.tensor(rng.standard_normal(f.shape) + 1j * rng.standard_normal(f.shape), device="cuda")
         dg = torch.tensor(rng.standard_normal(w.L) + 1j * rng.standard_normal(w.L), device="cuda") * 1e-2
         with torch.no_grad():

@@ -179,7 +179,7 @@ def test_maximum_in_lds_sizes(lat, dtype):
         Gs = round_to(np.stack([complex_normal(L // a * M, 542 + k).reshape(L // a, M) for k in range(2)]),
                       dtype == torch.complex64)
         ref = sum(oracle.window_gradient(f[k], Gs[k], a, M, l1, l2) for k in range(2))
-        assert rel(gg, ref) < 5 * TOL[dtype], ("window gradient", lat, rel(gg, ref))
+        assert rel(gg, ref) < TOL[dtype], ("window gradient", lat, rel(gg, ref))
         gw = gaussian_window(L, a, M)
         gd, _ = plan.dual(torch.tensor(gw))
         pts = np.linspace(0, L - 1, 16).astype(np.int64)
@@ -290,7 +290,7 @@ def full_size(w, dtype, B, columns, real=False, window=None):
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
 def test_large_workload_sampled(dtype, kernel_path):
     w = LARGE
-    B = w.batch if dtype == torch.complex64 else 8
+    B = w.batch
     cols = list(range(0, w.N, 97)) + [w.N - 1]
     plan, f, c, errs = full_size(w, dtype, B, cols)
     print("large workload", kernel_path, dtype, "B", B, "errors", errs)

@@ -134,11 +134,16 @@ SERVING_FREQ_SHEAR = {(36864, 32, 256), (73728, 32, 256), (36864, 64, 512), (737
 
 def test_workload_plans(lib):
     from dgt_inputs import GRADIENT, LARGE, PRECISION, SMALL, serving_plans
-    for w in (SMALL, LARGE, PRECISION, GRADIENT):
+    # the small workload has q = 2 (c = 6, d = 12); the others q = 8
+    for w, q in ((SMALL, 2), (LARGE, 8), (PRECISION, 8), (GRADIENT, 8)):
         h = B.dgtns_plan_create(w.L, w.a, w.M, w.lam1, w.lam2, 0, 1)
         i = B.dgtns_plan_info(h)
-        assert i.branch == B.DGTNS_TIME_SHEAR and i.s0 == 0 and i.p == 1 and i.q == 8 or w is SMALL
         B.dgtns_plan_destroy(h)
+        assert (i.branch, i.s0, i.p, i.q) == (B.DGTNS_TIME_SHEAR, 0, 1, q), (w, i.branch, i.s0, i.p, i.q)
+    h = B.dgtns_plan_create(SMALL.L, SMALL.a, SMALL.M, SMALL.lam1, SMALL.lam2, 1, 1)
+    i = B.dgtns_plan_info(h)
+    B.dgtns_plan_destroy(h)
+    assert (i.s1, i.c, i.d) == (-1, 6, 12)
     nfs = 0
     for (L, a, M, l1, l2) in serving_plans():
         h = B.dgtns_plan_create(L, a, M, l1, l2, 0, 8)
@@ -290,3 +295,111 @@ def test_error_paths_without_device(lib):
     with pytest.raises(B.DgtnsError):
         B.dgtns_workspace_bytes(h, 99, 1)
     B.dgtns_plan_destroy(h)
+
+
+OPS = (B.DGTNS_OP_FORWARD, B.DGTNS_OP_ADJOINT, B.DGTNS_OP_WINDOW_GRAD, B.DGTNS_OP_SET_WINDOW, B.DGTNS_OP_DUAL)
+
+
+def check_op(h, op, batch=1):
+    """Status of dgtns_check_op (host only) and its message."""
+    try:
+        B.dgtns_check_op(h, op, batch)
+        return B.DGTNS_OK, ""
+    except B.DgtnsError as e:
+        return e.status, str(e)
+
+
+# (plan constructor arguments, operation, phrase of the refusal message):
+# every DGTNS_EUNSUPPORTED refusal of a device call, found on the host
+REFUSALS = [
+    (("ola", 6144, 16, 64, 1, 2, 0, 2, 6000, 300, 1024), B.DGTNS_OP_ADJOINT, "forward transform only"),
+    (("ola", 6144, 16, 64, 1, 2, 0, 2, 6000, 300, 1024), B.DGTNS_OP_WINDOW_GRAD, "forward transform only"),
+    (("ola", 6144, 16, 64, 1, 2, 0, 2, 6000, 300, 1024), B.DGTNS_OP_DUAL, "shear-algorithm plans"),
+    (("fir", 144, 6, 12, 1, 2, 0, 2, 140, 20), B.DGTNS_OP_WINDOW_GRAD, "shear-algorithm plans"),
+    (("fir", 144, 6, 12, 1, 2, 0, 2, 140, 20), B.DGTNS_OP_DUAL, "shear-algorithm plans"),
+    (("mw", 144, 6, 12, 1, 2, 0, 2), B.DGTNS_OP_WINDOW_GRAD, "shear-algorithm plans"),
+    (("mw", 144, 6, 12, 1, 2, 0, 2), B.DGTNS_OP_DUAL, "shear-algorithm plans"),
+    (("shear", 180, 9, 10, 0, 1, 0, 2), B.DGTNS_OP_DUAL, "p <= 8"),                    # p = 9
+    (("shear", 48, 4, 6, 1, 2, 0, 2), B.DGTNS_OP_WINDOW_GRAD, "p = 1"),                # p = 2
+    (("shear", 161280, 32, 64, 1, 2, 0, 2), B.DGTNS_OP_DUAL, "two passes"),            # d = 20160
+    (("shear", 1 << 20, 32, 64, 1, 2, 1, 2), B.DGTNS_OP_DUAL, "two passes"),           # d = 16384
+]
+
+
+def make(args):
+    kind, rest = args[0], args[1:]
+    if kind == "ola":
+        return B.dgtns_plan_create_ola(*rest)
+    if kind == "fir":
+        return B.dgtns_plan_create_fir(*rest)
+    if kind == "mw":
+        return B.dgtns_plan_create_alg(*rest, B.DGTNS_ALG_MULTIWINDOW)
+    return B.dgtns_plan_create(*rest)
+
+
+@pytest.mark.parametrize("args,op,phrase", REFUSALS)
+def test_every_refusal_is_found_on_the_host(lib, args, op, phrase):
+    """dgtns_check_op runs a call's per-launch checks on the host, on an
+    unbound plan: each unsupported operation is refused with its reason, and
+    the device call runs the same checks before it enqueues anything."""
+    h = make(args)
+    try:
+        st, msg = check_op(h, op)
+        assert st == B.DGTNS_EUNSUPPORTED and phrase in msg, (args, op, st, msg)
+        # the transforms of the plan pass the same checks
+        for other in (B.DGTNS_OP_FORWARD, B.DGTNS_OP_SET_WINDOW) + ((B.DGTNS_OP_ADJOINT,) if args[0] != "ola" else ()):
+            assert check_op(h, other) == (B.DGTNS_OK, ""), (args, other)
+    finally:
+        B.dgtns_plan_destroy(h)
+
+
+def test_check_op_arguments(lib):
+    h = B.dgtns_plan_create(144, 6, 12, 1, 2, 0, 4)
+    try:
+        assert check_op(h, 99)[0] == B.DGTNS_EINVAL
+        assert check_op(h, B.DGTNS_OP_FORWARD, 0)[0] == B.DGTNS_EINVAL
+        assert check_op(h, B.DGTNS_OP_FORWARD, 5)[0] == B.DGTNS_EINVAL       # above max_batch
+        assert check_op(h, B.DGTNS_OP_FORWARD, 4)[0] == B.DGTNS_OK
+    finally:
+        B.dgtns_plan_destroy(h)
+    assert lib.dgtns_check_op(None, 0, 1) == B.DGTNS_EINVAL
+
+
+# the largest sizes of the GPU tests: rows of 4096 channels, columns of 4096
+# values, p d at the element budgets and beyond (two-level columns)
+LARGE_LATTICES = [(65536, 64, 4096, 0, 1), (65536, 16, 16, 1, 2), (32768, 8, 8, 0, 1), (65536, 64, 4096, 1, 2),
+                  (131072, 64, 8192, 1, 2), (49152, 8, 12, 0, 1), (49152, 8, 12, 1, 2), (98304, 8, 12, 1, 2),
+                  (36864, 12, 8, 0, 1), (73728, 12, 8, 0, 1), (1 << 20, 128, 1024, 1, 4), (262144, 64, 512, 1, 2),
+                  (302400, 40, 60, 1, 4), (604800, 60, 80, 1, 5), (161280, 32, 64, 1, 2)]
+
+
+def test_check_op_sweep(lib):
+    """Every operation on every small feasible lattice (both precisions, the
+    shear and multiwindow algorithms, FIR plans) and on the largest sizes:
+    the host check either passes or refuses with DGTNS_EUNSUPPORTED, and the
+    forward and adjoint transforms of shear and multiwindow plans always
+    pass."""
+    seen = {B.DGTNS_OK: 0, B.DGTNS_EUNSUPPORTED: 0}
+    lats = feasible_lattices(max_L=72, max_lam2=3) + LARGE_LATTICES
+    for lat in lats:
+        for dt in (0, 1):
+            for alg in (B.DGTNS_ALG_SHEAR, B.DGTNS_ALG_MULTIWINDOW, B.DGTNS_ALG_FIR):
+                try:
+                    if alg == B.DGTNS_ALG_FIR:
+                        h = B.dgtns_plan_create_fir(*lat, dt, 3, lat[0] - 1, max(1, lat[0] // 3))
+                    else:
+                        h = B.dgtns_plan_create_alg(*lat, dt, 3, alg)
+                except B.DgtnsError as e:
+                    assert e.status in (B.DGTNS_EUNSUPPORTED, B.DGTNS_ELATTICE), (lat, alg, e)
+                    continue
+                try:
+                    for op in OPS:
+                        for batch in (1, 3):
+                            st, msg = check_op(h, op, batch)
+                            assert st in seen, (lat, dt, alg, op, st, msg)
+                            seen[st] += 1
+                            if op in (B.DGTNS_OP_FORWARD, B.DGTNS_OP_ADJOINT, B.DGTNS_OP_SET_WINDOW):
+                                assert st == B.DGTNS_OK, (lat, dt, alg, op, msg)
+                finally:
+                    B.dgtns_plan_destroy(h)
+    assert seen[B.DGTNS_OK] > 1000 and seen[B.DGTNS_EUNSUPPORTED] > 100
