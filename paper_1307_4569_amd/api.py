@@ -9,7 +9,6 @@ streams, libdgtns does all the computation.
 """
 from __future__ import annotations
 
-import weakref
 from typing import Dict, Optional, Tuple
 
 import torch
@@ -80,9 +79,7 @@ class Plan:
             B.dgtns_plan_bind(self._h, self._pptr, nbytes, _stream_handle(self.device))
         self._ws: Dict[Tuple[int, int], torch.Tensor] = {}
         self.window: Optional[torch.Tensor] = None
-        # the tensor (and its in-place version) the resident window was set
-        # from, and a serial number that changes with every set_window
-        self._window_src = None
+        # changes with every set_window
         self.window_serial = 0
 
     # ------------------------------------------------------------------
@@ -122,14 +119,7 @@ class Plan:
         ws, wsb = self.workspace(B.DGTNS_OP_SET_WINDOW, 1, st)
         B.dgtns_set_window(self._h, g64.data_ptr(), ws, wsb, st)
         self.window = g64
-        self._window_src = (weakref.ref(g), g._version)
         self.window_serial += 1
-
-    def window_is(self, g: torch.Tensor) -> bool:
-        """True if the resident window was set from this very tensor and the
-        tensor has not been modified in place since."""
-        src = self._window_src
-        return src is not None and src[0]() is g and src[1] == g._version
 
     def _signals(self, f: torch.Tensor):
         if f.dim() == 1:
@@ -219,17 +209,17 @@ class DGTFunction(torch.autograd.Function):
     grad_g(j) = sum_k sum_n f_k(j + n a) conj(y_{k,n}(j + n a)), both computed
     by libdgtns.
 
-    The plan's resident window is prepared (dgtns_set_window) only when g is
-    not the tensor it was last set from, or was modified in place since: once
-    per training step when the optimiser updates g, not again in backward.
-    The function sets the window of the plan it is given, so one plan must
-    not serve two graphs with different windows on different streams at once
+    The plan's resident window is prepared (dgtns_set_window) once per
+    forward, from the values g holds at that moment (a tensor's values can
+    change without a version bump, e.g. through .data), and not again in
+    backward unless another window was set on the plan in between.  The
+    function sets the window of the plan it is given, so one plan must not
+    serve two graphs with different windows on different streams at once
     (give each its own plan)."""
 
     @staticmethod
     def forward(ctx, f, g, plan: Plan):
-        if not plan.window_is(g):
-            plan.set_window(g)
+        plan.set_window(g)
         c = plan.forward(f)
         ctx.plan = plan
         ctx.serial = plan.window_serial

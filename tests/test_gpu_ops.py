@@ -254,9 +254,8 @@ def test_autograd_matches_oracle_gradients(lat):
 
 
 def test_autograd_prepares_the_window_once_per_step():
-    """DGTFunction prepares the plan's window only when the window tensor is
-    new or was updated in place (an optimiser step), and prepares it again
-    in backward only if another window was set after the forward."""
+    """DGTFunction prepares the plan's window once per forward, and prepares
+    it again in backward only if another window was set after the forward."""
     from paper_1307_4569_amd import DGTFunction
     lat = (144, 6, 12, 1, 2)
     plan = plan_for(lat, torch.complex128, 1)
