@@ -18,7 +18,10 @@ Contents and the passages they follow:
   window S^{-1} g, canonical tight window S^{-1/2} g (Section 4.2), frame
   bounds;
 * ``grad.*`` -- gradients of a spectrogram loss with respect to the signal and
-  the window.
+  the window;
+* ``real.*`` -- the real-signal variant named in Section 4.4: the
+  non-redundant channels of the conjugate-symmetric columns of eq. (DGT) for a
+  real signal and window, and the synthesis of such coefficients.
 
 Every function is pinned by tests in ``tests/test_oracle.py`` against
 brute force, closed forms, library routines and invariants.
@@ -28,10 +31,11 @@ from .dgt import (coefficient_frequencies, dgt_direct, dgt_fold, dgt_multiwindow
 from .dual import (dual_window, frame_blocks, frame_bounds, frame_operator_apply, tight_window,
                    walnut_weights)
 from .grad import loss_and_grads, spectrogram_loss, window_gradient
+from .real import dgtreal, idgtreal, pack_real, real_layout, unpack_real
 
 __all__ = [
     "coefficient_frequencies", "dgt_direct", "dgt_fold", "dgt_multiwindow", "dgt_separable",
     "idgt_adjoint", "offsets", "dual_window", "frame_blocks", "frame_bounds",
     "frame_operator_apply", "tight_window", "walnut_weights", "loss_and_grads", "spectrogram_loss",
-    "window_gradient",
+    "window_gradient", "dgtreal", "idgtreal", "pack_real", "real_layout", "unpack_real",
 ]

@@ -348,3 +348,87 @@ def test_small_workload_shape():
     c = oracle.dgt_fold(f, g, SMALL.a, SMALL.M, SMALL.lam1, SMALL.lam2)
     assert c.shape == (24, 12)
     assert abs(np.linalg.norm(g) - 1) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Real-signal variant: conjugate symmetry of the columns with w(n) in {0, 1/2}
+# ---------------------------------------------------------------------------
+
+REAL_LATTICES = [(36, 6, 6, 0, 1), (36, 6, 6, 1, 2), (36, 6, 6, 1, 3), (36, 6, 6, 2, 3), (64, 4, 8, 1, 4),
+                 (60, 5, 6, 1, 2), (72, 6, 4, 1, 3), (144, 6, 12, 1, 2), (60, 6, 5, 1, 2), (72, 4, 9, 1, 2),
+                 (144, 4, 9, 1, 4), (64, 2, 8, 3, 4)]
+
+
+@pytest.mark.parametrize("lat", REAL_LATTICES)
+def test_real_signal_symmetry_from_atoms(lat):
+    """For a real signal and a real window, the explicit atoms give
+    c((-m - e) mod M, n) = conj(c(m, n)) in every column whose offset w(n) is
+    0 or 1/2 (e = 2 w(n)), and not in the other columns; the layout keeps
+    exactly the channels that determine each column (even and odd M)."""
+    from oracle.real import real_layout
+    L, a, M, l1, l2 = lat
+    f, g = RNG.standard_normal(L), RNG.standard_normal(L)
+    A = brute_force_atoms(g.astype(np.complex128), L, a, M, l1, l2)
+    c = np.einsum("l,lnm->nm", f, np.conj(A))
+    N = L // a
+    S, off, count, e = real_layout(M, l1, l2)
+    nsym = 0
+    for n in range(N):
+        k = n % l2
+        w2 = (2 * ((n * l1) % l2))
+        m = np.arange(M)
+        if w2 % l2 == 0:
+            nsym += 1
+            assert e[k] == w2 // l2 and count[k] == M // 2 + 1
+            assert np.allclose(c[n, (-m - e[k]) % M], np.conj(c[n]), atol=1e-12)
+            # every orbit {m, -m - e} has a member among the stored channels
+            assert set(np.minimum(m, (-m - e[k]) % M)) <= set(range(count[k]))
+        else:
+            assert e[k] is None and count[k] == M
+            # the negated frequencies are off the lattice: no symmetry
+            assert not np.allclose(c[n, (-m) % M], np.conj(c[n]), atol=1e-6)
+            assert not np.allclose(c[n, (-m - 1) % M], np.conj(c[n]), atol=1e-6)
+    assert S == sum(count) and nsym == N // l2 * (1 + (l2 % 2 == 0))
+
+
+@pytest.mark.parametrize("lat", REAL_LATTICES)
+def test_real_signal_pack_unpack_and_synthesis(lat):
+    """The stored channels determine the transform of a real signal (unpack
+    restores the brute-force coefficients); the synthesis of real-signal
+    coefficients is the adjoint of the transform under the real inner
+    product (Re <C f, E c> = <f, synthesis(c)> with E the expansion); with
+    the canonical dual window it reconstructs the signal."""
+    from oracle.real import dgtreal, idgtreal, pack_real, real_layout, unpack_real
+    L, a, M, l1, l2 = lat
+    N = L // a
+    f, g = RNG.standard_normal(L), RNG.standard_normal(L)
+    A = brute_force_atoms(g.astype(np.complex128), L, a, M, l1, l2)
+    c_bf = np.einsum("l,lnm->nm", f, np.conj(A))
+    cr = dgtreal(f, g, a, M, l1, l2)
+    S, off, count, e = real_layout(M, l1, l2)
+    assert cr.shape == (N // l2, S)
+    assert rel(unpack_real(cr, N, M, l1, l2), c_bf) < 1e-13
+    assert np.array_equal(pack_real(unpack_real(cr, N, M, l1, l2), M, l1, l2), cr)
+    # adjoint under the real inner product, against the explicit atoms
+    z = rand_c(N // l2, S)
+    lhs = np.real(np.vdot(c_bf, unpack_real(z, N, M, l1, l2)))
+    synth = np.real(np.einsum("lnm,nm->l", A, unpack_real(z, N, M, l1, l2)))
+    assert rel(idgtreal(z, g, a, M, l1, l2), synth) < 1e-13
+    assert abs(lhs - np.dot(f, idgtreal(z, g, a, M, l1, l2))) < 1e-12 * abs(lhs) + 1e-12
+    # reconstruction through the canonical dual window (frame lattices only)
+    if L * L // (a * (L // M)) >= L:
+        gd = oracle.dual_window(g.astype(np.complex128), a, M, l1, l2)
+        if np.all(np.isfinite(gd)):
+            assert rel(idgtreal(cr, gd, a, M, l1, l2), f) < 1e-10
+
+
+def test_real_layout_separable_and_quincunx_shapes():
+    """lam2 <= 2: an (N, floor(M/2) + 1) array; lam2 = 4 (the precision
+    workload's lattice): two half and two whole columns per group of four."""
+    from oracle.real import real_layout
+    assert real_layout(12, 0, 1)[0] == 7
+    assert real_layout(12, 1, 2)[0] == 14
+    assert real_layout(1024, 1, 4)[0] == 2 * 513 + 2 * 1024
+    assert real_layout(9, 1, 3)[0] == 5 + 9 + 9
+    S, off, count, e = real_layout(1024, 1, 4)
+    assert list(count) == [513, 1024, 513, 1024] and e == [0, None, 1, None] and list(off) == [0, 513, 1537, 2050]
