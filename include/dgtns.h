@@ -230,6 +230,26 @@ int dgtns_forward(dgtns_plan plan, const void* f_dev, int real_input, void* c_de
                   void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * dgtns_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, layouts and results, without a workspace argument.  The
+ * workspace lives in a static device array of DGTNS_NOALLOC_SCRATCH_BYTES
+ * bytes, one per device, held from the first call on a device until the
+ * process ends.  The call allocates nothing (no hipMalloc, no stream or event
+ * is created; the opt-in two-stream chunk pipeline is not used).  Returns
+ * DGTNS_EWORKSPACE, before enqueueing anything, if the batch needs more
+ * scratch than that (dgtns_workspace_bytes(DGTNS_OP_FORWARD, B)), and
+ * DGTNS_EINVAL if `stream` belongs to another device than the current one.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (the forward writes every scratch value before reading
+ * it): calls that overlap on one device race, so serialise them (one stream,
+ * or events between streams).
+ */
+#define DGTNS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int dgtns_forward_noalloc(dgtns_plan plan, const void* f_dev, int real_input, void* c_dev, int64_t B,
+                          void* stream);
+
+/*
  * Forward transform of B signals that live in separate buffers (batching of
  * independent requests without staging copies): f_list and c_list are HOST
  * arrays of B device pointers, signal k read from f_list[k] (length L) and

@@ -80,6 +80,7 @@ SIGNATURES = [
     ("dgtns_workspace_bytes", ctypes.c_int, [c_vp, ctypes.c_int, c_i64, ctypes.POINTER(ctypes.c_size_t)]),
     ("dgtns_set_window", ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_forward", ctypes.c_int, [c_vp, c_vp, ctypes.c_int, c_vp, c_i64, c_vp, ctypes.c_size_t, c_vp]),
+    ("dgtns_forward_noalloc", ctypes.c_int, [c_vp, c_vp, ctypes.c_int, c_vp, c_i64, c_vp]),
     ("dgtns_forward_batch", ctypes.c_int, [c_vp, ctypes.POINTER(c_vp), ctypes.c_int, ctypes.POINTER(c_vp), c_i64,
                                            c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_adjoint", ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, ctypes.c_size_t, c_vp]),
@@ -171,6 +172,13 @@ def dgtns_set_window(plan, g_ptr, ws_ptr, ws_bytes, stream):
 
 def dgtns_forward(plan, f_ptr, real_input, c_ptr, B, ws_ptr, ws_bytes, stream):
     _call("dgtns_forward", plan, f_ptr, int(real_input), c_ptr, B, ws_ptr, ws_bytes, stream)
+
+
+DGTNS_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def dgtns_forward_noalloc(plan, f_ptr, real_input, c_ptr, B, stream):
+    _call("dgtns_forward_noalloc", plan, f_ptr, int(real_input), c_ptr, B, stream)
 
 
 DGTNS_MAX_LIST_BATCH = 16

@@ -24,9 +24,11 @@ namespace host {
 
 thread_local std::string g_err;
 thread_local bool g_dry = false;
+thread_local bool g_no_pipeline = false;
 
 void set_last_error(const std::string& msg) { g_err = msg; }
 bool dry_run() { return g_dry; }
+bool no_pipeline() { return g_no_pipeline; }
 
 Timing& timing() {
   static Timing t;
@@ -155,6 +157,34 @@ int dual_body(const Plan& P, const double2* g, double2* out, double* bounds, cha
   if (P.longd)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows need columns held by one in-LDS transform (this plan splits them in two passes)");
   return dual_c128(P, g, out, bounds, w, l, tight, st);
+}
+
+// Scratch of the forward that allocates nothing (dgtns_forward_noalloc): one
+// array per device, held by the loaded code object until the process ends.
+// Host code never uses the name of the array as an address; it takes the
+// device address from hipGetSymbolAddress once per device (scratch_address).
+constexpr size_t kScratchBytes = size_t(DGTNS_NOALLOC_SCRATCH_BYTES);
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+// Device address of this device's scratch array (looked up on the first call
+// on the device, with that device current).
+int scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return DGTNS_OK;
+  }
+  void* ptr = nullptr;
+  int rc = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch address");
+  if (rc) return rc;
+  if (!ptr) return fail(DGTNS_EDEVICE, "scratch address: null");
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return DGTNS_OK;
 }
 
 }  // namespace
@@ -328,6 +358,36 @@ int dgtns_forward(dgtns_plan plan, const void* f_dev, int real_input, void* c_de
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   return run_checked([&] { return forward_body(P, f_dev, real_input, c_dev, B, w, l, st); });
+}
+
+int dgtns_forward_noalloc(dgtns_plan plan, const void* f_dev, int real_input, void* c_dev, int64_t B,
+                          void* stream) {
+  if (!plan) return fail(DGTNS_EINVAL, "null plan");
+  const Plan& P = plan->p;
+  if (B < 1 || B > P.max_batch) return fail(DGTNS_EINVAL, "batch must be in [1, max_batch]");
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "current device");
+  if (rc) return rc;
+  if (stream) {
+    hipDevice_t sdev = 0;
+    rc = check_hip(hipStreamGetDevice(static_cast<hipStream_t>(stream), &sdev), "stream device");
+    if (rc) return rc;
+    if (int(sdev) != dev) return fail(DGTNS_EINVAL, "the stream belongs to another device than the current one");
+  }
+  g_no_pipeline = true;
+  const size_t need = ws_layout(P, DGTNS_OP_FORWARD, B).total;
+  g_no_pipeline = false;
+  if (need > kScratchBytes)
+    return fail(DGTNS_EWORKSPACE, "the forward of this batch needs " + std::to_string(need) +
+                                      " bytes of scratch; the static scratch holds " +
+                                      std::to_string(kScratchBytes) + " bytes (use a smaller batch)");
+  void* ptr = nullptr;
+  rc = scratch_address(dev, &ptr);
+  if (rc) return rc;
+  g_no_pipeline = true;
+  rc = dgtns_forward(plan, f_dev, real_input, c_dev, B, ptr, kScratchBytes, stream);
+  g_no_pipeline = false;
+  return rc;
 }
 
 int dgtns_forward_batch(dgtns_plan plan, const void* const* f_list, int real_input, void* const* c_list, int64_t B,

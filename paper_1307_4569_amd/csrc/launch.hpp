@@ -54,8 +54,12 @@ hipStream_t helper_stream();          // per device, created once (default prior
 hipEvent_t take_sync_event();
 void give_sync_event(hipEvent_t e);
 
+// True while a call that must not create streams or events runs (per
+// thread): the two-stream pipeline is then not used.
+bool no_pipeline();
+
 inline bool pipelined(const Plan& P, long long B, int op) {
-  return op == DGTNS_OP_FORWARD && P.chunk > 0 && B >= 2 * P.chunk;
+  return op == DGTNS_OP_FORWARD && P.chunk > 0 && B >= 2 * P.chunk && !no_pipeline();
 }
 
 template <typename S1, typename S2>
