@@ -62,6 +62,16 @@ inline bool pipelined(const Plan& P, long long B, int op) {
   return op == DGTNS_OP_FORWARD && P.chunk > 0 && B >= 2 * P.chunk && !no_pipeline();
 }
 
+// Sequential chunks of the forward and the adjoint: one h buffer of P.seq
+// signals, reused, when the whole batch's h is at least 256 MiB.
+inline bool seq_chunked(const Plan& P, long long B, int op) {
+  if (op != DGTNS_OP_FORWARD && op != DGTNS_OP_ADJOINT) return false;
+  if (P.seq < 1 || B <= P.seq || P.branch == kFreqShear || P.longd || P.branch == kFir || P.branch == kShearOla)
+    return false;
+  const double h_bytes = double(P.qi) * double(P.Mi) * double(P.di) * double(B) * (P.dtype == 0 ? 8.0 : 16.0);
+  return h_bytes >= double(256ll << 20);
+}
+
 template <typename S1, typename S2>
 int run_pipeline(long long B, long long chunk, hipStream_t st, S1 stage1, S2 stage2) {
   const long long nch = (B + chunk - 1) / chunk;
@@ -250,6 +260,8 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
       if (pipelined(P, B, op)) {
         l.H = take(es * MN * P.chunk);
         l.F = take(es * MN * P.chunk);   // second h buffer
+      } else if (seq_chunked(P, B, op)) {
+        l.H = take(es * MN * P.seq);
       } else {
         l.H = take(es * MN * B);
         if (fs) { l.F = take(es * L * B); l.Y = take(es * L * B); }
@@ -296,12 +308,14 @@ template <typename C> bool h_time_major(const Plan& P) {
   return cols && rows;
 }
 
+// min_wg: work-groups the launch aims for when the batch is small, by
+// splitting the q offsets of a column block over several work-groups (each
+// repeats the block's column DFTs).
 template <typename C, int D>
-int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t st) {
+int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t st, long long min_wg) {
   using F = FastCols<C, D>;
   const long long nblk = cdiv(P.Mi, F::W);
-  // at least about 2048 work-groups (8 per compute unit) when the batch is small
-  long long ns = (2048 + nblk * B - 1) / (nblk * B);
+  long long ns = (min_wg + nblk * B - 1) / (nblk * B);
   if (ns > P.qi) ns = P.qi;
   if (ns < 1) ns = 1;
   ColArgs<C> A2 = A;
@@ -456,9 +470,14 @@ int run_adj_cols_long(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long
                 "adjoint factorisation, last column pass");
 }
 
+// min_wg: see run_cols_fast.  About 2048 (8 per compute unit) for a small
+// batch on its own; 512 (two per compute unit, one full wave of the grid) for
+// the chunks of a sequential batch, where repeating column DFTs costs more
+// than the idle compute units of a split-free launch.
 template <typename C>
 int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C> ch, C* H, long long B,
-             hipStream_t st, const void* const* xlist = nullptr, C* U = nullptr, C* V = nullptr) {
+             hipStream_t st, const void* const* xlist = nullptr, C* U = nullptr, C* V = nullptr,
+             long long min_wg = 2048) {
   if (P.longd) return run_cols_long<C>(P, x, xs, real_in, ch, H, B, st, xlist, U, V);
   ColArgs<C> A;
   std::memset(&A, 0, sizeof(A));
@@ -480,12 +499,12 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
   // wave kernels up to d = 1024 (FP32) or 512 (FP64; d = 1024 would spill registers)
   if (P.pi == 1 && !P.generic && P.di * long(sizeof(C)) <= 8192) {
     switch (P.di) {
-      case 32: return run_cols_fast<C, 32>(P, A, B, st);
-      case 64: return run_cols_fast<C, 64>(P, A, B, st);
-      case 128: return run_cols_fast<C, 128>(P, A, B, st);
-      case 256: return run_cols_fast<C, 256>(P, A, B, st);
-      case 512: return run_cols_fast<C, 512>(P, A, B, st);
-      case 1024: return run_cols_fast<C, 1024>(P, A, B, st);
+      case 32: return run_cols_fast<C, 32>(P, A, B, st, min_wg);
+      case 64: return run_cols_fast<C, 64>(P, A, B, st, min_wg);
+      case 128: return run_cols_fast<C, 128>(P, A, B, st, min_wg);
+      case 256: return run_cols_fast<C, 256>(P, A, B, st, min_wg);
+      case 512: return run_cols_fast<C, 512>(P, A, B, st, min_wg);
+      case 1024: return run_cols_fast<C, 1024>(P, A, B, st, min_wg);
       default: break;
     }
   }
@@ -571,14 +590,18 @@ RowArgs<C> row_args(const Plan& P, const C* H, C* c) {
   return A;
 }
 
+// Bc: the batch whose coefficients the call writes in all (a sequential
+// chunk of a larger batch streams its stores when the whole output would not
+// stay in the last-level cache); 0: B.
 template <typename C>
 int run_rows(const Plan& P, const C* H, C* c, long long B, bool adjoint, hipStream_t st,
-             void* const* clist = nullptr) {
+             void* const* clist = nullptr, long long Bc = 0) {
   RowArgs<C> A = row_args<C>(P, H, c);
   // the adjoint writes h, the forward the coefficients
   // the forward of the frequency-shear branch scatters single coefficients
   // (Alg. 1's output permutation): plain stores let the cache merge them
-  A.hstream = adjoint ? stream_h(P, B, sizeof(C)) : (P.branch == kFreqShear ? 0 : stream_c(P, B, sizeof(C)));
+  A.hstream = adjoint ? stream_h(P, B, sizeof(C))
+                      : (P.branch == kFreqShear ? 0 : stream_c(P, Bc > 0 ? Bc : B, sizeof(C)));
   A.ht = !adjoint && h_time_major<C>(P);
   if (clist) {
     A.list = 1;
@@ -800,6 +823,22 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
           return run_rows<C>(P, Hb[buf], c + b0 * MN, nb, false, s);
         });
   }
+  if (seq_chunked(P, B, DGTNS_OP_FORWARD)) {
+    const size_t sig_bytes = size_t(P.L) * (real_in ? sizeof(C) / 2 : sizeof(C));
+    const long long MN = P.M * P.N;
+    for (long long b0 = 0; b0 < B; b0 += P.seq) {
+      const long long nb = B - b0 < P.seq ? B - b0 : P.seq;
+      if (flist)
+        rc = run_cols<C>(P, nullptr, P.L, real_in, chirp_tab<C>(P, P.off.chirp1, 0), H, nb, st, flist + b0,
+                         nullptr, nullptr, 512);
+      else
+        rc = run_cols<C>(P, static_cast<const char*>(f) + b0 * sig_bytes, P.L, real_in,
+                         chirp_tab<C>(P, P.off.chirp1, 0), H, nb, st, nullptr, nullptr, nullptr, 512);
+      if (!rc) rc = run_rows<C>(P, H, clist ? nullptr : c + b0 * MN, nb, false, st, clist ? clist + b0 : nullptr, B);
+      if (rc) return rc;
+    }
+    return DGTNS_OK;
+  }
   if (P.branch != kFreqShear) {
     rc = run_cols<C>(P, f, P.L, real_in, chirp_tab<C>(P, P.off.chirp1, 0), H, B, st, flist,
                      reinterpret_cast<C*>(ws + l.U), reinterpret_cast<C*>(ws + l.V));
@@ -865,6 +904,16 @@ int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const L
         [&](long long b0, long long nb, int buf, hipStream_t s) {
           return run_adj_cols<C>(P, Hb[buf], chirp_tab<C>(P, P.off.chirp1, 1), f + b0 * P.L, nb, s);
         });
+  }
+  if (seq_chunked(P, B, DGTNS_OP_ADJOINT)) {
+    const long long MN = P.M * P.N;
+    for (long long b0 = 0; b0 < B; b0 += P.seq) {
+      const long long nb = B - b0 < P.seq ? B - b0 : P.seq;
+      int rc = run_rows<C>(P, H, const_cast<C*>(c) + b0 * MN, nb, true, st);
+      if (!rc) rc = run_adj_cols<C>(P, H, chirp_tab<C>(P, P.off.chirp1, 1), f + b0 * P.L, nb, st);
+      if (rc) return rc;
+    }
+    return DGTNS_OK;
   }
   int rc = run_rows<C>(P, H, const_cast<C*>(c), B, true, st);
   if (rc) return rc;

@@ -395,6 +395,12 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
       p.chunk = (int64_t(std::atoi(cm)) << 20) / per_sig;
       if (p.chunk < 1) p.chunk = 1;
     }
+    // Sequential chunks of about 128 MiB of h (DGTNS_SEQ_MIB overrides; 0
+    // turns them off): used by calls whose whole h would not stay in the
+    // 256 MB last-level cache, while one chunk of h does.
+    const char* sm = std::getenv("DGTNS_SEQ_MIB");
+    const int64_t seq_mib = sm ? std::atoi(sm) : 128;
+    if (seq_mib > 0 && !p.chunk) p.seq = (seq_mib << 20) / per_sig;
   }
 
   // LDS element budget per work-group: 8192 complex elements (FP32) or 4096 (FP64)
@@ -447,6 +453,7 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
     const int64_t wl = budget / (p.d1 | 1);
     p.Wl = int(wl > 16 ? 16 : (wl < 1 ? 1 : wl));
     p.chunk = 0;
+    p.seq = 0;
   }
   if (p.Mi > budget) {
     *err = "channel count exceeds the in-LDS limit";

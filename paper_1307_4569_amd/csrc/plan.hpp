@@ -117,6 +117,13 @@ struct Plan {
   // branch (DGTNS_CHUNK_MIB): the workspace then holds two chunks of h
   // instead of the whole batch.  0: one launch per stage.
   int64_t chunk = 0;
+  // Signals per chunk of the sequential forward and adjoint (time-shear and
+  // separable branches, columns in one in-LDS transform): both stages of a
+  // chunk run back to back on the caller's stream through one h buffer of
+  // that many signals, small enough to stay in the last-level cache between
+  // the two kernels.  Used when the whole batch's h would not stay there.
+  // 0: one launch per stage.
+  int64_t seq = 0;
 };
 
 // Returns 0 on success, else an error status with a message in *err.

@@ -163,3 +163,36 @@ def test_crossover_row(lat, algorithm):
     print("crossover", lat, algorithm, "branch", plan.info.branch, "p", plan.info.p, "d", plan.info.d,
           "forward", errs, "adjoint", e_adj, "adjointness", e_dot)
     assert max(errs) < 1e-5 and e_adj < 1e-5 and e_dot < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Sequential chunks against one launch per stage
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_sequential_chunks_equal_single_launch(dtype, monkeypatch):
+    """The quincunx workload's forward and adjoint in sequential chunks (the
+    default for batches whose h exceeds the last-level cache) give the
+    coefficients and signals of one launch per stage bit for bit, with a
+    ragged last chunk (61 signals)."""
+    from paper_1307_4569_amd import Plan
+    w = LARGE
+    g = torch.tensor(round_to(gaussian_window(w.L, w.a, w.M), dtype == torch.complex64))
+    plans = {}
+    for env in ("128", "0"):
+        monkeypatch.setenv("DGTNS_SEQ_MIB", env)
+        plans[env] = Plan(w.L, w.a, w.M, w.lam1, w.lam2, dtype=dtype, max_batch=w.batch)
+        plans[env].set_window(g)
+    nb = 61
+    f = torch.stack([torch.tensor(round_to(complex_normal(w.L, seed_for(2, 700 + k)), True)) for k in range(4)])
+    f = f.to(dtype).cuda().repeat(16, 1)[:nb]
+    c1, c0 = plans["128"].forward(f), plans["0"].forward(f)
+    f1, f0 = plans["128"].adjoint(c0), plans["0"].adjoint(c0)
+    torch.cuda.synchronize()
+    assert torch.equal(c1, c0)
+    assert torch.equal(f1, f0)
+    # and one chunk's signal against the oracle's eq. (DGT) on sampled columns
+    cols = [0, 1, w.N // 3, w.N - 1]
+    ref = oracle.dgt_fold(f[60].cpu().to(torch.complex128).numpy(), g.numpy(), w.a, w.M, w.lam1, w.lam2,
+                          columns=cols)
+    assert rel(c1[60, cols].cpu().numpy(), ref) < TOL[dtype]

@@ -335,6 +335,7 @@ def test_pipelined_batches_match_single_launch(dtype, monkeypatch):
     for mode in ("pipeline", "single"):
         if mode == "single":
             monkeypatch.delenv("DGTNS_CHUNK_MIB", raising=False)
+            monkeypatch.setenv("DGTNS_SEQ_MIB", "0")    # one launch per stage
         else:
             monkeypatch.setenv("DGTNS_CHUNK_MIB", "64")
         plan = make_plan(w.L, w.a, w.M, w.lam1, w.lam2, dtype, B)

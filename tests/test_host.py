@@ -403,3 +403,34 @@ def test_check_op_sweep(lib):
                 finally:
                     B.dgtns_plan_destroy(h)
     assert seen[B.DGTNS_OK] > 1000 and seen[B.DGTNS_EUNSUPPORTED] > 100
+
+
+def test_sequential_chunk_workspace(lib, monkeypatch):
+    """A forward or adjoint whose whole h would not stay in the 256 MB
+    last-level cache runs in sequential chunks of about 128 MiB of h through
+    one buffer: the workspace then holds one chunk (8 signals of the quincunx
+    workload, 16 MiB of h each), not the batch.  DGTNS_SEQ_MIB=0 at plan
+    creation turns the chunks off."""
+    from dgt_inputs import LARGE as w
+    per_sig = 8 * w.N * w.M
+    for env, chunk_ws in ((None, True), ("0", False)):
+        if env is None:
+            monkeypatch.delenv("DGTNS_SEQ_MIB", raising=False)
+        else:
+            monkeypatch.setenv("DGTNS_SEQ_MIB", env)
+        h = B.dgtns_plan_create(w.L, w.a, w.M, w.lam1, w.lam2, 0, 64)
+        try:
+            for op in (B.DGTNS_OP_FORWARD, B.DGTNS_OP_ADJOINT):
+                ws64 = B.dgtns_workspace_bytes(h, op, 64)
+                # 16 signals: 256 MiB of h, chunked; 8 signals: 128 MiB, one launch
+                ws16 = B.dgtns_workspace_bytes(h, op, 16)
+                ws8 = B.dgtns_workspace_bytes(h, op, 8)
+                assert ws8 >= 8 * per_sig
+                if chunk_ws:
+                    assert 8 * per_sig <= ws64 < 9 * per_sig and ws16 == ws64, (op, ws64)
+                else:
+                    assert ws64 >= 64 * per_sig and ws16 >= 16 * per_sig
+            # the window gradient never chunks
+            assert B.dgtns_workspace_bytes(h, B.DGTNS_OP_WINDOW_GRAD, 64) >= 64 * per_sig
+        finally:
+            B.dgtns_plan_destroy(h)
