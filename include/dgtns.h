@@ -111,6 +111,9 @@ typedef struct {
   /* shear-OLA plans: block length L_b and the length L_x of the DGT each
      zero-extended block runs (0 for other plans) */
   int64_t block, block_dgt_length;
+  /* real-signal layout (dgtns_forward_real): values per group of lambda2
+     time positions; a signal's coefficients are (N / lambda2) real_row values */
+  int64_t real_row;
 } dgtns_plan_info_t;
 
 /* Human-readable name of a status code (static storage). */
@@ -228,6 +231,40 @@ int dgtns_set_window(dgtns_plan plan, const void* g_dev, void* ws, size_t ws_byt
  */
 int dgtns_forward(dgtns_plan plan, const void* f_dev, int real_input, void* c_dev, int64_t B,
                   void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Real-signal variant (Section 4.4 names a real-signal entry point beside the
+ * complex one without specifying it; this is the reading).  For a real
+ * signal and a real window, conjugating eq. (DGT) gives the coefficient of
+ * the negated frequency at the same time position; it lies on column n
+ * exactly when e(n) = 2 w(n) is an integer (w(n) in {0, 1/2}), so then
+ *     c((-m - e(n)) mod M, n) = conj(c(m, n))
+ * and channels 0 .. floor(M/2) determine the column.  The other columns are
+ * not redundant.  w(n) depends on n mod lambda2: the half columns are
+ * n = 0 and, for even lambda2, n = lambda2/2 (mod lambda2).
+ *
+ * Layout of a signal's coefficients (real_row = S from dgtns_plan_info):
+ * (N / lambda2) rows of S values; column n = j lambda2 + k starts at
+ * j S + off(k) and holds cnt(k) channels 0 .. cnt(k)-1, with
+ * cnt(k) = floor(M/2) + 1 for the half columns and M for the others, and
+ * off(k) = sum of cnt(k') over k' < k.  For lambda2 <= 2 this is an
+ * N x (floor(M/2) + 1) array.  c_dev is [B][N/lambda2][S] (plan dtype,
+ * complex); f_dev holds B real signals of length L (float or double by the
+ * plan dtype).
+ *
+ * dgtns_forward_real writes those channels of eq. (DGT) of the real signals
+ * (any window; the omitted channels are the conjugates of stored ones only
+ * when the window is real).  Workspace: DGTNS_OP_FORWARD.  Every algorithm.
+ * dgtns_adjoint_real expands c_dev to the full array (an omitted channel m
+ * of a half column is conj(c((-m - e(n)) mod M, n))) and writes the real
+ * part of its synthesis (the adjoint of eq. (DGT)) to f_dev; with the
+ * canonical dual window it inverts dgtns_forward_real.  Workspace:
+ * DGTNS_OP_ADJOINT.  Every algorithm with an adjoint (not shear-OLA).
+ */
+int dgtns_forward_real(dgtns_plan plan, const void* f_dev, void* c_dev, int64_t B, void* ws, size_t ws_bytes,
+                       void* stream);
+int dgtns_adjoint_real(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, void* ws, size_t ws_bytes,
+                       void* stream);
 
 /*
  * dgtns_forward for callers that cannot allocate device memory (code under

@@ -49,7 +49,7 @@ class dgtns_plan_info_t(ctypes.Structure):
         ("branch", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("inner_a", c_i64), ("inner_M", c_i64), ("c", c_i64), ("d", c_i64), ("p", c_i64), ("q", c_i64),
         ("max_batch", c_i64), ("persistent_bytes", ctypes.c_size_t), ("windows", c_i64),
-        ("block", c_i64), ("block_dgt_length", c_i64),
+        ("block", c_i64), ("block_dgt_length", c_i64), ("real_row", c_i64),
     ]
 
 
@@ -80,6 +80,8 @@ SIGNATURES = [
     ("dgtns_workspace_bytes", ctypes.c_int, [c_vp, ctypes.c_int, c_i64, ctypes.POINTER(ctypes.c_size_t)]),
     ("dgtns_set_window", ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_forward", ctypes.c_int, [c_vp, c_vp, ctypes.c_int, c_vp, c_i64, c_vp, ctypes.c_size_t, c_vp]),
+    ("dgtns_forward_real", ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, ctypes.c_size_t, c_vp]),
+    ("dgtns_adjoint_real", ctypes.c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_forward_noalloc", ctypes.c_int, [c_vp, c_vp, ctypes.c_int, c_vp, c_i64, c_vp]),
     ("dgtns_forward_batch", ctypes.c_int, [c_vp, ctypes.POINTER(c_vp), ctypes.c_int, ctypes.POINTER(c_vp), c_i64,
                                            c_vp, ctypes.c_size_t, c_vp]),
@@ -172,6 +174,14 @@ def dgtns_set_window(plan, g_ptr, ws_ptr, ws_bytes, stream):
 
 def dgtns_forward(plan, f_ptr, real_input, c_ptr, B, ws_ptr, ws_bytes, stream):
     _call("dgtns_forward", plan, f_ptr, int(real_input), c_ptr, B, ws_ptr, ws_bytes, stream)
+
+
+def dgtns_forward_real(plan, f_ptr, c_ptr, B, ws_ptr, ws_bytes, stream):
+    _call("dgtns_forward_real", plan, f_ptr, c_ptr, B, ws_ptr, ws_bytes, stream)
+
+
+def dgtns_adjoint_real(plan, c_ptr, f_ptr, B, ws_ptr, ws_bytes, stream):
+    _call("dgtns_adjoint_real", plan, c_ptr, f_ptr, B, ws_ptr, ws_bytes, stream)
 
 
 DGTNS_NOALLOC_SCRATCH_BYTES = 64 << 20

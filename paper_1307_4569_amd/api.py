@@ -161,6 +161,47 @@ class Plan:
         B.dgtns_adjoint(self._h, c.data_ptr(), out.data_ptr(), nb, ws, wsb, st)
         return out[0] if squeeze else out
 
+    @property
+    def real_shape(self) -> Tuple[int, int]:
+        """Per-signal shape (N / lambda2, real_row) of real-signal coefficients."""
+        return (self.N // self.info.lambda2, self.info.real_row)
+
+    def forward_real(self, f: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Real-signal variant: the non-redundant channels of eq. (DGT) of real
+        signals f (B, L), as (B, N / lambda2, real_row) (see dgtns_forward_real)."""
+        squeeze = f.dim() == 1
+        if f.is_complex():
+            raise ValueError("forward_real takes real signals")
+        if f.dim() == 1:
+            f = f.unsqueeze(0)
+        if f.dim() != 2 or f.shape[1] != self.L:
+            raise ValueError(f"signals must have shape (B, {self.L})")
+        f = f.to(device=self.device, dtype=_REAL[self.dtype]).contiguous()
+        nb = f.shape[0]
+        if out is None:
+            out = torch.empty((nb,) + self.real_shape, dtype=self.dtype, device=self.device)
+        st = _stream_handle(self.device)
+        ws, wsb = self.workspace(B.DGTNS_OP_FORWARD, nb, st)
+        B.dgtns_forward_real(self._h, f.data_ptr(), out.data_ptr(), nb, ws, wsb, st)
+        return out[0] if squeeze else out
+
+    def adjoint_real(self, c: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Real part of the synthesis of real-signal coefficients c
+        (B, N / lambda2, real_row), expanded by conjugate symmetry: real (B, L)."""
+        squeeze = c.dim() == 2
+        if squeeze:
+            c = c.unsqueeze(0)
+        if tuple(c.shape[1:]) != self.real_shape:
+            raise ValueError(f"coefficients must have shape (B, {self.real_shape[0]}, {self.real_shape[1]})")
+        c = c.to(device=self.device, dtype=self.dtype).contiguous()
+        nb = c.shape[0]
+        if out is None:
+            out = torch.empty((nb, self.L), dtype=_REAL[self.dtype], device=self.device)
+        st = _stream_handle(self.device)
+        ws, wsb = self.workspace(B.DGTNS_OP_ADJOINT, nb, st)
+        B.dgtns_adjoint_real(self._h, c.data_ptr(), out.data_ptr(), nb, ws, wsb, st)
+        return out[0] if squeeze else out
+
     def window_grad(self, f: torch.Tensor, gc: torch.Tensor) -> torch.Tensor:
         """Gradient of a real loss with respect to the window, summed over the
         batch, given the coefficient gradient gc (B, N, M)."""

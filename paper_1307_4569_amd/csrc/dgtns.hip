@@ -25,10 +25,13 @@ namespace host {
 thread_local std::string g_err;
 thread_local bool g_dry = false;
 thread_local bool g_no_pipeline = false;
+thread_local bool g_real = false;
 
 void set_last_error(const std::string& msg) { g_err = msg; }
 bool dry_run() { return g_dry; }
 bool no_pipeline() { return g_no_pipeline; }
+bool real_call() { return g_real; }
+void set_real_call(bool on) { g_real = on; }
 
 Timing& timing() {
   static Timing t;
@@ -259,6 +262,7 @@ int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info) {
   info->persistent_bytes = P.off.total;
   info->block = P.ola_Lb;
   info->block_dgt_length = P.ola_Lx;
+  info->real_row = real_row(P);
   return DGTNS_OK;
 }
 
@@ -358,6 +362,39 @@ int dgtns_forward(dgtns_plan plan, const void* f_dev, int real_input, void* c_de
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   return run_checked([&] { return forward_body(P, f_dev, real_input, c_dev, B, w, l, st); });
+}
+
+// The real-signal variant: the same bodies with the real-signal layout and
+// real samples for the whole call (dry run included).
+struct RealCallScope {
+  RealCallScope() { set_real_call(true); }
+  ~RealCallScope() { set_real_call(false); }
+};
+
+int dgtns_forward_real(dgtns_plan plan, const void* f_dev, void* c_dev, int64_t B, void* ws, size_t ws_bytes,
+                       void* stream) {
+  Layout l;
+  int rc = check_call(plan, B, ws, ws_bytes, DGTNS_OP_FORWARD, &l);
+  if (rc) return rc;
+  if (!f_dev || !c_dev) return fail(DGTNS_EINVAL, "null signal or coefficient pointer");
+  const Plan& P = plan->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  RealCallScope real;
+  return run_checked([&] { return forward_body(P, f_dev, 1, c_dev, B, w, l, st); });
+}
+
+int dgtns_adjoint_real(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, void* ws, size_t ws_bytes,
+                       void* stream) {
+  Layout l;
+  int rc = check_call(plan, B, ws, ws_bytes, DGTNS_OP_ADJOINT, &l);
+  if (rc) return rc;
+  if (!f_dev || !c_dev) return fail(DGTNS_EINVAL, "null signal or coefficient pointer");
+  const Plan& P = plan->p;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  RealCallScope real;
+  return run_checked([&] { return adjoint_body(P, c_dev, f_dev, B, w, l, st); });
 }
 
 int dgtns_forward_noalloc(dgtns_plan plan, const void* f_dev, int real_input, void* c_dev, int64_t B,

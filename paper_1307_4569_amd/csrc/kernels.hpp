@@ -78,6 +78,54 @@ template <typename C> __device__ __forceinline__ void st_h(C* p, C v, int hstrea
   else
     *p = v;
 }
+// Signal output of the synthesis: complex, or the real part only (the
+// real-signal variant's synthesis writes real samples).
+template <typename C> __device__ __forceinline__ void st_out(C* y, long long idx, C v, int real_out) {
+  using T = decltype(C::x);
+  if (real_out)
+    reinterpret_cast<T*>(y)[idx] = v.x;
+  else
+    y[idx] = v;
+}
+
+// Coefficient layout of a call.  Full: column n of a signal at n M, all M
+// channels.  Real-signal variant (Section 4.4's real-signal entry point, for
+// a real signal and window): a column whose offset w(n) is 0 or 1/2 is
+// conjugate symmetric, c((-m - 2 w(n)) mod M, n) = conj(c(m, n)), and keeps
+// channels 0 .. M/2 only; the other columns are kept whole.  w(n) depends on
+// n mod lambda2, and the half columns are n = 0 and, for even lambda2,
+// n = lambda2/2 (mod lambda2); the columns are grouped by n div lambda2 into
+// rows of S values.
+struct CoefLayout {
+  int real;        // 1: real-signal layout
+  int lam2, M, M2; // M2 = M/2 + 1
+  long long S;     // values per group of lambda2 columns
+};
+// Offset of column n within a signal's coefficients; *cnt: its stored
+// channels; *e: 2 w(n) of a half-stored column.
+__device__ __forceinline__ long long coef_col(const CoefLayout& R, long long n, int* cnt, int* e) {
+  if (!R.real) {
+    *cnt = R.M;
+    *e = 0;
+    return n * R.M;
+  }
+  const long long j = n / R.lam2;
+  const int k = int(n - j * R.lam2), h = R.lam2 >> 1;
+  const bool even = (R.lam2 & 1) == 0;
+  const bool half1 = even && k == h;
+  *cnt = (k == 0 || half1) ? R.M2 : R.M;
+  *e = half1 ? 1 : 0;
+  const int before = (k > 0 ? 1 : 0) + (even && k > h ? 1 : 0);
+  return j * R.S + (long long)k * R.M - (long long)(R.M - R.M2) * before;
+}
+// Channel m of a column at col (coef_col): stored, or the conjugate of the
+// stored channel (-m - e) mod M.
+template <typename C>
+__device__ __forceinline__ C coef_load(const C* cb, int M, long long col, int cnt, int e, int m) {
+  if (m < cnt) return cb[col + m];
+  return cconj(cb[col + (M - m - e)]);
+}
+
 template <typename C> __device__ __forceinline__ C ld_stream(const C* p) {
   using T = decltype(C::x);
   const typename NVec<T>::type w = __builtin_nontemporal_load(reinterpret_cast<const typename NVec<T>::type*>(p));
@@ -266,6 +314,7 @@ template <typename C> struct ColAdjArgs {
   int qw;                      // time offsets per window (q = nw qw), tables zs apart
   long long zs;
   FftSched fd;
+  int real_out;                // write the real part of y only (real samples)
 };
 
 // Factorisation for p = 1 and any 7-smooth d <= 64 MV, one column per
@@ -420,7 +469,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
     if (r < Mi) {
       const long long l = r + (long long)j * Mi;
       const int j0 = GENP ? j % p : 0, t = GENP ? j / p : j;
-      A.y[bo * A.ys + l] = apply_chirp(A.chirp, xb[(cc * p + j0) * Sd + t], l);
+      st_out(A.y, bo * A.ys + l, apply_chirp(A.chirp, xb[(cc * p + j0) * Sd + t], l), A.real_out);
     }
   }
 }
@@ -456,10 +505,15 @@ template <typename C> struct RowArgs {
   int ht;                      // h[n0][t][r] layout (fast forward kernels only)
   FftSched fm;
   long long N, L, b, M, K1, K2, K3, K4, K5, C1n, C2n, Kt1, Kt6;
+  CoefLayout lay;              // coefficient layout (c, cs and cl follow it)
 };
 
+// Frequency-shear post-processing of Alg. 1 for intermediate position m and
+// channel k: the phase *E and the coefficient's time position *nt and
+// channel *kt.
 template <typename C>
-__device__ __forceinline__ void shear_map(const RowArgs<C>& A, long long m, long long k, long long* dst, C* E) {
+__device__ __forceinline__ void shear_map(const RowArgs<C>& A, long long m, long long k, long long* nt,
+                                          long long* kt, C* E) {
   using T = decltype(C::x);
   const long long twoN = 2 * A.N;
   const long long sq = (A.K1 * k + A.K2 * m) % twoN;
@@ -469,9 +523,8 @@ __device__ __forceinline__ void shear_map(const RowArgs<C>& A, long long m, long
   e = (e - (m * inner) % twoN) % twoN;
   if (e < 0) e += twoN;
   *E = phase_pi(e, A.N, T());
-  const long long mt = (A.C1n * k + A.C2n * m) % A.N;
-  const long long kt = ((A.Kt1 * k + A.Kt6 * m) % A.L) / A.b;
-  *dst = mt * A.M + kt;
+  *nt = (A.C1n * k + A.C2n * m) % A.N;
+  *kt = ((A.Kt1 * k + A.Kt6 * m) % A.L) / A.b;
 }
 
 template <typename C, int MODE>
@@ -496,15 +549,20 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows(RowArgs<C> A) {
     if (t0 + row >= d) continue;
     const int n = row_time(n0, t0 + row, A.qw, A.nw);
     if (MODE == 0) {
+      int cnt, ee;
+      const long long col = coef_col(A.lay, n, &cnt, &ee);
+      if (mo >= cnt) continue;
       int mi = mo - A.rho[n];
       if (mi < 0) mi += Mi;
-      st_h(cb + (long long)n * Mi + mo, cmul(A.postE[n], buf[row * Sm + mi]), A.hstream);
+      st_h(cb + col + mo, cmul(A.postE[n], buf[row * Sm + mi]), A.hstream);
     } else {
       const long long k = mo == 0 ? 0 : Mi - mo;
-      long long dst;
+      long long nt, kt;
       C E;
-      shear_map(A, n, k, &dst, &E);
-      st_h(cb + dst, cmul(E, buf[row * Sm + mo]), A.hstream);
+      shear_map(A, n, k, &nt, &kt, &E);
+      int cnt, ee;
+      const long long col = coef_col(A.lay, nt, &cnt, &ee);
+      if (kt < cnt) st_h(cb + col + kt, cmul(E, buf[row * Sm + mo]), A.hstream);
     }
   }
 }
@@ -527,13 +585,17 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows(RowArgs<C> A) {
       if (MODE == 0) {
         int mo = m + A.rho[n];
         if (mo >= Mi) mo -= Mi;
-        v = cmulc(cb[(long long)n * Mi + mo], A.postE[n]);
+        int cnt, ee;
+        const long long col = coef_col(A.lay, n, &cnt, &ee);
+        v = cmulc(coef_load(cb, Mi, col, cnt, ee, mo), A.postE[n]);
       } else {
         const long long k = m == 0 ? 0 : Mi - m;
-        long long src;
+        long long nt, kt;
         C E;
-        shear_map(A, n, k, &src, &E);
-        v = cmulc(cb[src], E);
+        shear_map(A, n, k, &nt, &kt, &E);
+        int cnt, ee;
+        const long long col = coef_col(A.lay, nt, &cnt, &ee);
+        v = cmulc(coef_load(cb, int(A.M), col, cnt, ee, int(kt)), E);
       }
     }
     buf[row * Sm + m] = v;
@@ -612,6 +674,7 @@ template <typename C> struct RowFftArgs {
   const C* tws;
   int n, nrows, R, Sn;
   FftSched fs;
+  int real_out;   // write the real part of y only (real samples)
 };
 
 template <typename C, bool INV>
@@ -633,7 +696,7 @@ __global__ void __launch_bounds__(kThreads) k_row_fft(RowFftArgs<C> A) {
     const int k = e / R, rr = e - k * R, row = row0 + rr;
     if (row < nr) {
       const long long idx = (long long)k * nr + row;
-      A.y[bo * A.ys + idx] = cscale(apply_chirp(A.post, buf[rr * Sn + k], idx), A.scale);
+      st_out(A.y, bo * A.ys + idx, cscale(apply_chirp(A.post, buf[rr * Sn + k], idx), A.scale), A.real_out);
     }
   }
 }

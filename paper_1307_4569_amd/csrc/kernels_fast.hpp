@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(kThreads, sizeof(C) == 8 ? 4 : 1) k_adj_cols_w
     const int t = e / W, cc = e - t * W, r = r0 + cc;
     if (r < Mi) {
       const long long li = r + (long long)t * Mi;
-      A.y[bo * A.ys + li] = apply_chirp(A.chirp, lds[cc * SD + t], li);
+      st_out(A.y, bo * A.ys + li, apply_chirp(A.chirp, lds[cc * SD + t], li), A.real_out);
     }
   }
 }
@@ -435,28 +435,35 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
     } else if (MODE == 0) {
       const C En = A.postE[n];
       const int rho = A.rho[n];
-      C* row = cb + (long long)n * MI;
+      int cnt, ee;
+      C* row = cb + coef_col(A.lay, n, &cnt, &ee);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         int mo = l + T * e + rho;
         if (mo >= MI) mo -= MI;
-        if constexpr (HS)
-          st_stream(row + mo, cmul(En, v[k][e]));
-        else
-          row[mo] = cmul(En, v[k][e]);
+        if (mo < cnt) {
+          if constexpr (HS)
+            st_stream(row + mo, cmul(En, v[k][e]));
+          else
+            row[mo] = cmul(En, v[k][e]);
+        }
       }
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int kp = l + T * e;
         const long long kk = kp == 0 ? 0 : MI - kp;
-        long long dst;
+        long long nt, kt;
         C Ev;
-        shear_map(A, n, kk, &dst, &Ev);
-        if constexpr (HS)
-          st_stream(cb + dst, cmul(Ev, v[k][e]));
-        else
-          cb[dst] = cmul(Ev, v[k][e]);
+        shear_map(A, n, kk, &nt, &kt, &Ev);
+        int cnt, ee;
+        const long long col = coef_col(A.lay, nt, &cnt, &ee);
+        if (kt < cnt) {
+          if constexpr (HS)
+            st_stream(cb + col + kt, cmul(Ev, v[k][e]));
+          else
+            cb[col + kt] = cmul(Ev, v[k][e]);
+        }
       }
     }
   }
@@ -486,22 +493,25 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
     if (MODE == 0) {
       const C En = A.postE[n];
       const int rho = A.rho[n];
-      const C* row = cb + (long long)n * MI;
+      int cnt, ee;
+      const long long col = coef_col(A.lay, n, &cnt, &ee);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         int mo = l + T * e + rho;
         if (mo >= MI) mo -= MI;
-        v[k][e] = cmulc(row[mo], En);
+        v[k][e] = cmulc(coef_load(cb, MI, col, cnt, ee, mo), En);
       }
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int kp = l + T * e;
         const long long kk = kp == 0 ? 0 : MI - kp;
-        long long src;
+        long long nt, kt;
         C Ev;
-        shear_map(A, n, kk, &src, &Ev);
-        v[k][e] = cmulc(cb[src], Ev);
+        shear_map(A, n, kk, &nt, &kt, &Ev);
+        int cnt, ee;
+        const long long col = coef_col(A.lay, nt, &cnt, &ee);
+        v[k][e] = cmulc(coef_load(cb, int(A.M), col, cnt, ee, int(kt)), Ev);
       }
     }
     wave_fft<C, MI, true>(v[k], ex, l, tw);

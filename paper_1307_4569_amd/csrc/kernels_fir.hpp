@@ -36,6 +36,8 @@ template <typename C> struct FirArgs {
   long long L, start;
   int a, M, Lg, lam1, lam2, N, R, Sm;
   FftSched fm;
+  CoefLayout lay;  // coefficient layout (c, cs and cl follow it)
+  int real_out;    // the adjoint writes real samples
 };
 
 // Per-time-position constants of the folding: base = (n a + start) mod L
@@ -144,13 +146,16 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd_w(FirArgs<C> A) {
   C* ex = lds + (wave * TPW + tt) * WEx<C, MI>::EX;
   wave_fft<C, MI, false>(v, ex, l, tw);
   if (n < A.N) {
-    C* row = (A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs) + (long long)n * MI;
+    int cnt, ee;
+    C* row = (A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs) + coef_col(A.lay, n, &cnt, &ee);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      if constexpr (HS)
-        st_stream(row + l + T * e, v[e]);
-      else
-        row[l + T * e] = v[e];
+      if (l + T * e < cnt) {
+        if constexpr (HS)
+          st_stream(row + l + T * e, v[e]);
+        else
+          row[l + T * e] = v[e];
+      }
     }
   }
 }
@@ -252,13 +257,16 @@ __global__ void __launch_bounds__(kThreads, 4) k_fir_fwd_ws(FirArgs<C> A) {
   C* ex = lds + (wave * TPW + tt) * WEx<C, MI>::EX;
   wave_fft<C, MI, false>(v, ex, l, tw);
   if (n < A.N) {
-    C* row = (A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs) + (long long)n * MI;
+    int cnt, ee;
+    C* row = (A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs) + coef_col(A.lay, n, &cnt, &ee);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      if constexpr (HS)
-        st_stream(row + l + T * e, v[e]);
-      else
-        row[l + T * e] = v[e];
+      if (l + T * e < cnt) {
+        if constexpr (HS)
+          st_stream(row + l + T * e, v[e]);
+        else
+          row[l + T * e] = v[e];
+      }
     }
   }
 }
@@ -289,7 +297,10 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd(FirArgs<C> A) {
   C* cb = A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs;
   for (int e = threadIdx.x; e < R * M; e += kThreads) {
     const int r = e / M, m = e - r * M, n = n0 + r;
-    if (n < A.N) cb[(long long)n * M + m] = buf[r * Sm + m];
+    if (n >= A.N) continue;
+    int cnt, ee;
+    const long long col = coef_col(A.lay, n, &cnt, &ee);
+    if (m < cnt) cb[col + m] = buf[r * Sm + m];
   }
 }
 
@@ -308,10 +319,12 @@ __global__ void __launch_bounds__(kThreads) k_fir_adj_rows_w(FirArgs<C> A, C* Y,
   const long long bo = blockIdx.y;
   const int n = (blockIdx.x * 8 + wave) * TPW + tt;
   const bool ok = n < A.N;
-  const C* row = A.c + bo * A.cs + (long long)(ok ? n : 0) * MI;
+  int cnt, ee;
+  const long long col = coef_col(A.lay, ok ? n : 0, &cnt, &ee);
+  const C* cb = A.c + bo * A.cs;
   C v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = row[l + T * e];
+  for (int e = 0; e < E; ++e) v[e] = coef_load(cb, MI, col, cnt, ee, l + T * e);
   WTw<C, MI> tw;
   tw.load(A.twm, l);
   C* ex = lds + (wave * TPW + tt) * WEx<C, MI>::EX;
@@ -339,7 +352,13 @@ __global__ void __launch_bounds__(kThreads) k_fir_adj_rows(FirArgs<C> A, C* Y, l
   const C* cb = A.c + bo * A.cs;
   for (int e = threadIdx.x; e < R * M; e += kThreads) {
     const int r = e / M, m = e - r * M, n = n0 + r;
-    buf[r * Sm + m] = n < A.N ? cb[(long long)n * M + m] : czero<C>();
+    C v = czero<C>();
+    if (n < A.N) {
+      int cnt, ee;
+      const long long col = coef_col(A.lay, n, &cnt, &ee);
+      v = coef_load(cb, M, col, cnt, ee, m);
+    }
+    buf[r * Sm + m] = v;
   }
   __syncthreads();
   fft_lds<C, true>(buf, Sm, A.fm, R, tw);
@@ -393,7 +412,7 @@ __global__ void __launch_bounds__(kThreads) k_fir_adj_gather(FirArgs<C> A, const
     }
     acc = cadd(acc, s);
   }
-  f[bo * A.L + idx] = acc;
+  st_out(f, bo * A.L + idx, acc, A.real_out);
 }
 
 // Window support for the FIR algorithm: gw[j] = conj(g((start + j) mod L))

@@ -52,6 +52,7 @@ template <typename C> struct LongColArgs {
   int inmode, outmode, twmode;
   int tdiv, d, d2;
   FftSched fs;
+  int real_out;                // write the real part of y only (outmode 0 and 2)
 };
 
 template <typename C, bool INV>
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(kThreads) k_long_col(LongColArgs<C> A) {
       A.y[yoff + (long long)r * d + s2 + (long long)d2 * k] = v;
     } else {
       const long long idx = (long long)k * nc + col;
-      A.y[yoff + idx] = A.outmode == 2 ? apply_chirp(A.post, v, idx) : v;
+      st_out(A.y, yoff + idx, A.outmode == 2 ? apply_chirp(A.post, v, idx) : v, A.real_out);
     }
   }
 }

@@ -27,6 +27,7 @@ template <typename C> struct OlaArgs {
   const C* ph;         // exp(-2 pi i e / (lambda2 M)), e in Z_{lambda2 M}
   long long L, Lb, Lx, J0;
   int a, M, N, Nb, Nx, P0, lam1, lam2;
+  CoefLayout lay;      // layout of c (cs values per signal)
 };
 
 // X[k Nb + b][j] = f_k(b L_b - J0 + j) for j in [J0, J0 + L_b), else 0.
@@ -52,6 +53,9 @@ __global__ void __launch_bounds__(kThreads) k_ola_combine(OlaArgs<C> A) {
   const long long NM = (long long)A.N * A.M;
   if (idx >= NM) return;
   const int n = int(idx / A.M), m = int(idx - (long long)n * A.M);
+  int cnt, ee;
+  const long long col = coef_col(A.lay, n, &cnt, &ee);
+  if (m >= cnt) return;   // a channel the real-signal layout omits
   const long long k = blockIdx.y;
   const int Q = int(A.Lb / A.a);
   int t = n + A.P0;
@@ -70,7 +74,7 @@ __global__ void __launch_bounds__(kThreads) k_ola_combine(OlaArgs<C> A) {
     const C w = A.ph[(ob * mk) % PM];
     acc = cadd(acc, cmul(w, A.cl[((k * A.Nb + b) * A.Nx + np) * (long long)A.M + m]));
   }
-  A.c[k * A.cs + idx] = acc;
+  A.c[k * A.cs + col + m] = acc;
 }
 
 // Block window g_loc(i) = g((s + i) mod L) for i < L_g, 0 for i in [L_g, L_x)

@@ -58,6 +58,36 @@ void give_sync_event(hipEvent_t e);
 // thread): the two-stream pipeline is then not used.
 bool no_pipeline();
 
+// True while a call of the real-signal variant runs (per thread): the
+// launchers then read and write coefficients in the real-signal layout and
+// the synthesis writes real samples.  A scope that must use the full layout
+// (the inner blocks of shear-OLA) sets it with FullLayoutScope.
+bool real_call();
+void set_real_call(bool on);
+struct FullLayoutScope {
+  bool saved;
+  FullLayoutScope() : saved(real_call()) { set_real_call(false); }
+  ~FullLayoutScope() { set_real_call(saved); }
+};
+
+// Values per group of lambda2 columns in the real-signal layout: lambda2 M
+// minus the omitted channels of the one or two half-stored columns.
+inline long long real_row(const Plan& P) {
+  const long long M2 = P.M / 2 + 1;
+  return P.lam2 * P.M - (P.M - M2) * (P.lam2 % 2 == 0 ? 2 : 1);
+}
+// Coefficients per signal in the layout of the current call.
+inline long long coef_per_signal(const Plan& P) { return real_call() ? P.N / P.lam2 * real_row(P) : P.M * P.N; }
+inline CoefLayout coef_layout(const Plan& P) {
+  CoefLayout R;
+  R.real = real_call() ? 1 : 0;
+  R.lam2 = int(P.lam2);
+  R.M = int(P.M);
+  R.M2 = int(P.M / 2 + 1);
+  R.S = real_call() ? real_row(P) : P.M;
+  return R;
+}
+
 inline bool pipelined(const Plan& P, long long B, int op) {
   return op == DGTNS_OP_FORWARD && P.chunk > 0 && B >= 2 * P.chunk && !no_pipeline();
 }
@@ -439,7 +469,8 @@ int run_cols_long(const Plan& P, const void* x, long long xs, int real_in, Chirp
 }
 
 template <typename C>
-int run_adj_cols_long(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, hipStream_t st, C* U, C* V) {
+int run_adj_cols_long(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, hipStream_t st, C* U, C* V,
+                      int real_out) {
   if (!U || !V) return fail(DGTNS_EINVAL, "internal: no workspace for the two-level column passes");
   const long long ncol = P.Mi * P.pi, Md = P.Mi * P.di;
   const size_t es = sizeof(C);
@@ -465,6 +496,7 @@ int run_adj_cols_long(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long
   A3.post = ch;
   A3.y = y; A3.ys = P.L;
   A3.ncols = int(P.d2 * ncol); A3.inmode = 0; A3.outmode = 2; A3.twmode = 0;
+  A3.real_out = real_out;
   lds = es * (P.d1 + size_t(A3.W) * A3.Sn);
   return launch(k_long_col<C, true>, dim3(cdiv(A3.ncols, A3.W), unsigned(B), 1), lds, st, A3,
                 "adjoint factorisation, last column pass");
@@ -534,10 +566,11 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
 
 template <typename C>
 int run_adj_cols(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long B, hipStream_t st, C* U = nullptr,
-                 C* V = nullptr) {
-  if (P.longd) return run_adj_cols_long<C>(P, H, ch, y, B, st, U, V);
+                 C* V = nullptr, int real_out = 0) {
+  if (P.longd) return run_adj_cols_long<C>(P, H, ch, y, B, st, U, V, real_out);
   ColAdjArgs<C> A;
   std::memset(&A, 0, sizeof(A));
+  A.real_out = real_out;
   A.H = H; A.hs = h_per_signal(P);
   A.zc = tab<C>(P, P.off.zc);
   A.twd = tab<C>(P, P.off.tw_d);
@@ -568,7 +601,8 @@ RowArgs<C> row_args(const Plan& P, const C* H, C* c) {
   RowArgs<C> A;
   std::memset(&A, 0, sizeof(A));
   A.H = H; A.hs = h_per_signal(P);
-  A.c = c; A.cs = (long long)P.M * P.N;
+  A.c = c; A.cs = coef_per_signal(P);
+  A.lay = coef_layout(P);
   A.twm = tab<C>(P, P.off.tw_m);
   A.Mi = int(P.Mi); A.Ni = int(P.Ni);
   A.qw = int(P.qw); A.nw = int(P.nw);
@@ -655,6 +689,7 @@ int run_four_step(const Plan& P, const void* x, int real_in, C* tmp, C* y, long 
   RowFftArgs<C> R;
   std::memset(&R, 0, sizeof(R));
   R.x = tmp; R.xs = P.L; R.y = y; R.ys = P.L; R.post = post; R.scale = scale;
+  R.real_out = inv && real_call() ? 1 : 0;   // the synthesis' last pass writes the signal
   R.tws = inv ? tw1 : tw2;
   R.n = int(n2); R.nrows = int(n1); R.Sn = int(n2 | 1); R.R = block_width(R.Sn, sizeof(C)); R.fs = s2;
   lds = sizeof(C) * (n2 + size_t(R.R) * R.Sn);
@@ -694,6 +729,7 @@ FirArgs<C> fir_args(const Plan& P) {
   A.N = int(P.N);
   A.R = block_width(P.M | 1, sizeof(C)); A.Sm = int(P.M | 1);
   A.fm = sched(P.fm);
+  A.lay = coef_layout(P);
   return A;
 }
 
@@ -729,7 +765,7 @@ template <typename C>
 int run_fir_fwd(const Plan& P, const void* f, int real_in, C* c, long long B, hipStream_t st,
                 const void* const* flist, void* const* clist) {
   FirArgs<C> A = fir_args<C>(P);
-  A.x = f; A.xs = P.L; A.real_in = real_in; A.c = c; A.cs = P.M * P.N;
+  A.x = f; A.xs = P.L; A.real_in = real_in; A.c = c; A.cs = coef_per_signal(P);
   if (flist) {
     A.list = 1;
     for (long long k = 0; k < B; ++k) {
@@ -781,7 +817,8 @@ int run_fir_adj_rows(const FirArgs<C>& A, const Plan& P, long long B, C* Y, long
 template <typename C>
 int run_fir_adj(const Plan& P, const C* c, C* f, long long B, C* Y, hipStream_t st) {
   FirArgs<C> A = fir_args<C>(P);
-  A.c = const_cast<C*>(c); A.cs = P.M * P.N;
+  A.c = const_cast<C*>(c); A.cs = coef_per_signal(P);
+  A.real_out = real_call() ? 1 : 0;
   const long long ys = P.M * P.N;
   int rc = run_fir_adj_rows<C>(A, P, B, Y, ys, st);
   if (rc) return rc;
@@ -808,7 +845,7 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
   if (pipelined(P, B, DGTNS_OP_FORWARD)) {
     C* Hb[2] = {H, reinterpret_cast<C*>(ws + l.F)};
     const size_t sig_bytes = size_t(P.L) * (real_in ? sizeof(C) / 2 : sizeof(C));
-    const long long MN = P.M * P.N;
+    const long long MN = coef_per_signal(P);
     return run_pipeline(
         B, P.chunk, st,
         [&](long long b0, long long nb, int buf, hipStream_t s) {
@@ -825,7 +862,7 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
   }
   if (seq_chunked(P, B, DGTNS_OP_FORWARD)) {
     const size_t sig_bytes = size_t(P.L) * (real_in ? sizeof(C) / 2 : sizeof(C));
-    const long long MN = P.M * P.N;
+    const long long MN = coef_per_signal(P);
     for (long long b0 = 0; b0 < B; b0 += P.seq) {
       const long long nb = B - b0 < P.seq ? B - b0 : P.seq;
       if (flist)
@@ -874,7 +911,8 @@ int run_ola_fwd(const Plan& P, const void* f, int real_in, C* c, long long B, ch
   A.x = f; A.xs = P.L; A.real_in = real_in;
   A.X = reinterpret_cast<C*>(ws + l.ola_x);
   A.cl = reinterpret_cast<C*>(ws + l.ola_c);
-  A.c = c; A.cs = P.M * P.N;
+  A.c = c; A.cs = coef_per_signal(P);
+  A.lay = coef_layout(P);
   A.ph = tab<C>(P, P.off.fir_ph);
   A.L = P.L; A.Lb = P.ola_Lb; A.Lx = P.ola_Lx; A.J0 = P.ola_J0;
   A.a = int(P.a); A.M = int(P.M); A.N = int(P.N); A.Nb = int(P.ola_Nb); A.Nx = int(P.ola_Nx);
@@ -883,7 +921,10 @@ int run_ola_fwd(const Plan& P, const void* f, int real_in, C* c, long long B, ch
   int rc = launch_raw(k_ola_gather<C>, dim3(cdiv(P.ola_Lx, kThreads), unsigned(Bi)), dim3(kThreads), 0, st,
                       "OLA blocks", A);
   if (rc) return rc;
-  rc = forward_impl<C>(Q, A.X, 0, const_cast<C*>(A.cl), Bi, ws + l.inner, ws_layout(Q, DGTNS_OP_FORWARD, Bi), st);
+  {
+    FullLayoutScope full;   // block coefficients: full layout
+    rc = forward_impl<C>(Q, A.X, 0, const_cast<C*>(A.cl), Bi, ws + l.inner, ws_layout(Q, DGTNS_OP_FORWARD, Bi), st);
+  }
   if (rc) return rc;
   return launch_raw(k_ola_combine<C>, dim3(cdiv(P.N * P.M, kThreads), unsigned(B)), dim3(kThreads), 0, st,
                     "OLA overlap-add", A);
@@ -895,22 +936,27 @@ int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const L
   if (P.branch == kFir) return run_fir_adj<C>(P, c, f, B, H, st);
   if (pipelined(P, B, DGTNS_OP_ADJOINT)) {
     C* Hb[2] = {H, reinterpret_cast<C*>(ws + l.F)};
-    const long long MN = P.M * P.N;
+    const long long MN = coef_per_signal(P);
     return run_pipeline(
         B, P.chunk, st,
         [&](long long b0, long long nb, int buf, hipStream_t s) {
           return run_rows<C>(P, Hb[buf], const_cast<C*>(c) + b0 * MN, nb, true, s);
         },
         [&](long long b0, long long nb, int buf, hipStream_t s) {
-          return run_adj_cols<C>(P, Hb[buf], chirp_tab<C>(P, P.off.chirp1, 1), f + b0 * P.L, nb, s);
+          return run_adj_cols<C>(P, Hb[buf], chirp_tab<C>(P, P.off.chirp1, 1), f + b0 * P.L, nb, s, nullptr,
+                                 nullptr, real_call() ? 1 : 0);
         });
   }
   if (seq_chunked(P, B, DGTNS_OP_ADJOINT)) {
-    const long long MN = P.M * P.N;
+    const long long MN = coef_per_signal(P);
+    const size_t sig_bytes = size_t(P.L) * (real_call() ? sizeof(C) / 2 : sizeof(C));
     for (long long b0 = 0; b0 < B; b0 += P.seq) {
       const long long nb = B - b0 < P.seq ? B - b0 : P.seq;
+      C* fb = reinterpret_cast<C*>(reinterpret_cast<char*>(f) + b0 * sig_bytes);
       int rc = run_rows<C>(P, H, const_cast<C*>(c) + b0 * MN, nb, true, st);
-      if (!rc) rc = run_adj_cols<C>(P, H, chirp_tab<C>(P, P.off.chirp1, 1), f + b0 * P.L, nb, st);
+      if (!rc)
+        rc = run_adj_cols<C>(P, H, chirp_tab<C>(P, P.off.chirp1, 1), fb, nb, st, nullptr, nullptr,
+                             real_call() ? 1 : 0);
       if (rc) return rc;
     }
     return DGTNS_OK;
@@ -919,7 +965,8 @@ int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const L
   if (rc) return rc;
   C* U = reinterpret_cast<C*>(ws + l.U);
   C* V = reinterpret_cast<C*>(ws + l.V);
-  if (P.branch != kFreqShear) return run_adj_cols<C>(P, H, chirp_tab<C>(P, P.off.chirp1, 1), f, B, st, U, V);
+  if (P.branch != kFreqShear)
+    return run_adj_cols<C>(P, H, chirp_tab<C>(P, P.off.chirp1, 1), f, B, st, U, V, real_call() ? 1 : 0);
   C* F = reinterpret_cast<C*>(ws + l.F);
   C* Y = reinterpret_cast<C*>(ws + l.Y);
   rc = run_adj_cols<C>(P, H, no_chirp<C>(P), F, B, st, U, V);
