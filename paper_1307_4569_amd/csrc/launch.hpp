@@ -93,11 +93,16 @@ inline bool pipelined(const Plan& P, long long B, int op) {
 }
 
 // Sequential chunks of the forward and the adjoint: one h buffer of P.seq
-// signals, reused, when the whole batch's h is at least 256 MiB.
+// signals, reused, when the whole batch's h is at least 256 MiB.  Only for
+// FP32 columns of 32 to 512 values on the wave kernels, whose factorisation
+// kernels hold two work-groups per compute unit: with one (FP64, or FP32
+// d = 1024) a chunk's launch fills the GPU once or twice with work-groups in
+// the same phase, and the chunks were measured slower than one launch.
 inline bool seq_chunked(const Plan& P, long long B, int op) {
   if (op != DGTNS_OP_FORWARD && op != DGTNS_OP_ADJOINT) return false;
   if (P.seq < 1 || B <= P.seq || P.branch == kFreqShear || P.longd || P.branch == kFir || P.branch == kShearOla)
     return false;
+  if (P.dtype != 0 || P.pi != 1 || P.generic || P.di < 32 || P.di > 512 || (P.di & (P.di - 1)) != 0) return false;
   const double h_bytes = double(P.qi) * double(P.Mi) * double(P.di) * double(B) * (P.dtype == 0 ? 8.0 : 16.0);
   return h_bytes >= double(256ll << 20);
 }

@@ -16,6 +16,16 @@ Plans and their windows stay resident on the device.  Batches run on a pool
 of streams of default priority, so requests admitted while others run
 overlap on the GPU.  Latency is measured from a request's arrival time to
 the moment the loop observes its batch's completion event.
+
+Stream ordering: a batch's stream first waits for the work the submitting
+thread's current stream had enqueued when the batch was launched, so a
+signal produced asynchronously before submit() is complete when it is read.
+The request keeps its signal tensor alive until the batch completes.  The
+coefficient tensors handed out are recorded on the stream that is current
+when the loop retires the batch (the consumer's), so the caching allocator
+does not reuse their memory on a pool stream while the consumer's work on
+them is pending.  Each stream slot owns one workspace buffer, sized for the
+largest plan at max_batch and reused by every launch on that slot's stream.
 """
 from __future__ import annotations
 
@@ -59,6 +69,7 @@ class GpuExecutor:
         self.window_fn = window_fn
         self.plans: Dict[Key, object] = {}
         self.es = 8 if self.dtype == torch.complex64 else 16
+        self.ws = [None] * streams          # per-slot workspace, grown as plans are added
 
     def plan(self, key: Key):
         p = self.plans.get(key)
@@ -66,7 +77,11 @@ class GpuExecutor:
             from .api import Plan
             p = Plan(*key, dtype=self.dtype, max_batch=self.max_batch, device=self.device)
             p.set_window(self.window_fn(key))
+            need = self.B.dgtns_workspace_bytes(p._h, self.B.DGTNS_OP_FORWARD, self.max_batch)
             self.torch.cuda.synchronize(self.device)
+            for i in range(len(self.ws)):
+                if self.ws[i] is None or self.ws[i].numel() < need:
+                    self.ws[i] = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
             self.plans[key] = p
         return p
 
@@ -84,24 +99,27 @@ class GpuExecutor:
         p = self.plan(key)
         st = self.streams[slot]
         nb = len(reqs)
+        # the signals were produced on the submitter's stream
+        st.wait_stream(torch.cuda.current_stream(self.device))
+        ws = self.ws[slot]
         with torch.cuda.stream(st):
             c = torch.empty((nb, p.N, p.M), dtype=self.dtype, device=self.device)
-            wsb = self.B.dgtns_workspace_bytes(p._h, self.B.DGTNS_OP_FORWARD, nb)
-            ws = torch.empty(wsb, dtype=torch.uint8, device=self.device)
             base, stride = c.data_ptr(), p.N * p.M * self.es
             self.B.dgtns_forward_batch(p._h, [r.f.data_ptr() for r in reqs], 0,
-                                       [base + i * stride for i in range(nb)], ws.data_ptr(), wsb, st.cuda_stream)
+                                       [base + i * stride for i in range(nb)], ws.data_ptr(), ws.numel(),
+                                       st.cuda_stream)
             ev = torch.cuda.Event()
             ev.record(st)
-        return (ev, c, ws)
+        return (ev, c)
 
     @staticmethod
     def done(handle) -> bool:
         return handle[0].query()
 
-    @staticmethod
-    def outputs(handle):
+    def outputs(self, handle):
         c = handle[1]
+        # the consumer uses the coefficients on its own (current) stream
+        c.record_stream(self.torch.cuda.current_stream(self.device))
         return [c[i] for i in range(c.shape[0])]
 
     @property

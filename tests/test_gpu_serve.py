@@ -64,3 +64,32 @@ def test_admission_under_small_budget(setup):
     assert 0 < srv.peak_bytes <= budget
     for r in reqs[::9]:
         assert torch.equal(ex.plan(r.key).forward(r.f), r.c)
+
+
+def test_signals_produced_without_synchronising(setup):
+    """Signals written by torch work still pending on the current stream are
+    submitted without a synchronisation: each batch's stream waits for that
+    work, so the results equal the transforms computed afterwards.  The
+    coefficients handed out stay valid while the consumer's own work on them
+    runs and other batches allocate."""
+    from paper_1307_4569_amd.serve import Request, Server
+    ex, keys, _ = setup
+    sel = keys[:24]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4321)
+    # a long queue of work on the current stream ahead of the signals
+    x = torch.randn((2048, 2048), device="cuda", generator=gen)
+    for _ in range(8):
+        x = x @ x / 2048.0
+    sigs = [torch.randn(k[0], dtype=torch.complex64, generator=gen, device="cuda") + x[0, 0] * 0 for k in sel]
+    srv = Server(ex, hbm_budget=8 << 30, max_inflight_per_slot=2)
+    reqs = srv.run([Request(i, k, sigs[i], 0.0) for i, k in enumerate(sel)])
+    # consumer work on the handed-out coefficients, then more batches that allocate
+    norms = [r.c.abs().sum() for r in reqs]
+    srv2 = Server(ex, hbm_budget=8 << 30, max_inflight_per_slot=2)
+    srv2.run([Request(100 + i, k, sigs[i], 0.0) for i, k in enumerate(sel)])
+    torch.cuda.synchronize()
+    for r, nrm in zip(reqs, norms):
+        alone = ex.plan(r.key).forward(r.f)
+        assert torch.equal(alone, r.c), r.key
+        assert torch.equal(nrm, alone.abs().sum())

@@ -434,3 +434,14 @@ def test_sequential_chunk_workspace(lib, monkeypatch):
             assert B.dgtns_workspace_bytes(h, B.DGTNS_OP_WINDOW_GRAD, 64) >= 64 * per_sig
         finally:
             B.dgtns_plan_destroy(h)
+    # FP64 plans and FP32 columns of 1024 values (one factorisation work-group
+    # per compute unit) run one launch per stage
+    monkeypatch.delenv("DGTNS_SEQ_MIB", raising=False)
+    from dgt_inputs import PRECISION as p
+    for lat, dtype, per in (((w.L, w.a, w.M, w.lam1, w.lam2), 1, 2 * per_sig),
+                            ((p.L, p.a, p.M, p.lam1, p.lam2), 0, 8 * p.L * 8)):
+        h = B.dgtns_plan_create(*lat, dtype, 16)
+        try:
+            assert B.dgtns_workspace_bytes(h, B.DGTNS_OP_FORWARD, 16) >= 16 * per
+        finally:
+            B.dgtns_plan_destroy(h)
