@@ -64,9 +64,13 @@ template <typename C, int MI> struct FastRows {
 // HS: streaming stores of h (chosen at launch from the size of h, stream_h).
 // HT: h is written as h[n0][t][r] (time-major), which lets the row kernel read
 // each row of Mi channels as one contiguous run; otherwise h[n0][r][t].
-template <typename C, int D, bool HS, bool HT>
+// KF: wave transforms per wavefront (0: as many as the element budget allows;
+// 1: one, for the chunks of a sequential batch, whose h stays in the
+// last-level cache, so that the half-line rows of 8 columns cost nothing in
+// HBM and the lower register count lets more waves hide latency).
+template <typename C, int D, bool HS, bool HT, int KF = 0>
 __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
-  using F = FastCols<C, D>;
+  using F = FastCols<C, D, KF>;
   using I = WInfo<D>;
   constexpr int E = I::E, T = I::T, K = F::K, W = F::W, SD = F::SD;
   extern __shared__ __align__(16) unsigned char smem_raw[];

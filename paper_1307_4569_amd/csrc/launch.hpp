@@ -343,12 +343,12 @@ template <typename C> bool h_time_major(const Plan& P) {
   return cols && rows;
 }
 
-// min_wg: work-groups the launch aims for when the batch is small, by
-// splitting the q offsets of a column block over several work-groups (each
-// repeats the block's column DFTs).
-template <typename C, int D>
-int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t st, long long min_wg) {
-  using F = FastCols<C, D>;
+// The q offsets of a column block are split over several work-groups (each
+// repeats the block's column DFTs) until the launch has about min_wg
+// work-groups.
+template <typename C, int D, int KF>
+int run_cols_fast_k(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t st, long long min_wg) {
+  using F = FastCols<C, D, KF>;
   const long long nblk = cdiv(P.Mi, F::W);
   long long ns = (min_wg + nblk * B - 1) / (nblk * B);
   if (ns > P.qi) ns = P.qi;
@@ -358,12 +358,25 @@ int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t s
   dim3 grid(unsigned(nblk * ns), unsigned(B));
   if (A2.ht) {
     const size_t lds = sizeof(C) * F::LDS_T;
-    if (A2.hstream) return launch(k_fwd_cols_w<C, D, true, true>, grid, lds, st, A2, "factorisation kernel");
-    return launch(k_fwd_cols_w<C, D, false, true>, grid, lds, st, A2, "factorisation kernel");
+    if (A2.hstream) return launch(k_fwd_cols_w<C, D, true, true, KF>, grid, lds, st, A2, "factorisation kernel");
+    return launch(k_fwd_cols_w<C, D, false, true, KF>, grid, lds, st, A2, "factorisation kernel");
   }
   const size_t lds = sizeof(C) * F::LDS;
-  if (A2.hstream) return launch(k_fwd_cols_w<C, D, true, false>, grid, lds, st, A2, "factorisation kernel");
-  return launch(k_fwd_cols_w<C, D, false, false>, grid, lds, st, A2, "factorisation kernel");
+  if (A2.hstream) return launch(k_fwd_cols_w<C, D, true, false, KF>, grid, lds, st, A2, "factorisation kernel");
+  return launch(k_fwd_cols_w<C, D, false, false, KF>, grid, lds, st, A2, "factorisation kernel");
+}
+
+// chunk: the launch is a chunk of a sequential batch (FP32, d <= 512, h in the
+// last-level cache): one wave transform per wavefront (8 columns per
+// work-group) and at least 512 work-groups, two per compute unit.  Otherwise
+// as many transforms per wavefront as fit and at least about 2048
+// work-groups (8 per compute unit) for a small batch.
+template <typename C, int D>
+int run_cols_fast(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t st, bool chunk) {
+  if constexpr (sizeof(C) == 8 && D <= 512) {
+    if (chunk && !A.hstream) return run_cols_fast_k<C, D, 1>(P, A, B, st, 512);
+  }
+  return run_cols_fast_k<C, D, 0>(P, A, B, st, 2048);
 }
 
 template <typename C, int D>
@@ -507,14 +520,11 @@ int run_adj_cols_long(const Plan& P, const C* H, ChirpSrc<C> ch, C* y, long long
                 "adjoint factorisation, last column pass");
 }
 
-// min_wg: see run_cols_fast.  About 2048 (8 per compute unit) for a small
-// batch on its own; 512 (two per compute unit, one full wave of the grid) for
-// the chunks of a sequential batch, where repeating column DFTs costs more
-// than the idle compute units of a split-free launch.
+// chunk: the launch is a chunk of a sequential batch (run_cols_fast).
 template <typename C>
 int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C> ch, C* H, long long B,
              hipStream_t st, const void* const* xlist = nullptr, C* U = nullptr, C* V = nullptr,
-             long long min_wg = 2048) {
+             bool chunk = false) {
   if (P.longd) return run_cols_long<C>(P, x, xs, real_in, ch, H, B, st, xlist, U, V);
   ColArgs<C> A;
   std::memset(&A, 0, sizeof(A));
@@ -536,12 +546,12 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
   // wave kernels up to d = 1024 (FP32) or 512 (FP64; d = 1024 would spill registers)
   if (P.pi == 1 && !P.generic && P.di * long(sizeof(C)) <= 8192) {
     switch (P.di) {
-      case 32: return run_cols_fast<C, 32>(P, A, B, st, min_wg);
-      case 64: return run_cols_fast<C, 64>(P, A, B, st, min_wg);
-      case 128: return run_cols_fast<C, 128>(P, A, B, st, min_wg);
-      case 256: return run_cols_fast<C, 256>(P, A, B, st, min_wg);
-      case 512: return run_cols_fast<C, 512>(P, A, B, st, min_wg);
-      case 1024: return run_cols_fast<C, 1024>(P, A, B, st, min_wg);
+      case 32: return run_cols_fast<C, 32>(P, A, B, st, chunk);
+      case 64: return run_cols_fast<C, 64>(P, A, B, st, chunk);
+      case 128: return run_cols_fast<C, 128>(P, A, B, st, chunk);
+      case 256: return run_cols_fast<C, 256>(P, A, B, st, chunk);
+      case 512: return run_cols_fast<C, 512>(P, A, B, st, chunk);
+      case 1024: return run_cols_fast<C, 1024>(P, A, B, st, chunk);
       default: break;
     }
   }
@@ -872,10 +882,10 @@ int forward_impl(const Plan& P, const void* f, int real_in, C* c, long long B, c
       const long long nb = B - b0 < P.seq ? B - b0 : P.seq;
       if (flist)
         rc = run_cols<C>(P, nullptr, P.L, real_in, chirp_tab<C>(P, P.off.chirp1, 0), H, nb, st, flist + b0,
-                         nullptr, nullptr, 512);
+                         nullptr, nullptr, true);
       else
         rc = run_cols<C>(P, static_cast<const char*>(f) + b0 * sig_bytes, P.L, real_in,
-                         chirp_tab<C>(P, P.off.chirp1, 0), H, nb, st, nullptr, nullptr, nullptr, 512);
+                         chirp_tab<C>(P, P.off.chirp1, 0), H, nb, st, nullptr, nullptr, nullptr, true);
       if (!rc) rc = run_rows<C>(P, H, clist ? nullptr : c + b0 * MN, nb, false, st, clist ? clist + b0 : nullptr, B);
       if (rc) return rc;
     }
