@@ -188,9 +188,13 @@ int dgtns_plan_create_fir(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int
  * coefficients; the result equals eq. (DGT) with the truncated window.  The
  * work grows by the factor rho = L_x / block (eq. (OLA-eff)).  block must
  * divide L and be a multiple of lambda2 a, and max_batch * L / block must not
- * exceed 65535.  Such a plan runs dgtns_forward only; dgtns_forward_batch,
- * dgtns_adjoint, dgtns_window_grad, dgtns_dual_window and dgtns_tight_window
- * return DGTNS_EUNSUPPORTED.  dgtns_plan_info reports branch
+ * exceed 65535.  Such a plan runs dgtns_forward and dgtns_adjoint (and
+ * their real-signal variants); the adjoint takes each stage's adjoint in
+ * reverse order: every block receives the global coefficients of its
+ * positions times the conjugate position phases, the inner plan synthesises
+ * all blocks as one batch, and each block's own samples form the signal.
+ * dgtns_forward_batch, dgtns_window_grad, dgtns_dual_window and
+ * dgtns_tight_window return DGTNS_EUNSUPPORTED.  dgtns_plan_info reports branch
  * DGTNS_SHEAR_OLA with the inner plan's s0, s1, b_r, c, d, p, q.  Errors as
  * for dgtns_plan_create_fir, plus DGTNS_EINVAL for a bad block length and
  * DGTNS_EUNSUPPORTED when no feasible block length below L exists.

@@ -132,14 +132,13 @@ int forward_body(const Plan& P, const void* f, int real_input, void* c, int64_t 
 }
 
 int adjoint_body(const Plan& P, const void* c, void* f, int64_t B, char* w, const Layout& l, hipStream_t st) {
-  if (P.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "shear-OLA plans compute the forward transform only");
   if (P.dtype == 0) return adjoint_c64(P, c, f, B, w, l, st);
   return adjoint_c128(P, c, f, B, w, l, st);
 }
 
 int grad_body(const Plan& P, const void* f, const void* gc, void* gg, int64_t B, char* w, const Layout& l,
               hipStream_t st) {
-  if (P.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "shear-OLA plans compute the forward transform only");
+  if (P.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for shear-algorithm plans only");
   if (P.branch == kMultiwindow || P.branch == kFir)
     return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for shear-algorithm plans only");
   if (P.pi != 1) return fail(DGTNS_EUNSUPPORTED, "window gradient is implemented for p = 1 of the sheared lattice");

@@ -77,6 +77,50 @@ __global__ void __launch_bounds__(kThreads) k_ola_combine(OlaArgs<C> A) {
   A.c[k * A.cs + col + m] = acc;
 }
 
+// Adjoint of the overlap-add: block b's coefficient at local position n' is
+// the global coefficient c(m, n) of the position n it adds to, times the
+// conjugate of the combine's phase:
+//     cl[k Nb + b][n'][m] = conj(exp(-2 pi i o_b (m lambda2 + kn) / (lambda2 M))) c_k(m, n),
+// with i = n' div Q, n00 = n' mod Q (Q = L_b / a), n = ((b + i) mod Nb) Q +
+// n00 - P0 (mod N).  grid (ceil(Nx M / kThreads), B Nb).
+template <typename C>
+__global__ void __launch_bounds__(kThreads) k_ola_split(OlaArgs<C> A) {
+  const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const long long NxM = (long long)A.Nx * A.M;
+  if (idx >= NxM) return;
+  const int np = int(idx / A.M), m = int(idx - (long long)np * A.M);
+  const long long kb = blockIdx.y;
+  const long long k = kb / A.Nb;
+  const int b = int(kb - k * A.Nb);
+  const int Q = int(A.Lb / A.a);
+  const int i = np / Q, n00 = np - i * Q;
+  int bh = b + i;
+  if (bh >= A.Nb) bh -= A.Nb;   // i < Nb (np < Nx < N)
+  int n = bh * Q + n00 - A.P0;
+  if (n < 0) n += A.N;
+  const long long PM = (long long)A.lam2 * A.M;
+  const long long mk = (long long)m * A.lam2 + ((long long)n * A.lam1) % A.lam2;
+  long long ob = ((long long)b * A.Lb - A.J0) % PM;
+  if (ob < 0) ob += PM;
+  const C w = A.ph[(ob * mk) % PM];
+  int cnt, ee;
+  const long long col = coef_col(A.lay, n, &cnt, &ee);
+  const C v = coef_load(A.c + k * A.cs, A.M, col, cnt, ee, m);
+  const_cast<C*>(A.cl)[kb * NxM + idx] = cmulc(v, w);
+}
+
+// Adjoint of the block gather: sample j of block b's synthesis, j in
+// [J0, J0 + L_b), is global sample b L_b + j - J0 (each sample in one block).
+// grid (ceil(L / kThreads), B).
+template <typename C>
+__global__ void __launch_bounds__(kThreads) k_ola_scatter(OlaArgs<C> A, C* f, int real_out) {
+  const long long l = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (l >= A.L) return;
+  const long long k = blockIdx.y;
+  const long long b = l / A.Lb, j = l - b * A.Lb + A.J0;
+  st_out(f, k * A.L + l, A.X[(k * A.Nb + b) * A.Lx + j], real_out);
+}
+
 // Block window g_loc(i) = g((s + i) mod L) for i < L_g, 0 for i in [L_g, L_x)
 // (FP64).  grid ceil(Lx / kThreads).
 template <int Unused = 0>

@@ -274,7 +274,7 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
   if (P.branch == kShearOla) {
     // blocks and block coefficients, then the inner plan's own workspace
     const long long Bi = B * P.ola_Nb;
-    if (op == DGTNS_OP_FORWARD) {
+    if (op == DGTNS_OP_FORWARD || op == DGTNS_OP_ADJOINT) {
       l.ola_x = take(es * size_t(P.ola_Lx) * Bi);
       l.ola_c = take(es * size_t(P.ola_Nx) * size_t(P.M) * Bi);
       l.inner = take(ws_layout(*P.inner, op, Bi).total);
@@ -946,7 +946,42 @@ int run_ola_fwd(const Plan& P, const void* f, int real_in, C* c, long long B, ch
 }
 
 template <typename C>
+int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const Layout& l, hipStream_t st);
+
+// Shear-OLA adjoint: the adjoint of each forward stage in reverse order.  The
+// global coefficients are split into the blocks' coefficients with the
+// conjugate position phases, the inner plan synthesises all blocks as one
+// batch, and each block's own samples are written back to the signal.
+template <typename C>
+int run_ola_adj(const Plan& P, const C* c, C* f, long long B, char* ws, const Layout& l, hipStream_t st) {
+  const Plan& Q = *P.inner;
+  OlaArgs<C> A;
+  std::memset(&A, 0, sizeof(A));
+  A.X = reinterpret_cast<C*>(ws + l.ola_x);
+  A.cl = reinterpret_cast<C*>(ws + l.ola_c);
+  A.c = const_cast<C*>(c); A.cs = coef_per_signal(P);
+  A.lay = coef_layout(P);
+  A.ph = tab<C>(P, P.off.fir_ph);
+  A.L = P.L; A.Lb = P.ola_Lb; A.Lx = P.ola_Lx; A.J0 = P.ola_J0;
+  A.a = int(P.a); A.M = int(P.M); A.N = int(P.N); A.Nb = int(P.ola_Nb); A.Nx = int(P.ola_Nx);
+  A.P0 = int(P.ola_P0); A.lam1 = int(P.lam1); A.lam2 = int(P.lam2);
+  const long long Bi = B * P.ola_Nb;
+  int rc = launch_raw(k_ola_split<C>, dim3(cdiv(P.ola_Nx * P.M, kThreads), unsigned(Bi)), dim3(kThreads), 0, st,
+                      "OLA split", A);
+  if (rc) return rc;
+  const int real_out = real_call() ? 1 : 0;
+  {
+    FullLayoutScope full;   // block coefficients and block signals: full layout, complex
+    rc = adjoint_impl<C>(Q, A.cl, A.X, Bi, ws + l.inner, ws_layout(Q, DGTNS_OP_ADJOINT, Bi), st);
+  }
+  if (rc) return rc;
+  return launch_raw(k_ola_scatter<C>, dim3(cdiv(P.L, kThreads), unsigned(B)), dim3(kThreads), 0, st,
+                    "OLA block scatter", A, f, real_out);
+}
+
+template <typename C>
 int adjoint_impl(const Plan& P, const C* c, C* f, long long B, char* ws, const Layout& l, hipStream_t st) {
+  if (P.branch == kShearOla) return run_ola_adj<C>(P, c, f, B, ws, l, st);
   C* H = reinterpret_cast<C*>(ws + l.H);
   if (P.branch == kFir) return run_fir_adj<C>(P, c, f, B, H, st);
   if (pipelined(P, B, DGTNS_OP_ADJOINT)) {
