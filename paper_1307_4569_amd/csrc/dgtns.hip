@@ -141,7 +141,6 @@ int grad_body(const Plan& P, const void* f, const void* gc, void* gg, int64_t B,
   if (P.branch == kShearOla) return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for shear-algorithm plans only");
   if (P.branch == kMultiwindow || P.branch == kFir)
     return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for shear-algorithm plans only");
-  if (P.pi != 1) return fail(DGTNS_EUNSUPPORTED, "window gradient is implemented for p = 1 of the sheared lattice");
   if (P.dtype == 0) return grad_c64(P, f, gc, gg, B, w, l, st);
   return grad_c128(P, f, gc, gg, B, w, l, st);
 }

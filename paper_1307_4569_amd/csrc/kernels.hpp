@@ -1004,13 +1004,18 @@ __global__ void __launch_bounds__(kThreads) k_minmax_final(const double* part, i
 }
 
 // ----------------------------------------------------------------------------
-// Window gradient (p = 1).  For output window column u and time offset n0 the
-// contributing signal column is r = (u + n0 ai) mod Mi; in the Zak domain
-//   grad Zg_u(nu) += X_r(nu) conj(Hhat_{n0,r}(nu)) exp(-2 pi i nu delta/d) / d,
-// with Hhat the DFT over t' of h*_{n0 + q t'}(r) and delta = -1 when the
-// column index wrapped.  The window gradient is the unnormalised inverse DFT
-// of grad Zg.  grid (ceil(Mi/W), B): one partial per signal, summed by
-// k_batch_sum (deterministic, no atomics).
+// Window gradient.  The window's Zak transform has Mi p columns u (window
+// samples u + Mi p t, t in Z_d); the factorisation multiplies signal column
+// (r, j0) (samples r + Mi j0 + Mi p t) by conj(Zg_u) with u = r + Mi j0 - n0 ai
+// (mod Mi p, a wrap multiplying by exp(-2 pi i nu / d)).  For a given u and
+// time offset n0 exactly one pair (r, j0) contributes: w = u + n0 ai mod Mi p,
+// j0 = w div Mi, r = w mod Mi.  In the Zak domain
+//   grad Zg_u(nu) += X_w(nu) conj(Hhat_{n0,r}(nu)) exp(-2 pi i nu delta/d) / d,
+// with X_w the DFT over t of the signal column w, Hhat the DFT over t' of
+// h*_{n0 + q t'}(r) and delta = -1 when w wrapped.  (p = 1: w = r.)  The
+// window gradient is the unnormalised inverse DFT of grad Zg.  grid
+// (ceil(Mi p / W), B): one partial per signal, summed by k_batch_sum
+// (deterministic, no atomics).
 // ----------------------------------------------------------------------------
 template <typename C> struct GradArgs {
   const void* x;
@@ -1023,6 +1028,7 @@ template <typename C> struct GradArgs {
   long long ps;
   const C* twd;
   int Mi, ai, d, q, W, Sd;
+  int p;                       // columns of the window's Zak transform: Mi p
   FftSched fd;
 };
 
@@ -1035,7 +1041,7 @@ __global__ void __launch_bounds__(kThreads) k_grad_cols(GradArgs<C> A) {
   C* lds = reinterpret_cast<C*>(smem_raw);
   C* twl = lds;
   const C* tw = TWG ? A.twd : twl;
-  const int d = A.d, W = A.W, Sd = A.Sd, Mi = A.Mi;
+  const int d = A.d, W = A.W, Sd = A.Sd, Mi = A.Mi, Mp = A.Mi * A.p;
   C* xb = TWG ? lds : lds + d;   // W transforms of the signal columns, then W of h*
   C* yb = xb + W * Sd;
   if (!TWG)
@@ -1052,10 +1058,10 @@ __global__ void __launch_bounds__(kThreads) k_grad_cols(GradArgs<C> A) {
     for (int e = threadIdx.x; e < WD; e += kThreads) {
       const int t = e / W, cc = e - t * W, u = u0 + cc;
       C v = czero<C>();
-      if (u < Mi) {
-        int r = u + n0 * A.ai;
-        if (r >= Mi) r -= Mi;
-        const long long l = r + (long long)t * Mi;
+      if (u < Mp) {
+        int w = u + n0 * A.ai;
+        if (w >= Mp) w -= Mp;
+        const long long l = w + (long long)t * Mp;
         v = apply_chirp(A.chirp, load_sig<C>(A.x, A.real_in, bo * A.xs + l), l);
       }
       xb[cc * Sd + t] = v;
@@ -1063,9 +1069,10 @@ __global__ void __launch_bounds__(kThreads) k_grad_cols(GradArgs<C> A) {
     for (int e = threadIdx.x; e < WD; e += kThreads) {
       const int cc = e / d, t = e - cc * d, u = u0 + cc;
       C h = czero<C>();
-      if (u < Mi) {
-        int r = u + n0 * A.ai;
-        if (r >= Mi) r -= Mi;
+      if (u < Mp) {
+        int w = u + n0 * A.ai;
+        if (w >= Mp) w -= Mp;
+        const int r = w - (w / Mi) * Mi;
         h = A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t];
       }
       yb[cc * Sd + t] = h;
@@ -1083,9 +1090,9 @@ __global__ void __launch_bounds__(kThreads) k_grad_cols(GradArgs<C> A) {
       const int e = threadIdx.x + i * kThreads;
       if (e < WD) {
         const int cc = e / d, nu = e - cc * d, u = u0 + cc;
-        if (u < Mi) {
+        if (u < Mp) {
           C pr = cmulc(xb[cc * Sd + nu], yb[cc * Sd + nu]);
-          if (u + n0 * A.ai >= Mi) pr = cmulc(pr, tw[nu]);
+          if (u + n0 * A.ai >= Mp) pr = cmulc(pr, tw[nu]);
           acc[i] = cadd(acc[i], pr);
         }
       }
@@ -1105,7 +1112,7 @@ __global__ void __launch_bounds__(kThreads) k_grad_cols(GradArgs<C> A) {
   fft_lds<C, true>(xb, Sd, A.fd, W, tw);
   for (int e = threadIdx.x; e < WD; e += kThreads) {
     const int t = e / W, cc = e - t * W, u = u0 + cc;
-    if (u < Mi) A.part[bo * A.ps + u + (long long)t * Mi] = xb[cc * Sd + t];
+    if (u < Mp) A.part[bo * A.ps + u + (long long)t * Mp] = xb[cc * Sd + t];
   }
 }
 

@@ -1073,11 +1073,12 @@ int run_grad_cols_generic(const Plan& P, const void* x, ChirpSrc<C> ch, const C*
   A.part = part; A.ps = P.L;
   A.twd = tab<C>(P, P.off.tw_d);
   A.Mi = int(P.Mi); A.ai = int(P.ai); A.d = int(P.di); A.q = int(P.qi);
+  A.p = int(P.pi);
   A.Sd = int(P.di | 1);
   A.W = block_width(2 * A.Sd, sizeof(C));
   A.fd = sched(P.fd);
   const size_t lds = sizeof(C) * (P.di + 2 * size_t(A.W) * A.Sd), lcols = sizeof(C) * 2 * size_t(A.W) * A.Sd;
-  const dim3 grid(cdiv(P.Mi, A.W), unsigned(B));
+  const dim3 grid(cdiv(P.Mi * P.pi, A.W), unsigned(B));
   if (lds <= 160 * 1024) return launch(k_grad_cols<C, false>, grid, lds, st, A, "window gradient");
   return launch(k_grad_cols<C, true>, grid, lcols, st, A, "window gradient");
 }

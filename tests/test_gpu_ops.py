@@ -43,11 +43,15 @@ def plan_for(lat, dtype, B):
     return Plan(*lat, dtype=dtype, max_batch=B)
 
 
-# lattices with p = 1 of the sheared lattice, both shear branches
+# lattices of both shear branches and the separable one
 GRAD_LATTICES = [(144, 6, 12, 1, 2), (16, 4, 8, 1, 2), (72, 6, 12, 1, 3), (2048, 16, 64, 1, 2),
                  (4096, 32, 128, 1, 2), (18432, 32, 256, 1, 2), (1152, 8, 64, 2, 3), (576, 4, 32, 0, 1),
                  # d = 32 and 64 with Mi = 12: ragged work-groups of the wave-kernel gradient
-                 (384, 2, 12, 1, 2), (768, 2, 12, 0, 1)]
+                 (384, 2, 12, 1, 2), (768, 2, 12, 0, 1),
+                 # p > 1 of the sheared lattice: time shear, frequency shear and separable
+                 # plans with p = 2, 3, 5, 7 and a Fig. 2 shape (a, M) = (40, 60)
+                 (48, 4, 6, 1, 2), (48, 4, 6, 1, 4), (48, 6, 8, 0, 1), (72, 6, 8, 1, 3), (120, 10, 12, 1, 2),
+                 (224, 7, 8, 1, 2), (2400, 40, 60, 1, 2), (3600, 40, 60, 1, 3)]
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
@@ -225,7 +229,7 @@ def test_autograd_gradcheck_fp64():
     assert torch.autograd.gradcheck(fn, (f, g), eps=1e-6, atol=1e-8, rtol=1e-6, fast_mode=True)
 
 
-@pytest.mark.parametrize("lat", [(144, 6, 12, 1, 2), (4096, 32, 128, 1, 2)])
+@pytest.mark.parametrize("lat", [(144, 6, 12, 1, 2), (4096, 32, 128, 1, 2), (2400, 40, 60, 1, 2)])
 def test_autograd_matches_oracle_gradients(lat):
     from paper_1307_4569_amd import DGTFunction
     L, a, M, l1, l2 = lat
