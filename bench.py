@@ -232,6 +232,9 @@ def crossover_bench(torch, dev, steps=5):
             if "ms_per_signal" in row.get("shear", {}) and "ms_per_signal" in row.get("multiwindow", {}):
                 row["faster"] = ("shear" if row["shear"]["ms_per_signal"] < row["multiwindow"]["ms_per_signal"]
                                  else "multiwindow")
+                ap = Plan(L, a, M, lam1, lam2, dtype=torch.complex64, max_batch=1, device=dev, algorithm="auto")
+                row["auto_choice"] = "multiwindow" if ap.info.branch == Bm.DGTNS_MULTIWINDOW else "shear"
+                del ap
             rows.append(row)
             log(f"crossover a={a} M={M} lambda={lam1}/{lam2}: "
                 + ", ".join(f"{k} {v.get('ms_per_signal')}" for k, v in row.items() if isinstance(v, dict)))
@@ -508,9 +511,11 @@ def serve_bench(nreq, torch, dev):
     (L in {36864, 73728, 147456, 294912}, (a, M) in {(32,256), (64,512)},
     lambda in {1/2, 1/3, 2/3}), signals CN(0,1) pre-staged in HBM.  The FP32
     continuous-batching server (4 streams, list batches of up to 8) and the
-    plain FP64 per-request server (1 stream, batch 1) are each measured closed
-    loop (capacity mu) and open loop with Poisson arrivals at 0.5, 0.8 and
-    0.95 mu."""
+    plain FP64 per-request server (1 stream, batch 1, shear algorithm) are
+    each measured closed loop (capacity mu) and open loop with Poisson
+    arrivals at 0.5, 0.8 and 0.95 mu.  The FP32 server's plans choose their
+    algorithm (DGTNS_ALG_AUTO: multiwindow for the six lattices whose shear
+    needs a frequency shear)."""
     import numpy as np
 
     from dgt_inputs import gaussian_window, poisson_arrivals, serving_plans, serving_requests, seed_for
@@ -563,9 +568,9 @@ def serve_bench(nreq, torch, dev):
         CHECKS.add(res, "max_rel_err_vs_oracle", fn)
         return res
 
-    def run_server(name, dtype, streams, max_batch, inflight, sigs, rates=None):
+    def run_server(name, dtype, streams, max_batch, inflight, sigs, rates=None, algorithm="auto"):
         ex = GpuExecutor(lambda k: torch.tensor(gaussian_window(k[0], k[1], k[2])), dtype=dtype, streams=streams,
-                         max_batch=max_batch, device=dev)
+                         max_batch=max_batch, device=dev, algorithm=algorithm)
         ex.prepare(plans)
         mk = lambda: [Request(j, key, sigs[j], 0.0) for j, (_, key, _) in enumerate(spec)]
         srv = Server(ex, hbm_budget=16 << 30, max_inflight_per_slot=inflight, keep_outputs=False)
@@ -594,7 +599,7 @@ def serve_bench(nreq, torch, dev):
         return res
 
     sig64 = [x.to(torch.complex128) for x in sig32]
-    out["fp64_per_request"] = run_server("fp64", torch.complex128, 1, 1, 4, sig64)
+    out["fp64_per_request"] = run_server("fp64", torch.complex128, 1, 1, 4, sig64, algorithm="shear")
     del sig64
     # the FP32 server also at the FP64 server's offered rates, for latencies
     # measured under the same load

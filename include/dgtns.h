@@ -82,7 +82,8 @@ enum dgtns_algorithm {
   DGTNS_ALG_SHEAR = 0,      /* shear algorithm, Alg. 1 (dgtns_plan_create) */
   DGTNS_ALG_MULTIWINDOW = 1, /* multiwindow algorithm, Section 3.1 (Prop. 4, Prop. 5) */
   DGTNS_ALG_FIR = 2,         /* FIR-window algorithm: use dgtns_plan_create_fir */
-  DGTNS_ALG_SHEAR_OLA = 3    /* shear-OLA algorithm: use dgtns_plan_create_ola */
+  DGTNS_ALG_SHEAR_OLA = 3,   /* shear-OLA algorithm: use dgtns_plan_create_ola */
+  DGTNS_ALG_AUTO = 4         /* shear or multiwindow, chosen by the plan (dgtns_plan_create_alg) */
 };
 
 enum dgtns_op {
@@ -151,6 +152,13 @@ int dgtns_plan_create(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t
  * s0 = s1 = 0, inner_a = lambda2 a, q per window and windows = lambda2; the
  * persistent memory holds lambda2 window tables.  Errors as for
  * dgtns_plan_create, plus DGTNS_EINVAL for an unknown algorithm.
+ * DGTNS_ALG_AUTO chooses between the two (Section 4.4: the multiwindow
+ * algorithm is the fast one for simple lattices, the shear algorithm for
+ * complex ones): the shear plan, unless its factorisation needs a frequency
+ * shear (s0 != 0) and the multiwindow lattice (lambda2 a, M) has
+ * p = lambda2 a / gcd(lambda2 a, M) <= 15, in which case the multiwindow plan
+ * (when the multiwindow kernels cover the lattice).  dgtns_plan_info's
+ * branch tells which was chosen.
  */
 int dgtns_plan_create_alg(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1,
                           int64_t lambda2, int dtype, int64_t max_batch, int algorithm);

@@ -31,6 +31,7 @@ DGTNS_ALG_SHEAR = 0
 DGTNS_ALG_MULTIWINDOW = 1
 DGTNS_ALG_FIR = 2
 DGTNS_ALG_SHEAR_OLA = 3
+DGTNS_ALG_AUTO = 4
 
 DGTNS_OP_FORWARD = 0
 DGTNS_OP_ADJOINT = 1

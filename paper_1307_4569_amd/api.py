@@ -24,7 +24,7 @@ def _stream_handle(device) -> int:
 
 
 _ALG = {"shear": B.DGTNS_ALG_SHEAR, "multiwindow": B.DGTNS_ALG_MULTIWINDOW, "fir": B.DGTNS_ALG_FIR,
-        "shear-ola": B.DGTNS_ALG_SHEAR_OLA}
+        "shear-ola": B.DGTNS_ALG_SHEAR_OLA, "auto": B.DGTNS_ALG_AUTO}
 
 
 class Plan:

@@ -323,12 +323,13 @@ template <typename C> struct ColAdjArgs {
 // (fft_wave_rt) with no further work-group barrier.  The column spectrum
 // stays in registers (MV values per lane) across the q window products.
 // TWL: the twiddle table is copied into LDS after the tile (when it fits).
-// grid (ceil(Mi / 8) * nsplit, B), 512 threads.
-template <typename C, int MV, bool TWL>
-__global__ void __launch_bounds__(kThreads) k_fwd_cols_wr(ColArgs<C> A) {
+// NW: wavefronts (columns) per work-group.
+// grid (ceil(Mi / NW) * nsplit, B), 64 NW threads.
+template <typename C, int MV, bool TWL, int NW = kThreads / 64>
+__global__ void __launch_bounds__(64 * NW) k_fwd_cols_wr(ColArgs<C> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
-  constexpr int W = kThreads / 64;
+  constexpr int W = NW, NT = 64 * NW;
   const int d = A.d, Sd = A.Sd, Mi = A.Mi;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int cb = blockIdx.x / A.nsplit, part = blockIdx.x - cb * A.nsplit;
@@ -338,7 +339,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_wr(ColArgs<C> A) {
   const long long bo = blockIdx.y;
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = A.list ? 0 : bo * A.xs;
-  for (int e = tid; e < W * d; e += kThreads) {
+  for (int e = tid; e < W * d; e += NT) {
     const int t = e / W, cc = e - t * W, r = r0 + cc;
     C v = czero<C>();
     if (r < Mi) {
@@ -350,7 +351,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_wr(ColArgs<C> A) {
   const C* twl = A.twd;
   if constexpr (TWL) {
     C* t = lds + W * Sd;
-    for (int e = tid; e < d; e += kThreads) t[e] = A.twd[e];
+    for (int e = tid; e < d; e += NT) t[e] = A.twd[e];
     twl = t;
   }
   __syncthreads();

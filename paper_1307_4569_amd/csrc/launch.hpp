@@ -209,6 +209,20 @@ int launch(K kernel, dim3 grid, size_t lds, hipStream_t st, const A& args, const
   return launch_v(kernel, grid, lds, st, name, args);
 }
 
+// launch with `threads` threads per work-group (the kernel's launch bounds)
+template <typename K, typename A>
+int launch_t(K kernel, dim3 grid, unsigned threads, size_t lds, hipStream_t st, const A& args, const char* name) {
+  if (grid.x == 0 || grid.y == 0) return DGTNS_OK;
+  if (lds > 160 * 1024) return fail(DGTNS_EUNSUPPORTED, std::string(name) + ": LDS request above 160 KiB");
+  if (dry_run()) return DGTNS_OK;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return check_hip(e, name);
+  }
+  return launch_raw(kernel, grid, dim3(threads), lds, st, name, args);
+}
+
 inline unsigned cdiv(long long a, long long b) { return unsigned((a + b - 1) / b); }
 
 // Device address of a table in the plan's persistent block (integer
@@ -557,16 +571,26 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
   }
   // other 7-smooth d up to 1152 (p = 1): one wavefront per column
   if (P.pi == 1 && !P.generic && P.di <= 1152) {
+    // FP32 columns above 576 values: 4 columns per work-group, so that three
+    // work-groups (12 wavefronts at 142 VGPRs) share a compute unit instead of
+    // one 8-column work-group holding 83 KB of LDS (batches of 8 serving
+    // requests, L = 294912: 159 -> 138 us; at d = 576 the 4-column form was
+    // slower on one plan and faster on another, so it keeps 8 columns)
+    const int nw = (sizeof(C) == 8 && P.di > 576) ? 4 : 8;
     // the twiddle table joins the tile in LDS when both fit in 160 KiB
-    const size_t lt = es * 8 * size_t(A.Sd), lw = lt + es * size_t(P.di);
+    const size_t lt = es * nw * size_t(A.Sd), lw = lt + es * size_t(P.di);
     const bool twl = lw <= 160 * 1024;
-    const long long nblk = cdiv(P.Mi, 8);
+    const long long nblk = cdiv(P.Mi, nw);
     // small batches: split the q offsets until every work-group slot is used once
     long long ns = (512 + nblk * B - 1) / (nblk * B);
     if (ns > P.qi) ns = P.qi;
     if (ns < 1) ns = 1;
     A.nsplit = int(ns);
     dim3 gw(unsigned(nblk * ns), unsigned(B));
+    if (nw == 4) {
+      if (twl) return launch_t(k_fwd_cols_wr<C, 18, true, 4>, gw, 256, lw, st, A, "factorisation kernel");
+      return launch_t(k_fwd_cols_wr<C, 18, false, 4>, gw, 256, lt, st, A, "factorisation kernel");
+    }
     if (!twl) return launch(k_fwd_cols_wr<C, 18, false>, gw, lt, st, A, "factorisation kernel");
     if (P.di <= 320) return launch(k_fwd_cols_wr<C, 5, true>, gw, lw, st, A, "factorisation kernel");
     if (P.di <= 576) return launch(k_fwd_cols_wr<C, 9, true>, gw, lw, st, A, "factorisation kernel");

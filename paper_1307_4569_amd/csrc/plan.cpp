@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <utility>
 #include <map>
 
 namespace dgtns {
@@ -217,9 +218,23 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
   const int kEInval = 1, kELattice = 2, kEUnsupported = 4;
   if (dtype != 0 && dtype != 1) { *err = "dtype must be DGTNS_C64 or DGTNS_C128"; return kEInval; }
   if (algorithm != kAlgShear && algorithm != kAlgMultiwindow && algorithm != kAlgFir &&
-      algorithm != kAlgShearOla) {
-    *err = "algorithm must be DGTNS_ALG_SHEAR, DGTNS_ALG_MULTIWINDOW, DGTNS_ALG_FIR or DGTNS_ALG_SHEAR_OLA";
+      algorithm != kAlgShearOla && algorithm != kAlgAuto) {
+    *err = "algorithm must be DGTNS_ALG_SHEAR, DGTNS_ALG_MULTIWINDOW, DGTNS_ALG_FIR, DGTNS_ALG_SHEAR_OLA or DGTNS_ALG_AUTO";
     return kEInval;
+  }
+  if (algorithm == kAlgAuto) {
+    // The shear plan, unless it needs a frequency shear (a length-L
+    // transform pair and Alg. 1's scattered output permutation, measured at
+    // 2.3-3.3x the multiwindow plan on such lattices) and the multiwindow
+    // lattice keeps p small enough (measured faster up to p = 15).
+    int rc = plan_make(L, a, M, lam1, lam2, dtype, max_batch, kAlgShear, P, err);
+    if (rc != 0 || P->branch != kFreqShear) return rc;
+    const int64_t ai = lam2 * a, pmw = ai / gcd64(ai, M);
+    if (pmw > kAutoMaxP) return rc;
+    Plan mw;
+    std::string e2;
+    if (plan_make(L, a, M, lam1, lam2, dtype, max_batch, kAlgMultiwindow, &mw, &e2) == 0) *P = std::move(mw);
+    return 0;
   }
   if (L < 1 || a < 1 || M < 1 || max_batch < 1) { *err = "L, a, M and max_batch must be positive"; return kEInval; }
   if (L > kMaxL) { *err = "L above 2^30 is not supported"; return kEUnsupported; }

@@ -54,7 +54,12 @@ bool fft_schedule(int64_t n, FftSchedule* out);
 Shear shearfind(int64_t L, int64_t a, int64_t M, int64_t s, int64_t b, std::string* err);
 
 enum Branch { kSeparable = 0, kTimeShear = 1, kFreqShear = 2, kMultiwindow = 3, kFir = 4, kShearOla = 5 };
-enum Algorithm { kAlgShear = 0, kAlgMultiwindow = 1, kAlgFir = 2, kAlgShearOla = 3 };
+enum Algorithm { kAlgShear = 0, kAlgMultiwindow = 1, kAlgFir = 2, kAlgShearOla = 3, kAlgAuto = 4 };
+
+// Automatic choice between the shear and the multiwindow algorithm: the
+// multiwindow plan when the shear factorisation needs a frequency shear and
+// the multiwindow lattice (lambda2 a, M) has p <= kAutoMaxP.
+constexpr int64_t kAutoMaxP = 15;
 
 struct Plan {
   // lattice

@@ -54,10 +54,12 @@ class Request:
 
 
 class GpuExecutor:
-    """Launches list-batched forward transforms through libdgtns."""
+    """Launches list-batched forward transforms through libdgtns.  Plans use
+    `algorithm` ("auto" by default: the shear algorithm, or the multiwindow
+    one for lattices whose shear needs a frequency shear)."""
 
     def __init__(self, window_fn: Callable[[Key], object], dtype=None, streams: int = 4, max_batch: int = 8,
-                 device=None):
+                 device=None, algorithm: str = "auto"):
         import torch
 
         from . import _binding as B
@@ -70,12 +72,13 @@ class GpuExecutor:
         self.plans: Dict[Key, object] = {}
         self.es = 8 if self.dtype == torch.complex64 else 16
         self.ws = [None] * streams          # per-slot workspace, grown as plans are added
+        self.algorithm = algorithm
 
     def plan(self, key: Key):
         p = self.plans.get(key)
         if p is None:
             from .api import Plan
-            p = Plan(*key, dtype=self.dtype, max_batch=self.max_batch, device=self.device)
+            p = Plan(*key, dtype=self.dtype, max_batch=self.max_batch, device=self.device, algorithm=self.algorithm)
             p.set_window(self.window_fn(key))
             need = self.B.dgtns_workspace_bytes(p._h, self.B.DGTNS_OP_FORWARD, self.max_batch)
             self.torch.cuda.synchronize(self.device)

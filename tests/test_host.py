@@ -444,3 +444,27 @@ def test_sequential_chunk_workspace(lib, monkeypatch):
             assert B.dgtns_workspace_bytes(h, B.DGTNS_OP_FORWARD, 16) >= 16 * per
         finally:
             B.dgtns_plan_destroy(h)
+
+
+def test_automatic_algorithm_choice(lib):
+    """DGTNS_ALG_AUTO keeps the shear plan unless it needs a frequency shear
+    and the multiwindow lattice (lambda2 a, M) has p <= 15: on the serving
+    lattices the six frequency-shear ones become multiwindow plans; on the
+    Fig. 2 lattices the choice follows the same rule."""
+    from dgt_inputs import crossover_lattices, serving_plans
+    nmw = 0
+    for lat in serving_plans() + crossover_lattices():
+        L, a, M, l1, l2 = lat
+        hs = B.dgtns_plan_create(*lat, 0, 1)
+        ha = B.dgtns_plan_create_alg(*lat, 0, 1, B.DGTNS_ALG_AUTO)
+        try:
+            s_branch = B.dgtns_plan_info(hs).branch
+            a_branch = B.dgtns_plan_info(ha).branch
+            pmw = l2 * a // math.gcd(l2 * a, M)
+            want_mw = s_branch == B.DGTNS_FREQ_SHEAR and pmw <= 15
+            assert a_branch == (B.DGTNS_MULTIWINDOW if want_mw else s_branch), (lat, s_branch, a_branch, pmw)
+            nmw += lat in serving_plans() and want_mw
+        finally:
+            B.dgtns_plan_destroy(hs)
+            B.dgtns_plan_destroy(ha)
+    assert nmw == 6
