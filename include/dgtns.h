@@ -339,10 +339,9 @@ int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, vo
  * optimal frame bounds (A, B); A == 0 means the system is not a frame and
  * gd_dev is then undefined (asynchronous calls cannot report
  * DGTNS_ENOTFRAME; callers check A).  Implemented for p <= 8 of the sheared
- * lattice (p x p blocks of the frame operator in the Zak domain), plans whose
- * columns fit one in-LDS transform (p d within 8192 values in FP32 or 4096 in
- * FP64, and 16 (d + p d) bytes within 160 KiB; longer columns run as two
- * passes) and shear-algorithm plans (DGTNS_EUNSUPPORTED otherwise).
+ * lattice (p x p blocks of the frame operator in the Zak domain) and
+ * shear-algorithm plans (DGTNS_EUNSUPPORTED otherwise); long columns
+ * (d = d1 d2) take the window Zak and its inverse in two passes.
  * Does not change the plan's window.  Workspace: DGTNS_OP_DUAL.
  */
 int dgtns_dual_window(dgtns_plan plan, const void* g_dev, void* gd_dev, double* bounds_dev,

@@ -155,8 +155,6 @@ int dual_body(const Plan& P, const double2* g, double2* out, double* bounds, cha
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are computed with shear-algorithm plans");
   if (P.pi > kDualMaxP)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p <= 8 of the sheared lattice");
-  if (P.longd)
-    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows need columns held by one in-LDS transform (this plan splits them in two passes)");
   return dual_c128(P, g, out, bounds, w, l, tight, st);
 }
 

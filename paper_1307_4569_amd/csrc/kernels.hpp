@@ -858,12 +858,14 @@ __global__ void __launch_bounds__(kThreads) k_dual_div(const double2* z, double2
 // (Section 4.2), and the optimal frame bounds are the extreme eigenvalues of
 // the blocks.  Each thread diagonalises one Hermitian block by cyclic Jacobi
 // rotations; eigenvalues that are not positive (no frame) contribute zero.
+// d2 != 0: the tables are those of the long factorisation (digit-reversed).
 // ----------------------------------------------------------------------------
 constexpr int kDualMaxP = 8;
 
 template <int PM>
 __global__ void __launch_bounds__(kThreads) k_dual_block(const double2* z, double2* zd, double* part, int Mi, int d,
-                                                        int p, int ai, int q, double scale_bounds, int tight) {
+                                                        int p, int ai, int q, double scale_bounds, int tight,
+                                                        int d2) {
   __shared__ double smin[kThreads], smax[kThreads];
   const long long tot = (long long)Mi * d;
   const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
@@ -876,8 +878,10 @@ __global__ void __launch_bounds__(kThreads) k_dual_block(const double2* z, doubl
         S[j][k] = make_double2(0, 0);
         V[j][k] = make_double2(j == k ? 1.0 : 0.0, 0);
       }
+    // tables of the long factorisation hold nu = k1 + d1 k2 at k1 d2 + k2
+    const int nut = d2 ? nu / d2 + (d / d2) * (nu % d2) : nu;
     double sw, cw;
-    sincospi(2.0 * nu / d, &sw, &cw);
+    sincospi(2.0 * nut / d, &sw, &cw);
     const double2 wrap = make_double2(cw, sw);
     // S = Mi d^2 A^H A = Mi sum_{n0} conj(a) a^T with a = d A(n0, .)
     for (int n0 = 0; n0 < q; ++n0) {

@@ -259,4 +259,39 @@ __global__ void __launch_bounds__(kThreads) k_long_zak(const double2* U, CO* zc,
   }
 }
 
+// Inverse window Zak of the long factorisation (FP64), first pass: with
+// nu = k1 + d1 k2 and t = t2 + d2 t1,
+//   x(r + Mi (j0 + p t)) = (1/d) sum_k1 exp(2 pi i k1 t1 / d1) V_k1(t2),
+//   V_k1(t2) = exp(2 pi i k1 t2 / d) sum_k2 Z_{r,j0}(nu) exp(2 pi i k2 t2 / d2).
+// This kernel forms V / d from the digit-reversed tables (one k1 and W
+// residues r per work-group) into U[k1][t2][r + Mi j0]; the length-d1 inverse
+// DFTs over k1 are a k_long_col pass.
+template <int Unused = 0>
+__global__ void __launch_bounds__(kThreads) k_long_zak_inv(const double2* z, double2* U, const double2* tw2,
+                                                           const double2* twd, int Mi, int p, int d, int d1,
+                                                           int d2, int W, int S, FftSched fs2) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* tw = reinterpret_cast<double2*>(smem_raw);
+  double2* xb = tw + d2;
+  const int ncol = Mi * p;
+  for (int e = threadIdx.x; e < d2; e += kThreads) tw[e] = tw2[e];
+  const int k1 = blockIdx.x % d1, r0 = (blockIdx.x / d1) * W;
+  for (int e = threadIdx.x; e < W * p * d2; e += kThreads) {
+    const int cc = e / (p * d2), rem = e - cc * (p * d2), j0 = rem / d2, k2 = rem - j0 * d2, r = r0 + cc;
+    xb[(cc * p + j0) * S + k2] =
+        r < Mi ? z[((long long)r * p + j0) * d + (long long)k1 * d2 + k2] : make_double2(0, 0);
+  }
+  __syncthreads();
+  fft_lds<double2, true, 8>(xb, S, fs2, W * p, tw);
+  const double inv_d = 1.0 / d;
+  double2* Ub = U + (long long)k1 * d2 * ncol;
+  for (int e = threadIdx.x; e < W * p * d2; e += kThreads) {
+    const int t2 = e / (W * p), rem = e - t2 * (W * p), j0 = rem / W, cc = rem - j0 * W, r = r0 + cc;
+    if (r < Mi) {
+      const double2 v = cmulc(xb[(cc * p + j0) * S + t2], twd[(long long)k1 * t2 % d]);
+      Ub[(long long)t2 * ncol + r + Mi * j0] = cscale(v, inv_d);
+    }
+  }
+}
+
 }  // namespace dgtns

@@ -332,6 +332,7 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
       l.F = take(16 * L);   // divided Zak
       l.G = take(16 * L);   // separable dual / frequency-domain dual
       if (fs) l.Y = take(16 * L);
+      if (P.longd) l.U = take(16 * L);   // between the two inverse column passes
       l.part = take(16 * (size_t(cdiv((long long)P.Mi * P.di, kThreads)) + 1));
       break;
     default:
@@ -1256,6 +1257,7 @@ inline int dual_impl(const Plan& P, const double2* g_dev, double2* gd_dev, doubl
   Layout lw;
   lw.Y = l.Y;
   lw.G = l.G;
+  lw.U = l.U;
   rc = window_zak<double2>(P, g_dev, nullptr, Z, w, lw, st);
   if (rc) return rc;
   const long long tot = P.Mi * P.di;
@@ -1267,28 +1269,62 @@ inline int dual_impl(const Plan& P, const double2* g_dev, double2* gd_dev, doubl
   else {
     auto kern = P.pi <= 2 ? k_dual_block<2> : P.pi <= 4 ? k_dual_block<4> : k_dual_block<kDualMaxP>;
     rc = launch_raw(kern, dim3(nb), dim3(kThreads), 0, st, "dual block inversion", (const double2*)Z, Zd, part,
-                    int(P.Mi), int(P.di), int(P.pi), int(P.ai), int(P.qi), sb, tight ? 1 : 0);
+                    int(P.Mi), int(P.di), int(P.pi), int(P.ai), int(P.qi), sb, tight ? 1 : 0,
+                    P.longd ? int(P.d2) : 0);
   }
   if (rc) return rc;
   rc = launch_raw(k_minmax_final<>, dim3(1), dim3(kThreads), 0, st, "frame bounds", (const double*)part, int(nb),
                   bounds_dev);
   if (rc) return rc;
-  ZakInvArgs Zi;
-  Zi.z = Zd;
-  Zi.twd = tab<double2>(P, P.off.tw_d64);
-  Zi.Mi = int(P.Mi); Zi.d = int(P.di); Zi.p = int(P.pi); Zi.Sd = int(P.di | 1);
-  Zi.W = block_width(P.pi * Zi.Sd, 16);
-  Zi.fd = sched(P.fd);
-  size_t lds = 16 * (P.di + size_t(Zi.W) * P.pi * Zi.Sd);
-  if (P.branch != kFreqShear) {
-    Zi.chirp = P.branch == kSeparable ? no_chirp<double2>(P) : chirp_fly(P, P.sh.s1, 1);
-    Zi.x = gd_dev;
-    return launch(k_zak_inv<>, dim3(cdiv(P.Mi, Zi.W), 1), lds, st, Zi, "inverse Zak");
+  const ChirpSrc<double2> post = P.branch == kFreqShear ? no_chirp<double2>(P)
+                                 : P.branch == kSeparable ? no_chirp<double2>(P)
+                                                          : chirp_fly(P, P.sh.s1, 1);
+  double2* xout = P.branch == kFreqShear ? Gd : gd_dev;
+  if (P.longd) {
+    // two-level inverse Zak: length-d2 inverse DFTs of the digit-reversed
+    // tables with the twiddles and 1/d, then the length-d1 inverse DFTs
+    double2* U = reinterpret_cast<double2*>(w + l.U);
+    const int S = int(P.d2 | 1);
+    int W = 16;
+    while (W > 1 && (W * P.pi * P.d2 > 4096 || 16 * (P.d2 + size_t(W) * P.pi * S) > (64u << 10))) --W;
+    const size_t zl = 16 * (P.d2 + size_t(W) * P.pi * S);
+    if (zl > 160 * 1024) return fail(DGTNS_EUNSUPPORTED, "inverse Zak: LDS request above 160 KiB");
+    if (zl > 64 * 1024 && !dry_run()) {
+      rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_long_zak_inv<>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(zl)),
+                     "inverse Zak");
+      if (rc) return rc;
+    }
+    rc = launch_raw(k_long_zak_inv<>, dim3(unsigned(P.d1) * cdiv(P.Mi, W)), dim3(kThreads), zl, st,
+                    "inverse Zak, middle pass", (const double2*)Zd, U, tab<double2>(P, P.off.tw_d2_64),
+                    tab<double2>(P, P.off.tw_d64), int(P.Mi), int(P.pi), int(P.di), int(P.d1), int(P.d2), W, S,
+                    sched(P.fd2));
+    if (rc) return rc;
+    LongColArgs<double2> A;
+    std::memset(&A, 0, sizeof(A));
+    A.x = U; A.pre = no_chirp<double2>(P); A.post = post;
+    A.y = xout; A.ys = P.L;
+    A.tws = tab<double2>(P, P.off.tw_d1_64); A.twd = tab<double2>(P, P.off.tw_d64);
+    A.n = int(P.d1); A.Sn = int(P.d1 | 1); A.W = block_width(A.Sn, 16);
+    A.ncols = int(P.d2 * P.Mi * P.pi); A.inmode = 0; A.outmode = 2; A.twmode = 0;
+    A.d = int(P.di); A.d2 = int(P.d2); A.fs = sched(P.fd1);
+    rc = launch(k_long_col<double2, true>, dim3(cdiv(A.ncols, A.W), 1, 1), 16 * (P.d1 + size_t(A.W) * A.Sn), st,
+                A, "inverse Zak, last column pass");
+    if (rc) return rc;
+  } else {
+    ZakInvArgs Zi;
+    Zi.z = Zd;
+    Zi.twd = tab<double2>(P, P.off.tw_d64);
+    Zi.Mi = int(P.Mi); Zi.d = int(P.di); Zi.p = int(P.pi); Zi.Sd = int(P.di | 1);
+    Zi.W = block_width(P.pi * Zi.Sd, 16);
+    Zi.fd = sched(P.fd);
+    const size_t lds = 16 * (P.di + size_t(Zi.W) * P.pi * Zi.Sd);
+    Zi.chirp = post;
+    Zi.x = xout;
+    rc = launch(k_zak_inv<>, dim3(cdiv(P.Mi, Zi.W), 1), lds, st, Zi, "inverse Zak");
+    if (rc) return rc;
   }
-  Zi.chirp = no_chirp<double2>(P);
-  Zi.x = Gd;
-  rc = launch(k_zak_inv<>, dim3(cdiv(P.Mi, Zi.W), 1), lds, st, Zi, "inverse Zak");
-  if (rc) return rc;
+  if (P.branch != kFreqShear) return DGTNS_OK;
   // g_d = conj(p1) IFFT(conj(p0) dual_sep(G))  (Alg. 2 with the time shear undone)
   double2* Y = reinterpret_cast<double2*>(w + l.Y);
   return run_four_step<double2>(P, Gd, 0, Y, gd_dev, 1, true, chirp_fly(P, -P.sh.s0, 1),

@@ -105,7 +105,56 @@ def test_long_columns_list_batch_and_refusals():
                            torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     assert torch.equal(out, c)
-    for fn in (lambda: plan.dual(g), lambda: plan.tight(g), lambda: plan.window_grad(f, c)):
-        with pytest.raises(Bb.DgtnsError) as e:
-            fn()
-        assert e.value.status == Bb.DGTNS_EUNSUPPORTED
+    with pytest.raises(Bb.DgtnsError) as e:
+        plan.window_grad(f, c)
+    assert e.value.status == Bb.DGTNS_EUNSUPPORTED
+
+
+# (lattice, plan dtype, branch, p): FP64 plans with p = 3 split p d = 5040 in
+# two passes; Fig. 2's first shape has d = 20160 in both precisions
+DUAL_LONG = [((20160, 3, 4, 1, 2), torch.complex128, 1, 3), ((20160, 12, 16, 1, 4), torch.complex128, 2, 3),
+             ((20160, 3, 4, 0, 1), torch.complex128, 0, 3), ((161280, 32, 64, 1, 2), torch.complex64, 2, 1)]
+
+
+@pytest.mark.parametrize("case", DUAL_LONG, ids=lambda c: "-".join(map(str, c[0])))
+def test_long_columns_dual_and_tight(case):
+    """Canonical dual and tight windows with the window Zak and its inverse
+    in two passes (Alg. 2 on long columns): S g_d = g and S_gt = I at sampled
+    points through the oracle's Walnut form, the frame bounds of both calls
+    agree, and they bracket S's Rayleigh quotient on the dual window."""
+    from paper_1307_4569_amd import Plan
+    lat, dtype, branch, p = case
+    L, a, M, l1, l2 = lat
+    plan = Plan(*lat, dtype=dtype, max_batch=1)
+    assert plan.branch == branch and plan.info.p == p and plan.info.d * p > 4096
+    g = gaussian_window(L, a, M) + 0.05j * complex_normal(L, 12)
+    gd, bd = plan.dual(torch.tensor(g))
+    gt, bt = plan.tight(torch.tensor(g))
+    gd, gt = gd.cpu().numpy(), gt.cpu().numpy()
+    bd, bt = bd.cpu().numpy(), bt.cpu().numpy()
+    assert 0 < bd[0] <= bd[1] and np.allclose(bd, bt, rtol=1e-12)
+    pts = np.concatenate([np.linspace(0, L - 1, 3).astype(np.int64), [1, L // 2 + 3]])
+    es = rel(oracle.frame_operator_apply(gd, g, a, M, l1, l2, pts), g[pts])
+    x = complex_normal(L, 13)
+    et = rel(oracle.frame_operator_apply(x, gt, a, M, l1, l2, pts), x[pts])
+    print("long dual/tight", lat, "S g_d = g", es, "S_gt = I", et, "bounds", bd)
+    assert es < 1e-11 and et < 1e-11
+
+
+def test_long_dual_matches_the_one_pass_path():
+    """The lattice L = 20160, a = 3, M = 4, lambda = 1/2 has p d = 5040: the
+    FP64 plan takes the two-pass Zak, the FP32 plan the in-LDS one (both
+    compute the window in FP64), so the two dual and tight windows and
+    frame bounds agree to FP64 rounding."""
+    from paper_1307_4569_amd import Plan
+    lat = (20160, 3, 4, 1, 2)
+    L, a, M, _, _ = lat
+    g = torch.tensor(gaussian_window(L, a, M) + 0.05j * complex_normal(L, 14))
+    p64 = Plan(*lat, dtype=torch.complex128, max_batch=1)
+    p32 = Plan(*lat, dtype=torch.complex64, max_batch=1)
+    for fn in ("dual", "tight"):
+        w64, b64 = getattr(p64, fn)(g)
+        w32, b32 = getattr(p32, fn)(g)
+        e = rel(w64.cpu().numpy(), w32.cpu().numpy())
+        print(fn, "two-pass against in-LDS", e)
+        assert e < 1e-12 and np.allclose(b64.cpu().numpy(), b32.cpu().numpy(), rtol=1e-12)
