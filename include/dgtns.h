@@ -324,8 +324,8 @@ int dgtns_adjoint(dgtns_plan plan, const void* c_dev, void* f_dev, int64_t B, vo
  * respect to the coefficients (convention dLoss/dRe + i dLoss/dIm), writes
  * gg_dev[L] (plan dtype) with gg(j) = sum_k sum_n f_k(j + n a) conj(y_{k,n}(j + n a)),
  * y_{k,n}(l) = sum_m gc_k(m, n) exp(2 pi i l (m + w(n)) / M).
- * Deterministic (no atomics).  Implemented for shear-algorithm plans (any p)
- * whose columns fit one in-LDS transform (DGTNS_EUNSUPPORTED otherwise).
+ * Deterministic (no atomics).  Implemented for shear-algorithm plans (any p,
+ * long columns d = d1 d2 included; DGTNS_EUNSUPPORTED otherwise).
  * Workspace: DGTNS_OP_WINDOW_GRAD.
  */
 int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, void* gg_dev,

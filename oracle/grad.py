@@ -26,9 +26,10 @@ def spectrogram_loss(c, T):
     return float(np.sum(p * p)), 4.0 * p * c
 
 
-def window_gradient(f, G, a, M, lam1, lam2):
+def window_gradient(f, G, a, M, lam1, lam2, points=None):
     """grad_g(j) = sum_n f(j + n a) conj(y_n(j + n a)) for a coefficient
-    gradient G given as G[n, m]."""
+    gradient G given as G[n, m]; at the time positions ``points`` only if
+    given (each position then costs N M instead of the whole L N)."""
     f = np.asarray(f, dtype=np.complex128)
     G = np.asarray(G, dtype=np.complex128)
     L = f.shape[-1]
@@ -37,6 +38,14 @@ def window_gradient(f, G, a, M, lam1, lam2):
     b = L // M
     K = M * lam2
     off = offsets(N, lam1, lam2)
+    if points is not None:
+        # y_n(l) = Y[n, l mod M] exp(2 pi i l w(n)), Y = M ifft(G[n]) (period M in l)
+        j = np.asarray(points, dtype=np.int64)
+        n = np.arange(N, dtype=np.int64)
+        Y = M * np.fft.ifft(G, axis=1)
+        ln = (j[:, None] + n[None, :] * a) % L
+        y = Y[n[None, :], ln % M] * _unit_root(ln * off[None, :], K, +1)
+        return np.sum(f[ln] * np.conj(y), axis=1)
     l = np.arange(L, dtype=np.int64)
     mods = [_unit_root(l * o, K, +1) for o in range(lam2)]
     gg = np.zeros(L, dtype=np.complex128)

@@ -294,4 +294,80 @@ __global__ void __launch_bounds__(kThreads) k_long_zak_inv(const double2* z, dou
   }
 }
 
+// ----------------------------------------------------------------------------
+// Middle pass of the window gradient (long columns).  grid (d1 ceil(Mp / W),
+// B), Mp = Mi p window columns; block x = ub d1 + k1 handles the window
+// columns u0 = ub W ... of spectral row k1.  For each n0 the signal column
+// w = (u + n0 ai) mod Mp (first column pass in U) and the column (n0, w mod Mi)
+// of h (first pass of the adjoint in V) are transformed over their second
+// digit, and
+//   acc(nu) += X_w(nu) conj(Y(nu)) exp(2 pi i k nu / d),  k = (u + n0 ai) div Mp,
+// nu = k1 + d1 k2 (the window's Zak columns wrap into the next period); then
+// the length-d2 inverse DFTs with the twiddle exp(2 pi i k1 t2 / d) and 1/d
+// into G[k1][t2][u] (per signal [d1][d2 Mp]); a length-d1 inverse column pass
+// finishes the gradient's polyphase columns.
+// ----------------------------------------------------------------------------
+template <typename C> struct LongGradArgs {
+  const C* U;   // per signal [d1][d2 Mp]
+  long long us;
+  const C* V;   // per signal [q][d1][Mi d2]
+  long long vs;
+  C* G;         // per signal [d1][d2 Mp]
+  long long gs;
+  const C* twd;
+  const C* tw2;
+  int Mi, ai, p, q, d, d1, d2, W, Sd2;
+  FftSched fs2;
+};
+
+template <typename C>
+__global__ void __launch_bounds__(kThreads) k_long_mid_grad(LongGradArgs<C> A) {
+  using T = decltype(C::x);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tw = reinterpret_cast<C*>(smem_raw);
+  const int d1 = A.d1, d2 = A.d2, d = A.d, W = A.W, S = A.Sd2, Mi = A.Mi, Mp = A.Mi * A.p;
+  C* xb = tw + d2;       // [W][S] signal spectra
+  C* yb = xb + W * S;    // [W][S] spectra of h
+  C* acc = yb + W * S;   // [W][S]
+  for (int e = threadIdx.x; e < d2; e += kThreads) tw[e] = A.tw2[e];
+  for (int e = threadIdx.x; e < W * S; e += kThreads) acc[e] = czero<C>();
+  const int k1 = blockIdx.x % d1, u0 = (blockIdx.x / d1) * W;
+  const long long bo = blockIdx.y;
+  const C* Ub = A.U + bo * A.us + (long long)k1 * d2 * Mp;
+  for (int n0 = 0; n0 < A.q; ++n0) {
+    const C* Vb = A.V + bo * A.vs + ((long long)n0 * d1 + k1) * Mi * d2;
+    __syncthreads();
+    for (int e = threadIdx.x; e < W * d2; e += kThreads) {
+      const int cc = e / d2, t = e - cc * d2, u = u0 + cc;
+      C x = czero<C>(), y = czero<C>();
+      if (u < Mp) {
+        const int w = int((u + (long long)n0 * A.ai) % Mp);
+        x = Ub[(long long)t * Mp + w];
+        y = Vb[(long long)(w % Mi) * d2 + t];
+      }
+      xb[cc * S + t] = x;
+      yb[cc * S + t] = y;
+    }
+    __syncthreads();
+    fft_lds<C, false>(xb, S, A.fs2, 2 * W, tw);
+    for (int e = threadIdx.x; e < W * d2; e += kThreads) {
+      const int cc = e / d2, k2 = e - cc * d2, u = u0 + cc;
+      if (u < Mp) {
+        C pr = cmulc(xb[cc * S + k2], yb[cc * S + k2]);
+        const long long k = (u + (long long)n0 * A.ai) / Mp;
+        if (k) pr = cmulc(pr, A.twd[(k * (k1 + (long long)d1 * k2)) % d]);
+        acc[cc * S + k2] = cadd(acc[cc * S + k2], pr);
+      }
+    }
+  }
+  __syncthreads();
+  fft_lds<C, true>(acc, S, A.fs2, W, tw);
+  const T inv_d = T(1) / T(d);
+  C* Gb = A.G + bo * A.gs + (long long)k1 * d2 * Mp;
+  for (int e = threadIdx.x; e < W * d2; e += kThreads) {
+    const int t2 = e / W, cc = e - t2 * W, u = u0 + cc;
+    if (u < Mp) Gb[(long long)t2 * Mp + u] = cscale(cmulc(acc[cc * S + t2], A.twd[((long long)t2 * k1) % d]), inv_d);
+  }
+}
+
 }  // namespace dgtns

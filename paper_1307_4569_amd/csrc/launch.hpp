@@ -320,7 +320,8 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
     case DGTNS_OP_WINDOW_GRAD:
       l.H = take(es * MN * B);
       l.part = take(es * L * B);
-      l.U = take(es * L * B);   // column spectra of the wave-kernel path
+      l.U = take(es * L * B);   // column spectra of the wave-kernel path, or first column pass
+      if (P.longd) l.V = take(es * MN * B);   // first column pass of h (long columns)
       if (fs) { l.F = take(es * L * B); l.Y = take(es * L * B); l.G = take(es * L); }
       break;
     case DGTNS_OP_SET_WINDOW:
@@ -1108,13 +1109,54 @@ int run_grad_cols_generic(const Plan& P, const void* x, ChirpSrc<C> ch, const C*
   return launch(k_grad_cols<C, true>, grid, lcols, st, A, "window gradient");
 }
 
+// Window gradient columns with long columns (d = d1 d2): the first column
+// pass of the signal (as the forward's) into U and of h (as the adjoint's)
+// into V, the middle pass into part, then the length-d1 inverse DFTs in place.
+template <typename C>
+int run_grad_cols_long(const Plan& P, const void* x, ChirpSrc<C> ch, const C* H, C* U, C* V, C* part, long long B,
+                       hipStream_t st) {
+  const long long Mp = P.Mi * P.pi, Md = P.Mi * P.di;
+  const size_t es = sizeof(C);
+  LongColArgs<C> A = long_col_args<C>(P);
+  A.x = x; A.xs = P.L; A.pre = ch;
+  A.y = U; A.ys = P.L;
+  A.ncols = int(P.d2 * Mp); A.inmode = 0; A.outmode = 0; A.twmode = 1; A.tdiv = int(Mp);
+  int rc = launch(k_long_col<C, false>, dim3(cdiv(A.ncols, A.W), unsigned(B), 1), es * (P.d1 + size_t(A.W) * A.Sn),
+                  st, A, "window gradient, signal column pass");
+  if (rc) return rc;
+  LongColArgs<C> A1 = long_col_args<C>(P);
+  A1.x = H; A1.xs = h_per_signal(P); A1.xz = Md;
+  A1.y = V; A1.ys = h_per_signal(P); A1.yz = Md;
+  A1.ncols = int(P.Mi * P.d2); A1.inmode = 1; A1.outmode = 0; A1.twmode = 2; A1.tdiv = int(P.d2);
+  rc = launch(k_long_col<C, false>, dim3(cdiv(A1.ncols, A1.W), unsigned(B), unsigned(P.qi)),
+              es * (P.d1 + size_t(A1.W) * A1.Sn), st, A1, "window gradient, h column pass");
+  if (rc) return rc;
+  LongGradArgs<C> G;
+  G.U = U; G.us = P.L; G.V = V; G.vs = h_per_signal(P); G.G = part; G.gs = P.L;
+  G.twd = tab<C>(P, P.off.tw_d); G.tw2 = tab<C>(P, P.off.tw_d2);
+  G.Mi = int(P.Mi); G.ai = int(P.ai); G.p = int(P.pi); G.q = int(P.qi);
+  G.d = int(P.di); G.d1 = int(P.d1); G.d2 = int(P.d2); G.Sd2 = int(P.d2 | 1);
+  G.fs2 = sched(P.fd2);
+  const long long budget = MaxE<C>::value * kThreads;
+  int W = 16;
+  while (W > 1 && (2 * W * P.d2 > budget || es * (P.d2 + 3 * size_t(W) * G.Sd2) > (64u << 10))) --W;
+  G.W = W;
+  rc = launch(k_long_mid_grad<C>, dim3(unsigned(P.d1) * cdiv(Mp, W), unsigned(B)),
+              es * (P.d2 + 3 * size_t(W) * G.Sd2), st, G, "window gradient, middle pass");
+  if (rc) return rc;
+  LongColArgs<C> A3 = long_col_args<C>(P);
+  A3.x = part; A3.xs = P.L;
+  A3.y = part; A3.ys = P.L;
+  A3.ncols = int(P.d2 * Mp); A3.inmode = 0; A3.outmode = 0; A3.twmode = 0;
+  return launch(k_long_col<C, true>, dim3(cdiv(A3.ncols, A3.W), unsigned(B), 1), es * (P.d1 + size_t(A3.W) * A3.Sn),
+                st, A3, "window gradient, last column pass");
+}
+
 template <typename C>
 int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* ws, const Layout& l,
               hipStream_t st) {
   if (P.branch == kMultiwindow || P.branch == kFir)
     return fail(DGTNS_EUNSUPPORTED, "the window gradient is implemented for shear-algorithm plans only");
-  if (P.longd)
-    return fail(DGTNS_EUNSUPPORTED, "the window gradient needs columns held by one in-LDS transform (this plan splits them in two passes)");
   C* H = reinterpret_cast<C*>(ws + l.H);
   C* part = reinterpret_cast<C*>(ws + l.part);
   int rc = run_rows<C>(P, H, const_cast<C*>(gc), B, true, st);
@@ -1133,7 +1175,10 @@ int grad_impl(const Plan& P, const C* f, const C* gc, C* gg, long long B, char* 
     ch = no_chirp<C>(P);
   }
   const bool wave = P.pi == 1 && !P.generic && wave_len(P.di) && P.di <= 512;
-  if (wave) {
+  if (P.longd) {
+    rc = run_grad_cols_long<C>(P, x, ch, H, reinterpret_cast<C*>(ws + l.U), reinterpret_cast<C*>(ws + l.V), part,
+                               B, st);
+  } else if (wave) {
     rc = run_grad_cols_fast<C>(P, x, ch, H, reinterpret_cast<C*>(ws + l.U), part, B, st);
   } else {
     rc = run_grad_cols_generic<C>(P, x, ch, H, part, B, st);

@@ -85,7 +85,7 @@ def test_fig2_frequency_shear_lattice():
     assert max(errs) < 1e-5 and abs(lhs - rhs) <= 1e-4 * abs(lhs)
 
 
-def test_long_columns_list_batch_and_refusals():
+def test_long_columns_list_batch():
     from paper_1307_4569_amd import Plan
     from paper_1307_4569_amd import _binding as Bb
     lat = (20160, 3, 6, 1, 3)
@@ -105,9 +105,39 @@ def test_long_columns_list_batch_and_refusals():
                            torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     assert torch.equal(out, c)
-    with pytest.raises(Bb.DgtnsError) as e:
-        plan.window_grad(f, c)
-    assert e.value.status == Bb.DGTNS_EUNSUPPORTED
+
+
+# (lattice, branch, p, dtype): the long-column lattices of the forward tests
+# in the precisions whose plans split the columns (FP32 plans hold p d = 5040
+# in one transform)
+GRAD_LONG = [((20160, 2, 4, 0, 1), 0, 1, torch.complex128), ((20160, 2, 4, 0, 1), 0, 1, torch.complex64),
+             ((20160, 3, 4, 1, 2), 1, 3, torch.complex128), ((20160, 3, 6, 1, 3), 2, 1, torch.complex128),
+             ((20160, 3, 6, 1, 3), 2, 1, torch.complex64), ((20160, 12, 16, 1, 4), 2, 3, torch.complex128)]
+
+
+@pytest.mark.parametrize("case", GRAD_LONG, ids=lambda c: "-".join(map(str, c[0])) + "-" + str(c[3])[-3:])
+def test_long_columns_window_gradient(case):
+    """Window gradient with the column transforms in two passes, summed over
+    a batch of 2, against the oracle's gradient (eq. (DGT) differentiated in
+    the window)."""
+    from paper_1307_4569_amd import Plan
+    lat, branch, p, dtype = case
+    L, a, M, l1, l2 = lat
+    N = L // a
+    single = dtype == torch.complex64
+    B = 2
+    plan = Plan(*lat, dtype=dtype, max_batch=B)
+    assert plan.branch == branch and plan.info.p == p
+    assert plan.info.d > 4096 or p * plan.info.d > (8192 if single else 4096)
+    g = round_to(complex_normal(L, 31), single)
+    f = round_to(np.stack([complex_normal(L, 32 + k) for k in range(B)]), single)
+    G = round_to(np.stack([complex_normal(N * M, 34 + k).reshape(N, M) for k in range(B)]), single)
+    plan.set_window(torch.tensor(g))
+    gg = plan.window_grad(torch.tensor(f), torch.tensor(G)).cpu().numpy()
+    ref = sum(oracle.window_gradient(f[k], G[k], a, M, l1, l2) for k in range(B))
+    e = rel(gg, ref)
+    print("long window gradient", lat, dtype, "d", plan.info.d, e)
+    assert e < TOL[dtype]
 
 
 # (lattice, plan dtype, branch, p): FP64 plans with p = 3 split p d = 5040 in
@@ -158,3 +188,26 @@ def test_long_dual_matches_the_one_pass_path():
         e = rel(w64.cpu().numpy(), w32.cpu().numpy())
         print(fn, "two-pass against in-LDS", e)
         assert e < 1e-12 and np.allclose(b64.cpu().numpy(), b32.cpu().numpy(), rtol=1e-12)
+
+
+def test_fig2_lattice_window_gradient():
+    """Window gradient on Fig. 2's first shape (L = 161280, a = 32, M = 64,
+    lambda = 1/2, columns of d = 20160 in two passes), FP32 batch of 4:
+    sampled time positions against the oracle, summed over the batch."""
+    from paper_1307_4569_amd import Plan
+    lat = (161280, 32, 64, 1, 2)
+    L, a, M, l1, l2 = lat
+    N = L // a
+    B = 4
+    plan = Plan(*lat, dtype=torch.complex64, max_batch=B)
+    assert plan.info.d == 20160
+    g = round_to(gaussian_window(L, a, M), True)
+    f = round_to(complex_normal_batch(B, L, 41), True)
+    G = round_to(complex_normal_batch(B, N * M, 42).reshape(B, N, M), True)
+    plan.set_window(torch.tensor(g))
+    gg = plan.window_grad(torch.tensor(f), torch.tensor(G)).cpu().numpy()
+    pts = np.concatenate([np.arange(0, L, 9973), [L - 1]])
+    ref = sum(oracle.window_gradient(f[k], G[k], a, M, l1, l2, points=pts) for k in range(B))
+    e = rel(gg[pts], ref)
+    print("fig2 window gradient", e)
+    assert e < 1e-5

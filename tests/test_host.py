@@ -319,7 +319,6 @@ REFUSALS = [
     (("mw", 144, 6, 12, 1, 2, 0, 2), B.DGTNS_OP_WINDOW_GRAD, "shear-algorithm plans"),
     (("mw", 144, 6, 12, 1, 2, 0, 2), B.DGTNS_OP_DUAL, "shear-algorithm plans"),
     (("shear", 180, 9, 10, 0, 1, 0, 2), B.DGTNS_OP_DUAL, "p <= 8"),                    # p = 9
-    (("shear", 161280, 32, 64, 1, 2, 0, 2), B.DGTNS_OP_WINDOW_GRAD, "two passes"),     # d = 20160
 ]
 
 

@@ -301,6 +301,20 @@ def test_gradients_finite_differences(lat):
         assert abs(fd - np.vdot(gg, d).real) < 1e-6 * max(1.0, abs(fd))
 
 
+@pytest.mark.parametrize("lat", [(36, 6, 6, 1, 2), (72, 6, 4, 1, 3), (64, 4, 8, 1, 4), (48, 4, 6, 0, 1)])
+def test_window_gradient_at_points_matches_the_whole_gradient(lat):
+    """The sampled form of the window gradient (used at sizes where the
+    whole one is too slow) agrees with the whole gradient, which the finite
+    differences and the dense-atom autograd pin."""
+    L, a, M, l1, l2 = lat
+    f = rand_c(L)
+    G = rand_c(L // a * M).reshape(L // a, M)
+    whole = oracle.window_gradient(f, G, a, M, l1, l2)
+    pts = np.array([0, 1, L // 3, L - 1], dtype=np.int64)
+    assert rel(oracle.window_gradient(f, G, a, M, l1, l2, points=pts), whole[pts]) < 1e-13
+    assert rel(oracle.window_gradient(f, G, a, M, l1, l2, points=np.arange(L)), whole) < 1e-13
+
+
 def test_gradients_match_torch_autograd_on_dense_atoms():
     torch = pytest.importorskip("torch")
     L, a, M, l1, l2 = 36, 6, 6, 1, 3
