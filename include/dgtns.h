@@ -338,7 +338,7 @@ int dgtns_window_grad(dgtns_plan plan, const void* f_dev, const void* gc_dev, vo
  * gd_dev: complex128[L].  bounds_dev: 2 doubles on the device receiving the
  * optimal frame bounds (A, B); A == 0 means the system is not a frame and
  * gd_dev is then undefined (asynchronous calls cannot report
- * DGTNS_ENOTFRAME; callers check A).  Implemented for p <= 8 of the sheared
+ * DGTNS_ENOTFRAME; callers check A).  Implemented for p <= 64 of the sheared
  * lattice (p x p blocks of the frame operator in the Zak domain) and
  * shear-algorithm plans (DGTNS_EUNSUPPORTED otherwise); long columns
  * (d = d1 d2) take the window Zak and its inverse in two passes.

@@ -153,8 +153,8 @@ int dual_body(const Plan& P, const double2* g, double2* out, double* bounds, cha
               hipStream_t st) {
   if (P.branch == kMultiwindow || P.branch == kFir || P.branch == kShearOla)
     return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are computed with shear-algorithm plans");
-  if (P.pi > kDualMaxP)
-    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p <= 8 of the sheared lattice");
+  if (P.pi > kDualLdsMaxP)
+    return fail(DGTNS_EUNSUPPORTED, "dual and tight windows are implemented for p <= 64 of the sheared lattice");
   return dual_c128(P, g, out, bounds, w, l, tight, st);
 }
 

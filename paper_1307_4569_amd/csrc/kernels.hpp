@@ -984,6 +984,163 @@ __global__ void __launch_bounds__(kThreads) k_dual_block(const double2* z, doubl
   }
 }
 
+// ----------------------------------------------------------------------------
+// The same dual and tight windows for 8 < p <= kDualLdsMaxP: one wavefront per
+// (r, nu) block (grid-stride over the blocks), the Hermitian block S and its
+// eigenvectors V in LDS.  The cyclic Jacobi rotations are those of
+// k_dual_block; each one changes two columns, then two rows, of S (and two
+// columns of V), and lane m updates the entries of row (column) m, so the
+// lanes apply one rotation together.  part receives one (min, max) pair per
+// work-group.
+// ----------------------------------------------------------------------------
+constexpr int kDualLdsMaxP = 64;
+constexpr int kDualLdsGroups = 8192;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int Unused = 0>
+__global__ void __launch_bounds__(64) k_dual_block_lds(const double2* z, double2* zd, double* part, int Mi, int d,
+                                                       int p, int ai, int q, double scale_bounds, int tight,
+                                                       int d2) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* S = reinterpret_cast<double2*>(smem_raw);   // [p][p]
+  double2* V = S + p * p;                               // [p][p]
+  __shared__ double2 vec[kDualLdsMaxP];
+  __shared__ double2 rot[2];                            // (c, s), e
+  const int m = threadIdx.x;
+  const long long tot = (long long)Mi * d;
+  double mn = 1e308, mx = 0;
+  for (long long i = blockIdx.x; i < tot; i += gridDim.x) {
+    const int r = int(i / d), nu = int(i - (long long)r * d);
+    const int nut = d2 ? nu / d2 + (d / d2) * (nu % d2) : nu;
+    double sw, cw;
+    sincospi(2.0 * nut / d, &sw, &cw);
+    const double2 wrap = make_double2(cw, sw);
+    __syncthreads();
+    for (int e = m; e < p * p; e += 64) {
+      S[e] = make_double2(0, 0);
+      V[e] = make_double2(e / p == e % p ? 1.0 : 0.0, 0);
+    }
+    // S = Mi sum_{n0} conj(a) a^T with a = d A(n0, .); lane m owns row m
+    for (int n0 = 0; n0 < q; ++n0) {
+      __syncthreads();
+      if (m < p) {
+        const long long v = r - (long long)n0 * ai + (long long)Mi * m;
+        long long u = v % Mi;
+        if (u < 0) u += Mi;
+        const long long j1 = (v - u) / Mi;
+        const long long jp = ((j1 % p) + p) % p;
+        double2 t = z[(u * p + jp) * d + nu];
+        t.y = -t.y;
+        if (j1 < 0) t = cmul(t, wrap);
+        vec[m] = t;
+      }
+      __syncthreads();
+      if (m < p) {
+        const double2 a = vec[m];
+        for (int k = 0; k < p; ++k) {
+          const double2 b = vec[k];
+          double2& sk = S[m * p + k];
+          sk.x += Mi * (a.x * b.x + a.y * b.y);
+          sk.y += Mi * (a.x * b.y - a.y * b.x);
+        }
+      }
+    }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      __syncthreads();
+      double off = 0, dia = 0;
+      if (m < p) {
+        dia = S[m * p + m].x * S[m * p + m].x;
+        for (int k = m + 1; k < p; ++k) off += S[m * p + k].x * S[m * p + k].x + S[m * p + k].y * S[m * p + k].y;
+      }
+      off = wave_sum(off);
+      dia = wave_sum(dia);
+      if (off <= 1e-32 * dia) break;
+      for (int j = 0; j < p - 1; ++j)
+        for (int k = j + 1; k < p; ++k) {
+          __syncthreads();
+          if (m == 0) {
+            const double2 h = S[j * p + k];
+            const double ah = hypot(h.x, h.y);
+            double c = 1, sn = 0;
+            double2 e = make_double2(1, 0);
+            if (ah != 0) {
+              e = make_double2(h.x / ah, h.y / ah);
+              const double tau = (S[k * p + k].x - S[j * p + j].x) / (2 * ah);
+              const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1 + tau * tau));
+              c = 1 / sqrt(1 + t * t);
+              sn = t * c;
+            }
+            rot[0] = make_double2(c, sn);
+            rot[1] = ah != 0 ? e : make_double2(0, 0);
+          }
+          __syncthreads();
+          const double2 e = rot[1];
+          if (e.x == 0 && e.y == 0) continue;   // uniform: S[j][k] is already zero
+          const double c = rot[0].x, sn = rot[0].y;
+          const double2 ec = make_double2(e.x, -e.y);
+          if (m < p) {   // columns j, k of S and V
+            const double2 x = S[m * p + j], y = cmul(S[m * p + k], ec);
+            S[m * p + j] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+            S[m * p + k] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+            const double2 vx = V[m * p + j], vy = cmul(V[m * p + k], ec);
+            V[m * p + j] = make_double2(c * vx.x - sn * vy.x, c * vx.y - sn * vy.y);
+            V[m * p + k] = make_double2(sn * vx.x + c * vy.x, sn * vx.y + c * vy.y);
+          }
+          __syncthreads();
+          if (m < p) {   // rows j, k of S
+            const double2 x = S[j * p + m], y = cmul(S[k * p + m], e);
+            S[j * p + m] = make_double2(c * x.x - sn * y.x, c * x.y - sn * y.y);
+            S[k * p + m] = make_double2(sn * x.x + c * y.x, sn * x.y + c * y.y);
+          }
+          __syncthreads();
+          if (m == 0) {
+            S[j * p + k] = make_double2(0, 0);
+            S[k * p + j] = make_double2(0, 0);
+            S[j * p + j].y = 0;
+            S[k * p + k].y = 0;
+          }
+        }
+    }
+    __syncthreads();
+    // out = V diag(lambda^-1 or lambda^-1/2) V^H Zg(r, ., nu)
+    if (m < p) {
+      double2 acc = make_double2(0, 0);
+      for (int j = 0; j < p; ++j) {
+        const double2 vj = V[j * p + m], g = z[((long long)r * p + j) * d + nu];
+        acc.x += vj.x * g.x + vj.y * g.y;
+        acc.y += vj.x * g.y - vj.y * g.x;
+      }
+      const double lam = S[m * p + m].x;
+      mn = fmin(mn, fmax(lam, 0.0) * scale_bounds);
+      mx = fmax(mx, lam * scale_bounds);
+      const double f = lam > 0 ? (tight ? 1 / sqrt(lam) : 1 / lam) : 0.0;
+      vec[m] = cscale(acc, f);
+    }
+    __syncthreads();
+    if (m < p) {
+      double2 acc = make_double2(0, 0);
+      for (int k = 0; k < p; ++k) {
+        const double2 t = cmul(V[m * p + k], vec[k]);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
+      zd[((long long)r * p + m) * d + nu] = acc;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+  }
+  if (m == 0) {
+    part[2 * blockIdx.x] = mn;
+    part[2 * blockIdx.x + 1] = mx;
+  }
+}
+
 template <int Unused = 0>
 __global__ void __launch_bounds__(kThreads) k_minmax_final(const double* part, int nparts, double* out) {
   __shared__ double smin[kThreads], smax[kThreads];

@@ -334,7 +334,8 @@ inline Layout ws_layout(const Plan& P, int op, long long B) {
       l.G = take(16 * L);   // separable dual / frequency-domain dual
       if (fs) l.Y = take(16 * L);
       if (P.longd) l.U = take(16 * L);   // between the two inverse column passes
-      l.part = take(16 * (size_t(cdiv((long long)P.Mi * P.di, kThreads)) + 1));
+      l.part = take(16 * (size_t(std::max<long long>(cdiv((long long)P.Mi * P.di, kThreads),
+                                                      std::min<long long>(P.Mi * P.di, kDualLdsGroups))) + 1));
       break;
     default:
       break;
@@ -1306,12 +1307,25 @@ inline int dual_impl(const Plan& P, const double2* g_dev, double2* gd_dev, doubl
   rc = window_zak<double2>(P, g_dev, nullptr, Z, w, lw, st);
   if (rc) return rc;
   const long long tot = P.Mi * P.di;
-  const unsigned nb = cdiv(tot, kThreads);
+  unsigned nb = cdiv(tot, kThreads);
   const double sb = P.branch == kFreqShear ? double(P.L) : 1.0;
   if (P.pi == 1)
     rc = launch_raw(k_dual_div<>, dim3(nb), dim3(kThreads), 0, st, "dual division", Z, Zd, part, int(P.Mi),
                     int(P.di), int(P.ai), int(P.qi), sb, tight ? 1 : 0);
-  else {
+  else if (P.pi > kDualMaxP) {
+    // one wavefront per block, S and its eigenvectors in LDS
+    nb = unsigned(std::min<long long>(tot, kDualLdsGroups));
+    const size_t lds = 32 * size_t(P.pi) * size_t(P.pi);
+    if (lds > 64 * 1024 && !dry_run()) {
+      rc = check_hip(hipFuncSetAttribute(reinterpret_cast<const void*>(k_dual_block_lds<>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)),
+                     "dual block inversion");
+      if (rc) return rc;
+    }
+    rc = launch_raw(k_dual_block_lds<>, dim3(nb), dim3(64), lds, st, "dual block inversion", (const double2*)Z, Zd,
+                    part, int(P.Mi), int(P.di), int(P.pi), int(P.ai), int(P.qi), sb, tight ? 1 : 0,
+                    P.longd ? int(P.d2) : 0);
+  } else {
     auto kern = P.pi <= 2 ? k_dual_block<2> : P.pi <= 4 ? k_dual_block<4> : k_dual_block<kDualMaxP>;
     rc = launch_raw(kern, dim3(nb), dim3(kThreads), 0, st, "dual block inversion", (const double2*)Z, Zd, part,
                     int(P.Mi), int(P.di), int(P.pi), int(P.ai), int(P.qi), sb, tight ? 1 : 0,

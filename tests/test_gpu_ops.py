@@ -151,11 +151,52 @@ def test_dual_and_tight_on_a_crossover_lattice():
     assert rel(st, x[pts]) < 1e-11
 
 
-def test_dual_refuses_p_above_eight():
+# p > 8 of the sheared lattice (one wavefront per p x p block, in LDS):
+# separable, time-shear and frequency-shear plans, p = 9 ... 64
+DUAL_LATTICES_WIDE = [(90, 9, 10, 0, 1), (180, 9, 10, 1, 2), (720, 18, 20, 1, 4), (810, 27, 30, 1, 3),
+                      (480, 15, 16, 1, 2), (1728, 27, 32, 1, 2), (2520, 35, 36, 1, 2), (4032, 63, 64, 0, 1),
+                      (4032, 64, 63, 0, 1), (8064, 63, 64, 1, 2)]
+
+
+@pytest.mark.parametrize("lat", DUAL_LATTICES_WIDE)
+def test_dual_and_tight_with_wide_blocks(lat):
+    """Canonical dual and tight windows and the frame bounds for p from 9 to
+    64 against the oracle's Walnut-block solve and eigendecomposition (L up
+    to 4032), S g_d = g and S_gt = I at sampled points.  a = 64, M = 63 is
+    not a frame: the lower bound is zero.  The window is a modulated Gaussian
+    with a small complex perturbation (frame bound ratio below 40, so the
+    FP64 solve keeps the 1e-12 bar)."""
+    L, a, M, l1, l2 = lat
+    plan = plan_for(lat, torch.complex128, 1)
+    assert plan.info.p > 8
+    l = np.arange(L)
+    g = gaussian_window(L, a, M) * np.exp(2j * np.pi * 5 * l / L) + 0.002j * complex_normal(L, 18)
+    gd, bd = plan.dual(torch.tensor(g))
+    gt, bt = plan.tight(torch.tensor(g))
+    gd, gt = gd.cpu().numpy(), gt.cpu().numpy()
+    bd, bt = bd.cpu().numpy(), bt.cpu().numpy()
+    assert np.allclose(bd, bt, rtol=1e-12)
+    if a > M:
+        assert bd[0] == 0 and bd[1] > 0
+        return
+    if L <= 4032:
+        lo, hi = oracle.frame_bounds(g, a, M, l1, l2)
+        ed = rel(gd, oracle.dual_window(g, a, M, l1, l2))
+        et = rel(gt, oracle.tight_window(g, a, M, l1, l2))
+        print("wide blocks", lat, plan.branch, plan.info.p, ed, et, (bd[0], lo), (bd[1], hi))
+        assert ed < 1e-12 and et < 1e-12
+        assert abs(bd[0] - lo) < 1e-10 * hi and abs(bd[1] - hi) < 1e-10 * hi
+    pts = np.linspace(0, L - 1, 8).astype(np.int64)
+    assert rel(oracle.frame_operator_apply(gd, g, a, M, l1, l2, pts), g[pts]) < 1e-11
+    x = complex_normal(L, 19)
+    assert rel(oracle.frame_operator_apply(x, gt, a, M, l1, l2, pts), x[pts]) < 1e-11
+
+
+def test_dual_refuses_p_above_64():
     from paper_1307_4569_amd import _binding as Bb
-    plan = plan_for((180, 9, 10, 0, 1), torch.complex64, 1)
-    assert plan.info.p == 9
-    g = torch.tensor(gaussian_window(180, 9, 10))
+    plan = plan_for((4160, 65, 64, 0, 1), torch.complex64, 1)
+    assert plan.info.p == 65
+    g = torch.tensor(gaussian_window(4160, 65, 64))
     for fn in (plan.dual, plan.tight):
         with pytest.raises(Bb.DgtnsError) as e:
             fn(g)

@@ -318,7 +318,7 @@ REFUSALS = [
     (("fir", 144, 6, 12, 1, 2, 0, 2, 140, 20), B.DGTNS_OP_DUAL, "shear-algorithm plans"),
     (("mw", 144, 6, 12, 1, 2, 0, 2), B.DGTNS_OP_WINDOW_GRAD, "shear-algorithm plans"),
     (("mw", 144, 6, 12, 1, 2, 0, 2), B.DGTNS_OP_DUAL, "shear-algorithm plans"),
-    (("shear", 180, 9, 10, 0, 1, 0, 2), B.DGTNS_OP_DUAL, "p <= 8"),                    # p = 9
+    (("shear", 4160, 65, 64, 0, 1, 0, 2), B.DGTNS_OP_DUAL, "p <= 64"),                 # p = 65
 ]
 
 
