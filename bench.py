@@ -347,8 +347,12 @@ def fir_bench(torch, dev, steps=20, with_shear=True, with_adjoint=True):
     if with_shear:
         algs += [("shear", "hann", {}), ("shear_gaussian", "gaussian", {})]
         # the shear algorithm on overlap-added blocks (Section 4)
+        # (block transforms by the automatic plan, multiwindow here, and by
+        # the shear plan, which needs a frequency shear at these lengths)
         algs += [(f"shear_ola_block{blk}", "hann", {"algorithm": "shear-ola", "support": (w.L - 1024, 2048),
                                                     "block": blk}) for blk in (32768, 131072)]
+        algs += [("shear_ola_shear_block32768", "hann", {"algorithm": "shear-ola", "support": (w.L - 1024, 2048),
+                                                         "block": 32768, "inner": "shear"})]
     for name, win, kw in algs:
         plan = Plan(*lat, dtype=torch.complex64, max_batch=w.batch, device=dev, **kw)
         plan.set_window(torch.tensor(g_host[win]))
@@ -369,6 +373,7 @@ def fir_bench(torch, dev, steps=20, with_shear=True, with_adjoint=True):
             Lx = plan.info.block_dgt_length
             out[name]["block_dgt_length"] = Lx
             out[name]["rho"] = Lx / kw["block"]
+            out[name]["block_transform"] = "multiwindow" if plan.info.windows > 1 else "shear"
         if name in ("fir", "shear_gaussian") and with_shear:
             # real-signal variant: the non-redundant channels (two half and two
             # whole columns per group of four), real samples back

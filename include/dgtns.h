@@ -188,10 +188,13 @@ int dgtns_plan_create_fir(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int
  * applied to blocks of the signal, combined by overlap-add, for a window of
  * short support g_start, ..., g_start + g_len - 1 (mod L) as in
  * dgtns_plan_create_fir.  The signal is cut into L / block blocks of block
- * samples; each block, zero-extended, is transformed by the shear algorithm
- * on the same lattice at a length L_x of about block + g_len (the least
- * feasible one, reported as block_dgt_length), so the sheared window spans
- * L_x samples instead of L.  The coefficients of each block are multiplied
+ * samples; each block, zero-extended, is transformed on the same lattice at
+ * a length L_x of about block + g_len (the least feasible one, reported as
+ * block_dgt_length), so the sheared window spans L_x samples instead of L.
+ * The block transform is the automatic plan of dgtns_plan_create_alg
+ * (DGTNS_ALG_AUTO): the shear algorithm, or the multiwindow algorithm where
+ * the shear algorithm would need a frequency shear;
+ * dgtns_plan_create_ola_alg selects it.  The coefficients of each block are multiplied
  * by the exact phase of its position and added into eq. (DGT)'s
  * coefficients; the result equals eq. (DGT) with the truncated window.  The
  * work grows by the factor rho = L_x / block (eq. (OLA-eff)).  block must
@@ -203,13 +206,23 @@ int dgtns_plan_create_fir(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int
  * all blocks as one batch, and each block's own samples form the signal.
  * dgtns_forward_batch, dgtns_window_grad, dgtns_dual_window and
  * dgtns_tight_window return DGTNS_EUNSUPPORTED.  dgtns_plan_info reports branch
- * DGTNS_SHEAR_OLA with the inner plan's s0, s1, b_r, c, d, p, q.  Errors as
+ * DGTNS_SHEAR_OLA with the inner plan's s0, s1, b_r, c, d, p, q and windows.  Errors as
  * for dgtns_plan_create_fir, plus DGTNS_EINVAL for a bad block length and
  * DGTNS_EUNSUPPORTED when no feasible block length below L exists.
  */
 int dgtns_plan_create_ola(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1,
                           int64_t lambda2, int dtype, int64_t max_batch, int64_t g_start, int64_t g_len,
                           int64_t block);
+
+/*
+ * dgtns_plan_create_ola with the algorithm of the block transform:
+ * DGTNS_ALG_SHEAR (Alg. 1 on every block, Section 4's shear-OLA as stated),
+ * DGTNS_ALG_MULTIWINDOW or DGTNS_ALG_AUTO (as dgtns_plan_create_ola).
+ * DGTNS_EINVAL for another algorithm.
+ */
+int dgtns_plan_create_ola_alg(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1,
+                              int64_t lambda2, int dtype, int64_t max_batch, int64_t g_start, int64_t g_len,
+                              int64_t block, int inner_algorithm);
 
 /* Fill *info (host only). */
 int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info);

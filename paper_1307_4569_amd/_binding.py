@@ -76,6 +76,9 @@ SIGNATURES = [
      [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64, c_i64, c_i64]),
     ("dgtns_plan_create_ola", ctypes.c_int,
      [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64, c_i64, c_i64, c_i64]),
+    ("dgtns_plan_create_ola_alg", ctypes.c_int,
+     [ctypes.POINTER(c_vp), c_i64, c_i64, c_i64, c_i64, c_i64, ctypes.c_int, c_i64, c_i64, c_i64, c_i64,
+      ctypes.c_int]),
     ("dgtns_plan_info", ctypes.c_int, [c_vp, ctypes.POINTER(dgtns_plan_info_t)]),
     ("dgtns_plan_bind", ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, c_vp]),
     ("dgtns_workspace_bytes", ctypes.c_int, [c_vp, ctypes.c_int, c_i64, ctypes.POINTER(ctypes.c_size_t)]),
@@ -150,6 +153,13 @@ def dgtns_plan_create_ola(L, a, M, lambda1, lambda2, dtype, max_batch, g_start, 
     h = c_vp()
     _call("dgtns_plan_create_ola", ctypes.byref(h), L, a, M, lambda1, lambda2, dtype, max_batch, g_start, g_len,
           block)
+    return h
+
+
+def dgtns_plan_create_ola_alg(L, a, M, lambda1, lambda2, dtype, max_batch, g_start, g_len, block, inner_algorithm):
+    h = c_vp()
+    _call("dgtns_plan_create_ola_alg", ctypes.byref(h), L, a, M, lambda1, lambda2, dtype, max_batch, g_start,
+          g_len, block, inner_algorithm)
     return h
 
 

@@ -33,24 +33,28 @@ class Plan:
     algorithm: "shear" (Alg. 1), "multiwindow" (lambda2 coset windows on the
     separable lattice (lambda2 a, M), Prop. 4 and Prop. 5), "fir" (windows of
     short support, support=(start, length): the window is taken to be zero
-    outside samples start, ..., start + length - 1 mod L) or "shear-ola" (the
-    same truncated window; the shear algorithm on blocks of block samples,
-    combined by overlap-add, Section 4; forward only).  All compute the
-    coefficients of eq. (DGT).  Window gradients, dual and tight windows need
-    a shear plan."""
+    outside samples start, ..., start + length - 1 mod L), "shear-ola" (the
+    same truncated window; blocks of block samples transformed on the lattice
+    and combined by overlap-add, Section 4; inner: the block transform's
+    algorithm, "auto" (default), "shear" or "multiwindow") or "auto" (the
+    shear plan, or the multiwindow plan where the shear plan would need a
+    frequency shear).  All compute the coefficients of eq. (DGT).  Window
+    gradients, dual and tight windows need a shear plan."""
 
     def __init__(self, L: int, a: int, M: int, lam1: int = 0, lam2: int = 1,
                  dtype: torch.dtype = torch.complex64, max_batch: int = 64, device=None,
                  algorithm: str = "shear", support: Optional[Tuple[int, int]] = None,
-                 block: Optional[int] = None):
+                 block: Optional[int] = None, inner: str = "auto"):
         if dtype not in _DT:
             raise ValueError("dtype must be torch.complex64 or torch.complex128")
         if algorithm not in _ALG:
-            raise ValueError("algorithm must be 'shear', 'multiwindow', 'fir' or 'shear-ola'")
+            raise ValueError("algorithm must be 'shear', 'multiwindow', 'fir', 'shear-ola' or 'auto'")
         if (algorithm in ("fir", "shear-ola")) != (support is not None):
             raise ValueError("support=(start, length) is given exactly for algorithms 'fir' and 'shear-ola'")
         if (algorithm == "shear-ola") != (block is not None):
             raise ValueError("block is given exactly for algorithm 'shear-ola'")
+        if inner not in ("auto", "shear", "multiwindow"):
+            raise ValueError("inner must be 'auto', 'shear' or 'multiwindow'")
         if not torch.cuda.is_available():
             raise RuntimeError("libdgtns needs a HIP device")
         self.device = torch.device(device if device is not None else "cuda")
@@ -62,8 +66,8 @@ class Plan:
             self._h = B.dgtns_plan_create_fir(L, a, M, lam1, lam2, _DT[dtype], max_batch, int(support[0]),
                                               int(support[1]))
         elif algorithm == "shear-ola":
-            self._h = B.dgtns_plan_create_ola(L, a, M, lam1, lam2, _DT[dtype], max_batch, int(support[0]),
-                                              int(support[1]), int(block))
+            self._h = B.dgtns_plan_create_ola_alg(L, a, M, lam1, lam2, _DT[dtype], max_batch, int(support[0]),
+                                                  int(support[1]), int(block), _ALG[inner])
         else:
             self._h = B.dgtns_plan_create_alg(L, a, M, lam1, lam2, _DT[dtype], max_batch, _ALG[algorithm])
         self.info = B.dgtns_plan_info(self._h)

@@ -213,13 +213,14 @@ int dgtns_plan_create(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t
 
 static int create_plan(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
                        int dtype, int64_t max_batch, int algorithm, int64_t g_start, int64_t g_len,
-                       int64_t block = 0) {
+                       int64_t block = 0, int inner = kAlgAuto) {
   if (!plan) return fail(DGTNS_EINVAL, "null plan pointer");
   if (max_batch > 65535) return fail(DGTNS_EINVAL, "max_batch above 65535");
   dgtns_plan_s* h = new (std::nothrow) dgtns_plan_s();
   if (!h) return fail(DGTNS_EINVAL, "out of host memory");
   std::string err;
-  int rc = plan_make(L, a, M, lambda1, lambda2, dtype, max_batch, algorithm, &h->p, &err, g_start, g_len, block);
+  int rc = plan_make(L, a, M, lambda1, lambda2, dtype, max_batch, algorithm, &h->p, &err, g_start, g_len, block,
+                     inner);
   if (rc) {
     delete h;
     return fail(rc, err);
@@ -243,6 +244,13 @@ int dgtns_plan_create_fir(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int
 int dgtns_plan_create_ola(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
                           int dtype, int64_t max_batch, int64_t g_start, int64_t g_len, int64_t block) {
   return create_plan(plan, L, a, M, lambda1, lambda2, dtype, max_batch, kAlgShearOla, g_start, g_len, block);
+}
+
+int dgtns_plan_create_ola_alg(dgtns_plan* plan, int64_t L, int64_t a, int64_t M, int64_t lambda1, int64_t lambda2,
+                              int dtype, int64_t max_batch, int64_t g_start, int64_t g_len, int64_t block,
+                              int inner_algorithm) {
+  return create_plan(plan, L, a, M, lambda1, lambda2, dtype, max_batch, kAlgShearOla, g_start, g_len, block,
+                     inner_algorithm);
 }
 
 int dgtns_plan_info(dgtns_plan plan, dgtns_plan_info_t* info) {

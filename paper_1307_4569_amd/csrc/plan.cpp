@@ -213,7 +213,7 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int dtype,
               int64_t max_batch, int algorithm, Plan* P, std::string* err, int64_t fir_start, int64_t fir_len,
-              int64_t ola_block) {
+              int64_t ola_block, int ola_inner) {
   // status codes mirror include/dgtns.h
   const int kEInval = 1, kELattice = 2, kEUnsupported = 4;
   if (dtype != 0 && dtype != 1) { *err = "dtype must be DGTNS_C64 or DGTNS_C128"; return kEInval; }
@@ -264,6 +264,10 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
     // and transformed by the shear algorithm at a length L_x on the same
     // lattice, then overlap-added with the phase of the block's position
     if (fir_len < 1 || fir_len > L) { *err = "window support length must be in [1, L]"; return kEInval; }
+    if (ola_inner != kAlgShear && ola_inner != kAlgMultiwindow && ola_inner != kAlgAuto) {
+      *err = "the block transform's algorithm must be DGTNS_ALG_SHEAR, DGTNS_ALG_MULTIWINDOW or DGTNS_ALG_AUTO";
+      return kEInval;
+    }
     const int64_t Lb = ola_block;
     if (Lb < 1 || L % Lb) { *err = "block length must divide L"; return kEInval; }
     if (Lb % (lam2 * a)) { *err = "block length must be a multiple of lambda2 a"; return kEInval; }
@@ -288,9 +292,11 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
     bool ok = false;
     std::string e2;
     // L_x + g_len <= L: a window offset in (-L_x, L_x) cannot alias the
-    // support of the global window modulo L
+    // support of the global window modulo L.  The block DGT's algorithm is
+    // ola_inner (by default the automatic choice: the shear plan, or the
+    // multiwindow plan where the shear plan needs a frequency shear).
     for (int k = 0; k < 64 && Nx * a + fir_len <= L; ++k, Nx += step) {
-      if (plan_make(Nx * a, a, M, lam1, lam2, dtype, max_batch * Nb, kAlgShear, in.get(), &e2) == 0) {
+      if (plan_make(Nx * a, a, M, lam1, lam2, dtype, max_batch * Nb, ola_inner, in.get(), &e2) == 0) {
         ok = true;
         break;
       }
@@ -302,7 +308,7 @@ int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int d
     p.branch = kShearOla;
     p.sh = in->sh;
     p.ai = in->ai; p.Mi = in->Mi; p.bi = in->bi; p.Ni = in->Ni;
-    p.ci = in->ci; p.pi = in->pi; p.qw = in->qw; p.qi = in->qi; p.di = in->di;
+    p.ci = in->ci; p.pi = in->pi; p.qw = in->qw; p.qi = in->qi; p.di = in->di; p.nw = in->nw;
     p.fir_start = fmod64(fir_start, L);
     p.fir_len = fir_len;
     p.ola_Lb = Lb; p.ola_Nb = Nb; p.ola_Nx = Nx; p.ola_Lx = Nx * a; p.ola_P0 = P0; p.ola_J0 = J0; p.ola_s = sg;

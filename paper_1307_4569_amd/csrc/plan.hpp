@@ -134,7 +134,7 @@ struct Plan {
 // Returns 0 on success, else an error status with a message in *err.
 int plan_make(int64_t L, int64_t a, int64_t M, int64_t lam1, int64_t lam2, int dtype,
               int64_t max_batch, int algorithm, Plan* p, std::string* err, int64_t fir_start = 0,
-              int64_t fir_len = 0, int64_t ola_block = 0);
+              int64_t fir_len = 0, int64_t ola_block = 0, int ola_inner = kAlgAuto);
 
 // Coset window mu of the multiwindow algorithm: g_mu(l) = exp(2 pi i l sigma / L)
 // g(l - mu a) with sigma = (mu s) mod b (Prop. 5).

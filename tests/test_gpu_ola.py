@@ -51,9 +51,9 @@ def truncate(g, start, length):
     return out
 
 
-def ola_plan(lat, support, block, dtype, B):
+def ola_plan(lat, support, block, dtype, B, inner="auto"):
     from paper_1307_4569_amd import Plan
-    return Plan(*lat, dtype=dtype, max_batch=B, algorithm="shear-ola", support=support, block=block)
+    return Plan(*lat, dtype=dtype, max_batch=B, algorithm="shear-ola", support=support, block=block, inner=inner)
 
 
 # (L, a, M, lambda1, lambda2), (support start, length), block
@@ -65,15 +65,21 @@ CASES = [((1536, 8, 16, 1, 2), (1536 - 24, 48), 192),
          ((6144, 16, 64, 1, 2), (6000, 300), 1024)]          # support wrapping past L
 
 
+@pytest.mark.parametrize("inner", ["shear", "auto"])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_shear_ola_matches_oracle(dtype, kernel_path):
+def test_shear_ola_matches_oracle(dtype, kernel_path, inner):
+    """Block transforms by the shear algorithm (separable, time-shear and
+    frequency-shear inner plans) or the automatic choice (multiwindow where
+    the shear plan needs a frequency shear)."""
     single = dtype == torch.complex64
-    seen = set()
+    seen, windows, shears = set(), set(), set()
     for lat, support, block in CASES:
         L, a, M, l1, l2 = lat
         B = 3
-        plan = ola_plan(lat, support, block, dtype, B)
+        plan = ola_plan(lat, support, block, dtype, B, inner)
         seen.add(plan.info.branch)
+        windows.add(plan.info.windows)
+        shears.add(plan.info.s0 != 0)
         g = round_to(complex_normal(L, 21), single)
         f = round_to(np.stack([complex_normal(L, 30 + k) for k in range(B)]), single)
         plan.set_window(torch.tensor(g))
@@ -86,14 +92,21 @@ def test_shear_ola_matches_oracle(dtype, kernel_path):
         cin = round_to(np.stack([complex_normal(N * M, 60 + k).reshape(N, M) for k in range(B)]), single)
         fa = plan.adjoint(torch.tensor(cin)).cpu().numpy()
         ea = max(rel(fa[k], oracle.idgt_adjoint(cin[k], gt, a, M, l1, l2)) for k in range(B))
-        print("shear-OLA", kernel_path, dtype, lat, support, block, plan.info.block_dgt_length, e, "adjoint", ea)
+        print("shear-OLA", inner, kernel_path, dtype, lat, support, block, plan.info.block_dgt_length, e,
+              "adjoint", ea)
         assert e < TOL[dtype] and ea < TOL[dtype], (lat, e, ea)
     assert seen == {5}
+    if inner == "shear":
+        assert windows == {1} and shears == {False, True}
+    else:
+        assert windows > {1} and shears == {False}
 
 
-def test_shear_ola_precision_workload():
+@pytest.mark.parametrize("inner", ["shear", "auto"])
+def test_shear_ola_precision_workload(inner):
     """Hann window of length 2048 centred at 0, L = 2^20, a = 128, M = 1024,
-    lambda = 1/4, real chirp signals in FP32, blocks of 32768 samples: sampled
+    lambda = 1/4, real chirp signals in FP32, blocks of 32768 samples, block
+    transforms by the shear and by the automatic (multiwindow) plan: sampled
     time positions against the oracle, and the FIR-window algorithm with the
     same window gives the same coefficients."""
     w = PRECISION
@@ -102,7 +115,8 @@ def test_shear_ola_precision_workload():
     g = round_to(hann_window(w.L, 2048), True)
     x = round_to(np.stack([chirp_mixture(w.L, 13074569 + 3000 + k) for k in range(B)]), True).real
     xt = torch.tensor(x.astype(np.complex64)).cuda()
-    plan = ola_plan(lat, (w.L - 1024, 2048), 32768, torch.complex64, B)
+    plan = ola_plan(lat, (w.L - 1024, 2048), 32768, torch.complex64, B, inner)
+    assert plan.info.windows == (1 if inner == "shear" else w.lam2)
     plan.set_window(torch.tensor(g))
     c = plan.forward(xt)
     cols = list(range(0, w.N, 331)) + [w.N - 1]
@@ -113,7 +127,7 @@ def test_shear_ola_precision_workload():
     fir.set_window(torch.tensor(g))
     cf = fir.forward(xt)
     d = (torch.linalg.vector_norm(c - cf) / torch.linalg.vector_norm(cf)).item()
-    print("shear-OLA precision workload", plan.info.block_dgt_length, errs, "vs FIR", d)
+    print("shear-OLA precision workload", inner, plan.info.block_dgt_length, errs, "vs FIR", d)
     assert max(errs) < 1e-5 and d < 2e-5
     # adjoint of the batch against the FIR algorithm's adjoint and the oracle
     # at sampled samples

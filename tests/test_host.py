@@ -251,11 +251,26 @@ def test_shear_ola_plans(lib):
         for cand in range(-(-(block + 2048) // step) * step, Lx, step):
             with pytest.raises(B.DgtnsError):
                 B.dgtns_plan_create(cand, a, M, l1, l2, 0, 1)
-        # the inner plan is a shear plan at that length
-        hi = B.dgtns_plan_create(Lx, a, M, l1, l2, 0, 1)
+        # the inner plan is the automatic plan at that length: here the shear
+        # plan needs a frequency shear, so the multiwindow plan
+        hi = B.dgtns_plan_create_alg(Lx, a, M, l1, l2, 0, 1, B.DGTNS_ALG_AUTO)
         ii = B.dgtns_plan_info(hi)
         B.dgtns_plan_destroy(hi)
+        assert ii.windows == l2
+        assert (ii.s0, ii.s1, ii.c, ii.d, ii.p, ii.q, ii.windows) == (i.s0, i.s1, i.c, i.d, i.p, i.q, i.windows)
+        # with the shear algorithm asked for: the frequency-shear plan at that length
+        h = B.dgtns_plan_create_ola_alg(L, a, M, l1, l2, 0, 4, L - 1024, 2048, block, B.DGTNS_ALG_SHEAR)
+        i = B.dgtns_plan_info(h)
+        B.dgtns_plan_destroy(h)
+        hi = B.dgtns_plan_create(i.block_dgt_length, a, M, l1, l2, 0, 1)
+        ii = B.dgtns_plan_info(hi)
+        B.dgtns_plan_destroy(hi)
+        assert i.block_dgt_length == Lx and i.windows == 1 and i.s0 != 0
         assert (ii.s0, ii.s1, ii.c, ii.d, ii.p, ii.q) == (i.s0, i.s1, i.c, i.d, i.p, i.q)
+    for alg in (B.DGTNS_ALG_FIR, B.DGTNS_ALG_SHEAR_OLA, 7):
+        with pytest.raises(B.DgtnsError) as e:
+            B.dgtns_plan_create_ola_alg(L, a, M, l1, l2, 0, 4, L - 1024, 2048, 32768, alg)
+        assert e.value.status == B.DGTNS_EINVAL
     h = B.dgtns_plan_create_fir(L, a, M, l1, l2, 0, 1, 0, 10)
     assert B.dgtns_plan_info(h).block == 0
     B.dgtns_plan_destroy(h)
