@@ -138,6 +138,46 @@ template <typename C> __device__ __forceinline__ C load_sig(const void* x, int r
   return reinterpret_cast<const C*>(x)[idx];
 }
 
+// The NL samples x[xoff + li[i]] (zero where !ok[i]; li[i] is then 0) times
+// the chirp at li[i]: every load of the thread is issued before the first is
+// used, so their latencies overlap (the precision and chirp source are
+// uniform per launch and tested once).
+template <typename C, int NL>
+__device__ __forceinline__ void load_chirped(const void* x, int real_in, long long xoff, const ChirpSrc<C>& ch,
+                                             const long long (&li)[NL], const bool (&ok)[NL], C (&v)[NL]) {
+  using T = decltype(C::x);
+  if (real_in) {
+    const T* xr = reinterpret_cast<const T*>(x) + xoff;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) v[i] = mk<C>(ok[i] ? xr[li[i]] : T(0), T(0));
+  } else {
+    const C* xc = reinterpret_cast<const C*>(x) + xoff;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) v[i] = ok[i] ? xc[li[i]] : czero<C>();
+  }
+  if (ch.tab) {
+    C p[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) p[i] = ch.tab[li[i]];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) v[i] = cmul_comp(v[i], ch.conj ? cconj(p[i]) : p[i]);
+  } else if (ch.K) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) v[i] = apply_chirp(ch, v[i], li[i]);
+  }
+}
+
+// XCD-aware order of a launch's x blocks: work-groups are dealt to the 8
+// XCDs in turn by linear id, so with gridDim.x a multiple of 8 the x blocks
+// of one XCD are those of one residue mod 8.  They get consecutive logical
+// indices here, so neighbouring column blocks (which share cache lines of
+// the signal and of h) run behind the same L2.
+__device__ __forceinline__ int xcd_block_x() {
+  const int G = gridDim.x, x = blockIdx.x;
+  if (G & 7) return x;
+  return (x & 7) * (G >> 3) + (x >> 3);
+}
+
 // exp(-2 pi i e / n) (sign = -1) or its conjugate, from a table or on the fly
 template <typename C> __device__ __forceinline__ C root_at(const C* tab, long long e, long long n, int inv) {
   using T = decltype(C::x);

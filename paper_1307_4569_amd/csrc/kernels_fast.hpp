@@ -31,6 +31,8 @@ template <typename C, int D, int KF = 0> struct FastCols {
   // forward with h[n0][t][r]: the [t][column] staging tile of stride W + 1
   static constexpr int SW = W + 1;
   static constexpr int LDS_T = (LDS > D * SW ? LDS : D * SW);
+  // KF = 1: the staging tile after the exchange areas instead of aliasing them
+  static constexpr int LDS_TS = (TILE > 8 * EXW + D * SW ? TILE : 8 * EXW + D * SW);
 };
 
 // Rows per work-group of the fast row kernels for length MI: half the element
@@ -78,7 +80,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
   const int Mi = A.Mi;
   // column block and the share of time offsets n0 of this work-group
-  const int cb = blockIdx.x / A.nsplit, part = blockIdx.x - cb * A.nsplit;
+  const int bx = xcd_block_x();
+  const int cb = bx / A.nsplit, part = bx - cb * A.nsplit;
   const int qper = (A.q + A.nsplit - 1) / A.nsplit;
   const int n0_begin = part * qper, n0_end = min(A.q, n0_begin + qper);
   const int r0 = cb * W;
@@ -86,14 +89,24 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = A.list ? 0 : bo * A.xs;
   // 1. coalesced load of W adjacent columns (d values each), chirp applied
-  for (int e = tid; e < W * D; e += kThreads) {
-    const int t = e / W, cc = e - t * W, r = r0 + cc;
-    C v = czero<C>();
-    if (r < Mi) {
-      const long long li = r + (long long)t * Mi;
-      v = apply_chirp(A.chirp, load_sig<C>(xsrc, A.real_in, xoff + li), li);
+  {
+    constexpr int NL = (W * D) / kThreads;
+    static_assert(NL * kThreads == W * D, "column tile is a whole number of passes");
+    long long li[NL];
+    bool ok[NL];
+    C v[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int e = tid + i * kThreads, t = e / W, cc = e - t * W, r = r0 + cc;
+      ok[i] = r < Mi;
+      li[i] = ok[i] ? r + (long long)t * Mi : 0;
     }
-    lds[cc * SD + t] = v;
+    load_chirped<C, NL>(xsrc, A.real_in, xoff, A.chirp, li, ok, v);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      const int e = tid + i * kThreads, t = e / W, cc = e - t * W;
+      lds[cc * SD + t] = v[i];
+    }
   }
   WTw<C, D> tw;
   tw.load(A.twd, l);
@@ -115,13 +128,18 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
     // index u = r - n0 ai below zero multiplies the window Zak by
     // exp(2 pi i nu / d); after the inverse DFT that is the cyclic shift
     // h(t) = y(t + 1), applied here as a shifted staging index.
+    // SEP (KF = 1): the staging tile has LDS of its own, after the exchange
+    // areas, which saves one barrier per offset; the window rows of the next
+    // offset are loaded while the current one is transformed and stored, and
+    // each thread reads all its staged values before it stores them.
     constexpr int SW = F::SW;
-    C* stg = lds;
-    for (int n0 = n0_begin; n0 < n0_end; ++n0) {
+    constexpr bool SEP = KF == 1;
+    C* stg = SEP ? lds + 8 * F::EXW : lds;
+    C Z[K][E];
+    int sh[K];
+    auto zload = [&](int n0) {
       int n0w;
       const C* zc = window_of(A.zc, A.zs, A.qw, n0, &n0w);
-      C Y[K][E];
-      int sh[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int r = r0 + (wave * K + k) * I::TPW + tt;
@@ -130,29 +148,65 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
         sh[k] = v0 < 0 ? D - 1 : 0;
         const C* zrow = zc + (long long)(r < Mi ? u : 0) * D;
 #pragma unroll
-        for (int e = 0; e < E; ++e) Y[k][e] = cmul(X[k][e], zrow[l + T * e]);
+        for (int e = 0; e < E; ++e) Z[k][e] = zrow[l + T * e];
       }
+    };
+    if (SEP && n0_begin < n0_end) zload(n0_begin);
+    for (int n0 = n0_begin; n0 < n0_end; ++n0) {
+      if (!SEP) zload(n0);
+      C Y[K][E];
+      int shc[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        shc[k] = sh[k];
+#pragma unroll
+        for (int e = 0; e < E; ++e) Y[k][e] = cmul(X[k][e], Z[k][e]);
+      }
+      if (SEP && n0 + 1 < n0_end) zload(n0 + 1);
 #pragma unroll
       for (int k = 0; k < K; ++k) wave_fft<C, D, true>(Y[k], ex, l, tw);
-      __syncthreads();   // the exchange areas alias the staging tile
+      // SEP: every thread has read the previous offset's tile; otherwise the
+      // exchange areas alias the tile
+      __syncthreads();
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const int cc = (wave * K + k) * I::TPW + tt;
 #pragma unroll
-        for (int e = 0; e < E; ++e) stg[((l + T * e + sh[k]) & (D - 1)) * SW + cc] = Y[k][e];
+        for (int e = 0; e < E; ++e) stg[((l + T * e + shc[k]) & (D - 1)) * SW + cc] = Y[k][e];
       }
       __syncthreads();
       C* hb = A.H + bo * A.hs + (long long)n0 * D * Mi + r0;
-      for (int e = tid; e < W * D; e += kThreads) {
-        const int t = e / W, c = e - t * W;
-        if (r0 + c < Mi) {
-          if constexpr (HS)
-            st_stream(hb + (long long)t * Mi + c, stg[t * SW + c]);
-          else
-            hb[(long long)t * Mi + c] = stg[t * SW + c];
+      if constexpr (SEP) {
+        constexpr int NS = (W * D) / kThreads;
+        static_assert(NS * kThreads == W * D, "staging tile is a whole number of passes");
+        C sv[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const int e = tid + i * kThreads, t = e / W, c = e - t * W;
+          sv[i] = stg[t * SW + c];
         }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          const int e = tid + i * kThreads, t = e / W, c = e - t * W;
+          if (r0 + c < Mi) {
+            if constexpr (HS)
+              st_stream(hb + (long long)t * Mi + c, sv[i]);
+            else
+              hb[(long long)t * Mi + c] = sv[i];
+          }
+        }
+      } else {
+        for (int e = tid; e < W * D; e += kThreads) {
+          const int t = e / W, c = e - t * W;
+          if (r0 + c < Mi) {
+            if constexpr (HS)
+              st_stream(hb + (long long)t * Mi + c, stg[t * SW + c]);
+            else
+              hb[(long long)t * Mi + c] = stg[t * SW + c];
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
     return;
   }

@@ -374,7 +374,7 @@ int run_cols_fast_k(const Plan& P, const ColArgs<C>& A, long long B, hipStream_t
   A2.nsplit = int(ns);
   dim3 grid(unsigned(nblk * ns), unsigned(B));
   if (A2.ht) {
-    const size_t lds = sizeof(C) * F::LDS_T;
+    const size_t lds = sizeof(C) * (KF == 1 ? F::LDS_TS : F::LDS_T);
     if (A2.hstream) return launch(k_fwd_cols_w<C, D, true, true, KF>, grid, lds, st, A2, "factorisation kernel");
     return launch(k_fwd_cols_w<C, D, false, true, KF>, grid, lds, st, A2, "factorisation kernel");
   }
