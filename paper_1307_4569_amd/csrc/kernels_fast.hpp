@@ -36,15 +36,17 @@ template <typename C, int D, int KF = 0> struct FastCols {
 };
 
 // Rows per work-group of the fast row kernels for length MI: half the element
-// budget, so that four work-groups (32 wavefronts) fit on a compute unit.
+// budget, so that four work-groups (32 wavefronts) fit on a compute unit; the
+// adjoint (ADJ) takes the whole budget, so that its strided stores of h
+// cover whole 128-byte lines in FP32.
 // The [Mi][RB] tile of the adjoint (strided stores, row-wise loads) uses the
 // padded stride RB + 1; the forward tile (row-wise stores, strided loads)
 // stores element (m, i) at m RB + i + m / PD, which keeps both its stores
 // (128 bytes per cycle) and its column loads (256 bytes per cycle) free of
 // LDS bank conflicts when RB is below the 256 bytes a load serves.
-template <typename C, int MI> struct FastRows {
+template <typename C, int MI, bool ADJ = false> struct FastRows {
   static constexpr int TPW = WInfo<MI>::TPW;
-  static constexpr int K0 = Budget<C>::value / (16 * TPW * MI);
+  static constexpr int K0 = Budget<C>::value / ((ADJ ? 8 : 16) * TPW * MI);
   static constexpr int K = K0 < 1 ? 1 : K0;
   static constexpr int RB = 8 * TPW * K;          // rows (time positions t') per work-group
   static constexpr int SR = RB + 1;               // padded stride of the adjoint tile
@@ -529,7 +531,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_rows_w(RowArgs<C> A) {
 
 template <typename C, int MI, int MODE, bool HS>
 __global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
-  using F = FastRows<C, MI>;
+  using F = FastRows<C, MI, true>;
   using I = WInfo<MI>;
   constexpr int E = I::E, T = I::T, K = F::K, RB = F::RB, SR = F::SR;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -582,14 +584,24 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
     for (int e = 0; e < E; ++e) lds[(l + T * e) * SR + i] = v[k][e];
   }
   __syncthreads();
+  // all staged values of a thread are read before the first store
   C* hb = const_cast<C*>(A.H) + bo * A.hs + (long long)n0 * MI * d + t0;
-  for (int e = tid; e < RB * MI; e += kThreads) {
-    const int m = e / RB, i = e - m * RB;
+  constexpr int NS = (RB * MI) / kThreads;
+  static_assert(NS * kThreads == RB * MI, "row tile is a whole number of passes");
+  C sv[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    const int e = tid + j * kThreads, m = e / RB, i = e - m * RB;
+    sv[j] = lds[m * SR + i];
+  }
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    const int e = tid + j * kThreads, m = e / RB, i = e - m * RB;
     if (t0 + i < d) {
       if constexpr (HS)
-        st_stream(hb + (long long)m * d + i, lds[m * SR + i]);
+        st_stream(hb + (long long)m * d + i, sv[j]);
       else
-        hb[(long long)m * d + i] = lds[m * SR + i];
+        hb[(long long)m * d + i] = sv[j];
     }
   }
 }

@@ -183,17 +183,40 @@ __global__ void __launch_bounds__(kThreads, 4) k_fir_fwd_ws(FirArgs<C> A) {
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = A.list ? 0 : bo * A.xs;
   const int nf = blockIdx.x * P, S = (P - 1) * A.a + A.Lg;
-  // 1. span f((base0 + i) mod L), i < S, and window gw[j], j < L_g
+  // 1. span f((base0 + i) mod L), i < S, and window gw[j], j < L_g; each
+  // thread issues U loads before it waits for the first
   {
+    constexpr int U = 4;
     const long long base0 = ((long long)nf * A.a + A.start) % A.L;
     C* span = lds;
-    for (int i = tid; i < S; i += kThreads) {
-      long long idx = base0 + i;
-      if (idx >= A.L) idx %= A.L;
-      span[i] = load_sig<C>(xsrc, A.real_in, xoff + idx);
+    for (int i0 = tid; i0 < S; i0 += U * kThreads) {
+      C v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kThreads;
+        long long idx = base0 + i;
+        if (idx >= A.L) {
+          idx -= A.L;
+          if (idx >= A.L) idx %= A.L;   // spans longer than L (short signals)
+        }
+        v[u] = i < S ? load_sig<C>(xsrc, A.real_in, xoff + idx) : czero<C>();
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * kThreads < S) span[i0 + u * kThreads] = v[u];
     }
     C* win = lds + S;
-    for (int j = tid; j < A.Lg; j += kThreads) win[j] = A.gw[j];
+    for (int j0 = tid; j0 < A.Lg; j0 += U * kThreads) {
+      C v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * kThreads;
+        v[u] = j < A.Lg ? A.gw[j] : czero<C>();
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (j0 + u * kThreads < A.Lg) win[j0 + u * kThreads] = v[u];
+    }
   }
   __syncthreads();
   // 2. fold: bin k = l + T e of position n

@@ -406,8 +406,9 @@ int run_adj_cols_fast(const Plan& P, const ColAdjArgs<C>& A, long long B, hipStr
 template <typename C, int MI>
 int run_rows_fast(const Plan& P, const RowArgs<C>& A, long long B, bool adjoint, hipStream_t st) {
   using F = FastRows<C, MI>;
-  dim3 grid(unsigned(P.qi) * cdiv(P.di, F::RB), unsigned(B));
-  const size_t lds = sizeof(C) * F::LDS;
+  using FA = FastRows<C, MI, true>;   // as in k_adj_rows_w
+  dim3 grid(unsigned(P.qi) * cdiv(P.di, adjoint ? FA::RB : F::RB), unsigned(B));
+  const size_t lds = sizeof(C) * (adjoint ? FA::LDS : F::LDS);
   const bool fs = P.branch == kFreqShear;
   if (!adjoint && A.ht) {
     // rows come straight from h[n0][t][r]: LDS only for the wave exchanges
