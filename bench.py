@@ -769,7 +769,11 @@ def main():
         "wall_ms_per_step": wall_ms,
         "whole_path": {"compulsory_bytes_per_coeff": 9.0,
                        "compulsory_GBps": round(9.0 * value / 1e9, 1),
-                       "frac_of_compulsory_bound": round(9.0 * value / 1e9 / HBM_PEAK_GBS, 4)},
+                       "frac_of_compulsory_bound": round(9.0 * value / 1e9 / HBM_PEAK_GBS, 4),
+                       # read f, write and read back h, write c: the two-kernel design's bytes
+                       # if h made the round trip through HBM (here it stays in the Infinity Cache)
+                       "two_kernel_bytes_per_coeff": 25.0,
+                       "frac_of_two_kernel_bound": round(25.0 * value / 1e9 / HBM_PEAK_GBS, 4)},
     }
 
     # practical HBM ceiling: a plain device copy of the same size as the
