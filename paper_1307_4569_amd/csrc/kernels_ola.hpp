@@ -46,35 +46,58 @@ __global__ void __launch_bounds__(kThreads) k_ola_gather(OlaArgs<C> A) {
 // c_k(m, n) = sum over the blocks b whose local positions n' = (n + P0 -
 // b L_b / a) mod N lie in Z_Nx of exp(-2 pi i o_b (m lambda2 + kn) /
 // (lambda2 M)) cl[k Nb + b][n'][m], kn = n lambda1 mod lambda2, in a fixed
-// order (no atomics).  grid (ceil(N M / kThreads), B).
+// order (no atomics).  One work-group per time position n and signal k
+// (grid (N, B), kOlaThreads threads): the covering blocks, their rows and
+// position phases are found once per work-group, and the phase index of
+// channel m advances by a constant step between a thread's channels.
+constexpr int kOlaThreads = 256;
+constexpr int kOlaPer = 16;   // channels per thread and slice
+
 template <typename C>
-__global__ void __launch_bounds__(kThreads) k_ola_combine(OlaArgs<C> A) {
-  const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
-  const long long NM = (long long)A.N * A.M;
-  if (idx >= NM) return;
-  const int n = int(idx / A.M), m = int(idx - (long long)n * A.M);
+__global__ void __launch_bounds__(kOlaThreads) k_ola_combine(OlaArgs<C> A) {
+  const int n = blockIdx.x, tid = threadIdx.x;
+  const long long k = blockIdx.y;
   int cnt, ee;
   const long long col = coef_col(A.lay, n, &cnt, &ee);
-  if (m >= cnt) return;   // a channel the real-signal layout omits
-  const long long k = blockIdx.y;
   const int Q = int(A.Lb / A.a);
   int t = n + A.P0;
   if (t >= A.N) t -= A.N;
   const int bh = t / Q, n00 = t - bh * Q;
-  const long long PM = (long long)A.lam2 * A.M;
-  const long long mk = (long long)m * A.lam2 + ((long long)n * A.lam1) % A.lam2;
-  C acc = czero<C>();
-  for (int i = 0;; ++i) {
-    const int np = n00 + i * Q;   // np < Nx < N = Nb Q, so i < Nb
-    if (np >= A.Nx) break;
-    int b = bh - i;
-    if (b < 0) b += A.Nb;
-    long long ob = ((long long)b * A.Lb - A.J0) % PM;
-    if (ob < 0) ob += PM;
-    const C w = A.ph[(ob * mk) % PM];
-    acc = cadd(acc, cmul(w, A.cl[((k * A.Nb + b) * A.Nx + np) * (long long)A.M + m]));
+  const unsigned long long PM = (unsigned long long)A.lam2 * A.M;
+  const unsigned long long kn = (unsigned long long)(((long long)n * A.lam1) % A.lam2);
+  // channels in slices of kOlaThreads kOlaPer (one slice for M <= 4096)
+  for (int m0 = 0; m0 < cnt; m0 += kOlaThreads * kOlaPer) {
+    C acc[kOlaPer];
+#pragma unroll
+    for (int j = 0; j < kOlaPer; ++j) acc[j] = czero<C>();
+    for (int i = 0;; ++i) {
+      const int np = n00 + i * Q;   // np < Nx < N = Nb Q, so i < Nb
+      if (np >= A.Nx) break;
+      int b = bh - i;
+      if (b < 0) b += A.Nb;
+      long long ob = ((long long)b * A.Lb - A.J0) % (long long)PM;
+      if (ob < 0) ob += PM;
+      // phase index of channel m: (ob (m lambda2 + kn)) mod PM = (e0 + m st) mod PM
+      const unsigned long long e0 = ((unsigned long long)ob * kn) % PM;
+      const unsigned long long st = ((unsigned long long)ob * A.lam2) % PM;
+      const unsigned long long est = (st * kOlaThreads) % PM;
+      unsigned long long e = (e0 + st * (unsigned long long)(m0 + tid)) % PM;
+      const C* src = A.cl + ((k * A.Nb + b) * A.Nx + np) * (long long)A.M;
+#pragma unroll
+      for (int j = 0; j < kOlaPer; ++j) {
+        const int m = m0 + tid + j * kOlaThreads;
+        if (m < cnt) acc[j] = cadd(acc[j], cmul(A.ph[e], src[m]));
+        e += est;
+        if (e >= PM) e -= PM;
+      }
+    }
+    C* dst = A.c + k * A.cs + col;
+#pragma unroll
+    for (int j = 0; j < kOlaPer; ++j) {
+      const int m = m0 + tid + j * kOlaThreads;
+      if (m < cnt) dst[m] = acc[j];
+    }
   }
-  A.c[k * A.cs + col + m] = acc;
 }
 
 // Adjoint of the overlap-add: block b's coefficient at local position n' is
@@ -82,13 +105,13 @@ __global__ void __launch_bounds__(kThreads) k_ola_combine(OlaArgs<C> A) {
 // conjugate of the combine's phase:
 //     cl[k Nb + b][n'][m] = conj(exp(-2 pi i o_b (m lambda2 + kn) / (lambda2 M))) c_k(m, n),
 // with i = n' div Q, n00 = n' mod Q (Q = L_b / a), n = ((b + i) mod Nb) Q +
-// n00 - P0 (mod N).  grid (ceil(Nx M / kThreads), B Nb).
+// n00 - P0 (mod N).  grid (Nx, B Nb), kOlaThreads threads.
 template <typename C>
-__global__ void __launch_bounds__(kThreads) k_ola_split(OlaArgs<C> A) {
-  const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
+__global__ void __launch_bounds__(kOlaThreads) k_ola_split(OlaArgs<C> A) {
+  // one work-group per local position n' (blockIdx.x) of block kb: the
+  // global position, its column and the block phase are uniform
+  const int np = blockIdx.x, tid = threadIdx.x;
   const long long NxM = (long long)A.Nx * A.M;
-  if (idx >= NxM) return;
-  const int np = int(idx / A.M), m = int(idx - (long long)np * A.M);
   const long long kb = blockIdx.y;
   const long long k = kb / A.Nb;
   const int b = int(kb - k * A.Nb);
@@ -98,15 +121,23 @@ __global__ void __launch_bounds__(kThreads) k_ola_split(OlaArgs<C> A) {
   if (bh >= A.Nb) bh -= A.Nb;   // i < Nb (np < Nx < N)
   int n = bh * Q + n00 - A.P0;
   if (n < 0) n += A.N;
-  const long long PM = (long long)A.lam2 * A.M;
-  const long long mk = (long long)m * A.lam2 + ((long long)n * A.lam1) % A.lam2;
-  long long ob = ((long long)b * A.Lb - A.J0) % PM;
+  const unsigned long long PM = (unsigned long long)A.lam2 * A.M;
+  const unsigned long long kn = (unsigned long long)(((long long)n * A.lam1) % A.lam2);
+  long long ob = ((long long)b * A.Lb - A.J0) % (long long)PM;
   if (ob < 0) ob += PM;
-  const C w = A.ph[(ob * mk) % PM];
+  const unsigned long long e0 = ((unsigned long long)ob * kn) % PM;
+  const unsigned long long st = ((unsigned long long)ob * A.lam2) % PM;
+  const unsigned long long est = (st * kOlaThreads) % PM;
+  unsigned long long e = (e0 + st * tid) % PM;
   int cnt, ee;
   const long long col = coef_col(A.lay, n, &cnt, &ee);
-  const C v = coef_load(A.c + k * A.cs, A.M, col, cnt, ee, m);
-  const_cast<C*>(A.cl)[kb * NxM + idx] = cmulc(v, w);
+  const C* cb = A.c + k * A.cs;
+  C* dst = const_cast<C*>(A.cl) + kb * NxM + (long long)np * A.M;
+  for (int m = tid; m < A.M; m += kOlaThreads) {
+    dst[m] = cmulc(coef_load(cb, A.M, col, cnt, ee, m), A.ph[e]);
+    e += est;
+    if (e >= PM) e -= PM;
+  }
 }
 
 // Adjoint of the block gather: sample j of block b's synthesis, j in

@@ -969,7 +969,7 @@ int run_ola_fwd(const Plan& P, const void* f, int real_in, C* c, long long B, ch
     rc = forward_impl<C>(Q, A.X, 0, const_cast<C*>(A.cl), Bi, ws + l.inner, ws_layout(Q, DGTNS_OP_FORWARD, Bi), st);
   }
   if (rc) return rc;
-  return launch_raw(k_ola_combine<C>, dim3(cdiv(P.N * P.M, kThreads), unsigned(B)), dim3(kThreads), 0, st,
+  return launch_raw(k_ola_combine<C>, dim3(unsigned(P.N), unsigned(B)), dim3(kOlaThreads), 0, st,
                     "OLA overlap-add", A);
 }
 
@@ -994,7 +994,7 @@ int run_ola_adj(const Plan& P, const C* c, C* f, long long B, char* ws, const La
   A.a = int(P.a); A.M = int(P.M); A.N = int(P.N); A.Nb = int(P.ola_Nb); A.Nx = int(P.ola_Nx);
   A.P0 = int(P.ola_P0); A.lam1 = int(P.lam1); A.lam2 = int(P.lam2);
   const long long Bi = B * P.ola_Nb;
-  int rc = launch_raw(k_ola_split<C>, dim3(cdiv(P.ola_Nx * P.M, kThreads), unsigned(Bi)), dim3(kThreads), 0, st,
+  int rc = launch_raw(k_ola_split<C>, dim3(unsigned(P.ola_Nx), unsigned(Bi)), dim3(kOlaThreads), 0, st,
                       "OLA split", A);
   if (rc) return rc;
   const int real_out = real_call() ? 1 : 0;
