@@ -179,6 +179,13 @@ template <typename C, bool INV> struct Bfly<C, 3, INV> : BflyOdd<C, 3, INV> {};
 template <typename C, bool INV> struct Bfly<C, 5, INV> : BflyOdd<C, 5, INV> {};
 template <typename C, bool INV> struct Bfly<C, 7, INV> : BflyOdd<C, 7, INV> {};
 
+// Quotient x / d of integers 0 <= x < 2^15 and 1 <= d <= 4096 from the
+// correctly rounded reciprocal inv = 1.0f / d: (x + 1/2) / d lies at least
+// 1 / (2 d) from every integer, far more than the error of one rounded
+// product, so truncation gives the exact quotient (checked for every such
+// pair).  Three vector instructions instead of a runtime integer division.
+__device__ __forceinline__ int qdiv(int x, float inv) { return int((float(x) + 0.5f) * inv); }
+
 // One in-place Stockham pass over `ntr` transforms of length n stored at
 // buf + t * tstride (t in Z_ntr).
 template <typename C, int R, bool INV, int MAXE>
@@ -187,12 +194,13 @@ __device__ __noinline__ void fft_pass(C* buf, int tstride, int n, int ntr, int N
   const int nb = n / R;
   const int total = nb * ntr;
   const int twstep = n / (Ns * R);
+  const float inb = 1.0f / float(nb), ins = 1.0f / float(Ns);   // total < 2^15, n <= 4096
   C v[KB][R];
 #pragma unroll
   for (int i = 0; i < KB; ++i) {
     const int bf = threadIdx.x + i * kThreads;
     if (bf < total) {
-      const int t = bf / nb, j = bf - t * nb;
+      const int t = qdiv(bf, inb), j = bf - t * nb;
       const C* src = buf + t * tstride + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = src[r * nb];
@@ -203,8 +211,8 @@ __device__ __noinline__ void fft_pass(C* buf, int tstride, int n, int ntr, int N
   for (int i = 0; i < KB; ++i) {
     const int bf = threadIdx.x + i * kThreads;
     if (bf < total) {
-      const int t = bf / nb, j = bf - t * nb;
-      const int k = j % Ns;
+      const int t = qdiv(bf, inb), j = bf - t * nb;
+      const int k = j - Ns * qdiv(j, ins);
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -253,6 +261,7 @@ __device__ __forceinline__ void wrt_pass(C* buf, int n, int Ns, const C* tw, int
   constexpr int KB = MV / R + 1;   // butterflies per lane: ceil(n / (64 R)) <= KB
   const int nb = n / R;
   const int twstep = n / (Ns * R);
+  const float ins = 1.0f / float(Ns);
   C v[KB][R];
 #pragma unroll
   for (int i = 0; i < KB; ++i) {
@@ -266,7 +275,7 @@ __device__ __forceinline__ void wrt_pass(C* buf, int n, int Ns, const C* tw, int
   for (int i = 0; i < KB; ++i) {
     const int j = lane + 64 * i;
     if (j < nb) {
-      const int k = j % Ns;
+      const int k = j - Ns * qdiv(j, ins);
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {

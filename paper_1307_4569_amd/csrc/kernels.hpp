@@ -267,8 +267,9 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = A.list ? 0 : bo * A.xs;
   const int b = p * d;
+  const float rW = 1.0f / float(W), rd = 1.0f / float(d);   // W b, W d < 2^15
   for (int e = threadIdx.x; e < W * b; e += kThreads) {
-    const int j = e / W, cc = e - j * W, r = r0 + cc;
+    const int j = qdiv(e, rW), cc = e - j * W, r = r0 + cc;
     C v = czero<C>();
     if (r < Mi) {
       const long long l = r + (long long)j * Mi;
@@ -287,7 +288,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
     for (int i = 0; i < KX; ++i) {
       const int e = threadIdx.x + i * kThreads;
       if (e < WD) {
-        const int cc = e / d, nu = e - cc * d;
+        const int cc = qdiv(e, rd), nu = e - cc * d;
         X[i] = xb[cc * Sd + nu];
       }
     }
@@ -301,7 +302,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
       for (int i = 0; i < KX; ++i) {
         const int e = threadIdx.x + i * kThreads;
         if (e < WD) {
-          const int cc = e / d, nu = e - cc * d, r = r0 + cc;
+          const int cc = qdiv(e, rd), nu = e - cc * d, r = r0 + cc;
           C y = czero<C>();
           if (r < Mi) {
             const int v = r - n0w * A.ai;
@@ -318,7 +319,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
       }
     } else {
       for (int e = threadIdx.x; e < WD; e += kThreads) {
-        const int cc = e / d, nu = e - cc * d, r = r0 + cc;
+        const int cc = qdiv(e, rd), nu = e - cc * d, r = r0 + cc;
         C y = czero<C>();
         if (r < Mi) {
           for (int j0 = 0; j0 < p; ++j0)
@@ -330,7 +331,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
     __syncthreads();
     fft_lds<C, true>(yb, Sd, A.fd, W, tw);
     for (int e = threadIdx.x; e < WD; e += kThreads) {
-      const int cc = e / d, t = e - cc * d, r = r0 + cc;
+      const int cc = qdiv(e, rd), t = e - cc * d, r = r0 + cc;
       if (r < Mi) st_h(A.H + bo * A.hs + ((long long)n0 * Mi + r) * d + t, yb[cc * Sd + t], A.hstream);
     }
   }
@@ -444,6 +445,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
   const int r0 = blockIdx.x * W;
   const long long bo = blockIdx.y;
   const int WD = W * d;
+  const float rW = 1.0f / float(W), rd = 1.0f / float(d);   // W p d < 2^15
   constexpr int KX = GENP ? 1 : MaxE<C>::value;
   C acc[KX];
 #pragma unroll
@@ -453,7 +455,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
   for (int n0 = 0; n0 < A.q; ++n0) {
     __syncthreads();
     for (int e = threadIdx.x; e < WD; e += kThreads) {
-      const int cc = e / d, t = e - cc * d, r = r0 + cc;
+      const int cc = qdiv(e, rd), t = e - cc * d, r = r0 + cc;
       yb[cc * Sd + t] = r < Mi ? A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t] : czero<C>();
     }
     __syncthreads();
@@ -465,7 +467,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
       for (int i = 0; i < KX; ++i) {
         const int e = threadIdx.x + i * kThreads;
         if (e < WD) {
-          const int cc = e / d, nu = e - cc * d, r = r0 + cc;
+          const int cc = qdiv(e, rd), nu = e - cc * d, r = r0 + cc;
           if (r < Mi) {
             const int v = r - n0w * A.ai;
             C z;
@@ -480,7 +482,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
       }
     } else {
       for (int e = threadIdx.x; e < WD; e += kThreads) {
-        const int cc = e / d, nu = e - cc * d, r = r0 + cc;
+        const int cc = qdiv(e, rd), nu = e - cc * d, r = r0 + cc;
         if (r < Mi) {
           const C yv = yb[cc * Sd + nu];
           for (int j0 = 0; j0 < p; ++j0) {
@@ -497,7 +499,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
     for (int i = 0; i < KX; ++i) {
       const int e = threadIdx.x + i * kThreads;
       if (e < WD) {
-        const int cc = e / d, nu = e - cc * d;
+        const int cc = qdiv(e, rd), nu = e - cc * d;
         xb[cc * Sd + nu] = acc[i];
       }
     }
@@ -506,7 +508,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
   fft_lds<C, true>(xb, Sd, A.fd, W * p, tw);
   const int b = p * d;
   for (int e = threadIdx.x; e < W * b; e += kThreads) {
-    const int j = e / W, cc = e - j * W, r = r0 + cc;
+    const int j = qdiv(e, rW), cc = e - j * W, r = r0 + cc;
     if (r < Mi) {
       const long long l = r + (long long)j * Mi;
       const int j0 = GENP ? j % p : 0, t = GENP ? j / p : j;

@@ -596,6 +596,11 @@ int run_cols(const Plan& P, const void* x, long long xs, int real_in, ChirpSrc<C
       return launch_t(k_fwd_cols_wr<C, 18, false, 4>, gw, 256, lt, st, A, "factorisation kernel");
     }
     if (!twl) return launch(k_fwd_cols_wr<C, 18, false>, gw, lt, st, A, "factorisation kernel");
+    // values per lane: as few as hold d, so that short columns do not run
+    // masked iterations (d = 36: one value per lane instead of five)
+    if (P.di <= 64) return launch(k_fwd_cols_wr<C, 1, true>, gw, lw, st, A, "factorisation kernel");
+    if (P.di <= 128) return launch(k_fwd_cols_wr<C, 2, true>, gw, lw, st, A, "factorisation kernel");
+    if (P.di <= 192) return launch(k_fwd_cols_wr<C, 3, true>, gw, lw, st, A, "factorisation kernel");
     if (P.di <= 320) return launch(k_fwd_cols_wr<C, 5, true>, gw, lw, st, A, "factorisation kernel");
     if (P.di <= 576) return launch(k_fwd_cols_wr<C, 9, true>, gw, lw, st, A, "factorisation kernel");
     return launch(k_fwd_cols_wr<C, 18, true>, gw, lw, st, A, "factorisation kernel");

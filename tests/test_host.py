@@ -480,3 +480,16 @@ def test_automatic_algorithm_choice(lib):
             B.dgtns_plan_destroy(hs)
             B.dgtns_plan_destroy(ha)
     assert nmw == 6
+
+
+def test_float_reciprocal_quotient_is_exact():
+    """The runtime-schedule kernels divide small integers through a float
+    reciprocal: for 0 <= x < 2^15 and 1 <= d <= 4096, truncating
+    (x + 1/2) * fl(1/d) in IEEE single precision gives x // d exactly."""
+    import numpy as np
+    x = np.arange(0, 1 << 15, dtype=np.int64)
+    xf = x.astype(np.float32) + np.float32(0.5)
+    for d in range(1, 4097):
+        inv = np.float32(1.0) / np.float32(d)
+        q = (xf * inv).astype(np.int64)
+        assert np.array_equal(q, x // d), d
