@@ -548,8 +548,32 @@ template <typename C> struct RowArgs {
   int ht;                      // h[n0][t][r] layout (fast forward kernels only)
   FftSched fm;
   long long N, L, b, M, K1, K2, K3, K4, K5, C1n, C2n, Kt1, Kt6;
+  // floor((2^64 - 1) / m) for the moduli 2N, N, L and the divisor b (Barrett)
+  unsigned long long mu2N, muN, muL, mub;
   CoefLayout lay;              // coefficient layout (c, cs and cl follow it)
 };
+
+// x mod m for any 64-bit x by Barrett reduction with mu = floor((2^64 - 1) /
+// m), m >= 2: q = floor(x mu / 2^64) is floor(x / m) or at most 2 below it,
+// so r = x - q m needs at most two corrections.  A few 32-bit products
+// instead of a 64-bit integer division.
+__device__ __forceinline__ unsigned long long mod_b(unsigned long long x, unsigned long long m,
+                                                    unsigned long long mu) {
+  const unsigned long long q = __umul64hi(x, mu);
+  unsigned long long r = x - q * m;
+  if (r >= m) r -= m;
+  if (r >= m) r -= m;
+  return r;
+}
+// floor(x / m) by the same reduction
+__device__ __forceinline__ unsigned long long div_b(unsigned long long x, unsigned long long m,
+                                                    unsigned long long mu) {
+  unsigned long long q = __umul64hi(x, mu);
+  unsigned long long r = x - q * m;
+  if (r >= m) { r -= m; ++q; }
+  if (r >= m) ++q;
+  return q;
+}
 
 // Frequency-shear post-processing of Alg. 1 for intermediate position m and
 // channel k: the phase *E and the coefficient's time position *nt and
@@ -558,16 +582,19 @@ template <typename C>
 __device__ __forceinline__ void shear_map(const RowArgs<C>& A, long long m, long long k, long long* nt,
                                           long long* kt, C* E) {
   using T = decltype(C::x);
-  const long long twoN = 2 * A.N;
-  const long long sq = (A.K1 * k + A.K2 * m) % twoN;
-  const long long sq2 = (sq * sq) % twoN;
-  long long e = (A.K3 * sq2) % twoN;
-  const long long inner = (A.K4 * m + A.K5 * k) % twoN;
-  e = (e - (m * inner) % twoN) % twoN;
-  if (e < 0) e += twoN;
+  // every constant is reduced into [0, modulus) on the host and m, k are
+  // non-negative, so each product below stays under 2^63
+  using U = unsigned long long;
+  const U twoN = U(2 * A.N), um = U(m), uk = U(k);
+  const U sq = mod_b(U(A.K1) * uk + U(A.K2) * um, twoN, A.mu2N);
+  const U sq2 = mod_b(sq * sq, twoN, A.mu2N);
+  const U e1 = mod_b(U(A.K3) * sq2, twoN, A.mu2N);
+  const U inner = mod_b(U(A.K4) * um + U(A.K5) * uk, twoN, A.mu2N);
+  const U mi = mod_b(um * inner, twoN, A.mu2N);
+  const long long e = (long long)(e1 >= mi ? e1 - mi : e1 + twoN - mi);
   *E = phase_pi(e, A.N, T());
-  *nt = (A.C1n * k + A.C2n * m) % A.N;
-  *kt = ((A.Kt1 * k + A.Kt6 * m) % A.L) / A.b;
+  *nt = (long long)mod_b(U(A.C1n) * uk + U(A.C2n) * um, U(A.N), A.muN);
+  *kt = (long long)div_b(mod_b(U(A.Kt1) * uk + U(A.Kt6) * um, U(A.L), A.muL), U(A.b), A.mub);
 }
 
 template <typename C, int MODE>

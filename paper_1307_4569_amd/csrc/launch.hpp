@@ -668,6 +668,11 @@ RowArgs<C> row_args(const Plan& P, const C* H, C* c) {
     A.N = P.N; A.L = P.L; A.b = P.b; A.M = P.M;
     A.K1 = P.K1; A.K2 = P.K2; A.K3 = P.K3; A.K4 = P.K4; A.K5 = P.K5;
     A.C1n = P.C1n; A.C2n = P.C2n; A.Kt1 = P.Kt1; A.Kt6 = P.Kt6;
+    const unsigned long long all = ~0ull;
+    A.mu2N = all / (unsigned long long)(2 * P.N);
+    A.muN = all / (unsigned long long)P.N;
+    A.muL = all / (unsigned long long)P.L;
+    A.mub = all / (unsigned long long)P.b;
   }
   return A;
 }

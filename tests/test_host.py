@@ -493,3 +493,42 @@ def test_float_reciprocal_quotient_is_exact():
         inv = np.float32(1.0) / np.float32(d)
         q = (xf * inv).astype(np.int64)
         assert np.array_equal(q, x // d), d
+
+
+def test_barrett_reduction_of_the_index_maps():
+    """The frequency-shear index map reduces 64-bit products modulo 2N, N
+    and L and divides by b through Barrett reduction with mu = floor((2^64 -
+    1) / m): the quotient estimate floor(x mu / 2^64) is at most 2 below
+    floor(x / m), so two corrections give x mod m and x // m exactly.  The
+    same steps in Python integers, on the edge cases and random dividends."""
+    import random
+    M64 = (1 << 64) - 1
+
+    def mod_b(x, m, mu):
+        q = (x * mu) >> 64
+        r = x - q * m
+        if r >= m:
+            r -= m
+        if r >= m:
+            r -= m
+        return r
+
+    def div_b(x, m, mu):
+        q = (x * mu) >> 64
+        r = x - q * m
+        if r >= m:
+            r -= m
+            q += 1
+        if r >= m:
+            q += 1
+        return q
+
+    rng = random.Random(13074569)
+    moduli = [1, 2, 3, 7, 64, 1000, 4096, 36864, 2 * 147456, (1 << 30) - 1, 1 << 30, 2 * (1 << 30), 3 ** 19]
+    for m in moduli:
+        mu = M64 // m
+        xs = [0, 1, m - 1, m, m + 1, 2 * m - 1, (1 << 62) - 1, (1 << 63) - 1, M64] + \
+             [rng.randrange(0, 1 << 63) for _ in range(2000)]
+        for x in xs:
+            assert mod_b(x, m, mu) == x % m, (x, m)
+            assert div_b(x, m, mu) == x // m, (x, m)
