@@ -9,11 +9,11 @@ it is missing.
 """
 from ._binding import DgtnsError  # noqa: F401
 
-__all__ = ["Plan", "dgt", "idgt", "DGTFunction", "DgtnsError"]
+__all__ = ["Plan", "dgt", "idgt", "dual", "DGTFunction", "DgtnsError"]
 
 
 def __getattr__(name):
-    if name in ("Plan", "dgt", "idgt", "DGTFunction"):
+    if name in ("Plan", "dgt", "idgt", "dual", "DGTFunction"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

@@ -247,6 +247,17 @@ def idgt(c: torch.Tensor, plan: Plan) -> torch.Tensor:
     return plan.adjoint(c)
 
 
+def dual(g: torch.Tensor, a: int, M: int, lam1: int = 0, lam2: int = 1, tight: bool = False, device=None):
+    """Canonical dual window S^{-1} g (tight=True: the canonical tight window
+    S^{-1/2} g) of the Gabor frame of g (length L) on the lattice (a, M,
+    lambda1/lambda2), in FP64 on the GPU, with the optimal frame bounds
+    (A, B) (A = 0: not a frame).  A shear plan of the lattice is built for
+    the call (its tables hold the shear factorisation the computation uses)."""
+    L = int(g.shape[-1])
+    plan = Plan(L, a, M, lam1, lam2, dtype=torch.complex64, max_batch=1, device=device)
+    return plan.tight(g) if tight else plan.dual(g)
+
+
 class DGTFunction(torch.autograd.Function):
     """c = DGT_g(f) with gradients for both the signal and the window.
 

@@ -192,6 +192,24 @@ def test_dual_and_tight_with_wide_blocks(lat):
     assert rel(oracle.frame_operator_apply(x, gt, a, M, l1, l2, pts), x[pts]) < 1e-11
 
 
+def test_functional_dual_and_tight():
+    """paper_1307_4569_amd.dual(g, a, M, lambda1, lambda2) builds the plan
+    itself: the same windows and bounds as the plan calls and the oracle."""
+    import paper_1307_4569_amd as dgtns
+    lat = (144, 6, 12, 1, 2)
+    L, a, M, l1, l2 = lat
+    g = torch.tensor(gaussian_window(L, a, M) + 0.1j * complex_normal(L, 21))
+    gd, bd = dgtns.dual(g, a, M, l1, l2)
+    gt, bt = dgtns.dual(g, a, M, l1, l2, tight=True)
+    gn = g.numpy()
+    assert rel(gd.cpu().numpy(), oracle.dual_window(gn, a, M, l1, l2)) < 1e-12
+    assert rel(gt.cpu().numpy(), oracle.tight_window(gn, a, M, l1, l2)) < 1e-12
+    lo, hi = oracle.frame_bounds(gn, a, M, l1, l2)
+    for b in (bd, bt):
+        A, Bb = b.cpu().numpy()
+        assert abs(A - lo) < 1e-10 * hi and abs(Bb - hi) < 1e-10 * hi
+
+
 def test_dual_refuses_p_above_64():
     from paper_1307_4569_amd import _binding as Bb
     plan = plan_for((4160, 65, 64, 0, 1), torch.complex64, 1)
