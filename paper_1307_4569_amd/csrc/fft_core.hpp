@@ -186,6 +186,26 @@ template <typename C, bool INV> struct Bfly<C, 7, INV> : BflyOdd<C, 7, INV> {};
 // pair).  Three vector instructions instead of a runtime integer division.
 __device__ __forceinline__ int qdiv(int x, float inv) { return int((float(x) + 0.5f) * inv); }
 
+// for (e = e0; e < n; e += step) st(e, ld(e)), in batches of U trips whose
+// loads are all issued before the first is used (so their latencies overlap
+// instead of one load and wait per trip).
+template <int U, typename V, typename LD, typename ST>
+__device__ __forceinline__ void batched_for(int e0, int n, int step, LD ld, ST st) {
+  for (int b = e0; b < n; b += U * step) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = b + u * step;
+      if (e < n) v[u] = ld(e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = b + u * step;
+      if (e < n) st(e, v[u]);
+    }
+  }
+}
+
 // One in-place Stockham pass over `ntr` transforms of length n stored at
 // buf + t * tstride (t in Z_ntr).
 template <typename C, int R, bool INV, int MAXE>

@@ -268,16 +268,22 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols(ColArgs<C> A) {
   const long long xoff = A.list ? 0 : bo * A.xs;
   const int b = p * d;
   const float rW = 1.0f / float(W), rd = 1.0f / float(d);   // W b, W d < 2^15
-  for (int e = threadIdx.x; e < W * b; e += kThreads) {
-    const int j = qdiv(e, rW), cc = e - j * W, r = r0 + cc;
-    C v = czero<C>();
-    if (r < Mi) {
-      const long long l = r + (long long)j * Mi;
-      v = apply_chirp(A.chirp, load_sig<C>(xsrc, A.real_in, xoff + l), l);
-    }
-    const int j0 = GENP ? j % p : 0, t = GENP ? j / p : j;
-    xb[(cc * p + j0) * Sd + t] = v;
-  }
+  batched_for<4, C>(
+      threadIdx.x, W * b, kThreads,
+      [&](int e) {
+        const int j = qdiv(e, rW), cc = e - j * W, r = r0 + cc;
+        C v = czero<C>();
+        if (r < Mi) {
+          const long long l = r + (long long)j * Mi;
+          v = apply_chirp(A.chirp, load_sig<C>(xsrc, A.real_in, xoff + l), l);
+        }
+        return v;
+      },
+      [&](int e, C v) {
+        const int j = qdiv(e, rW), cc = e - j * W;
+        const int j0 = GENP ? j % p : 0, t = GENP ? j / p : j;
+        xb[(cc * p + j0) * Sd + t] = v;
+      });
   __syncthreads();
   fft_lds<C, false>(xb, Sd, A.fd, W * p, tw);
   const int WD = W * d;
@@ -380,15 +386,21 @@ __global__ void __launch_bounds__(64 * NW) k_fwd_cols_wr(ColArgs<C> A) {
   const long long bo = blockIdx.y;
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = A.list ? 0 : bo * A.xs;
-  for (int e = tid; e < W * d; e += NT) {
-    const int t = e / W, cc = e - t * W, r = r0 + cc;
-    C v = czero<C>();
-    if (r < Mi) {
-      const long long l = r + (long long)t * Mi;
-      v = apply_chirp(A.chirp, load_sig<C>(xsrc, A.real_in, xoff + l), l);
-    }
-    lds[cc * Sd + t] = v;
-  }
+  batched_for<4, C>(
+      tid, W * d, NT,
+      [&](int e) {
+        const int t = e / W, cc = e - t * W, r = r0 + cc;
+        C v = czero<C>();
+        if (r < Mi) {
+          const long long l = r + (long long)t * Mi;
+          v = apply_chirp(A.chirp, load_sig<C>(xsrc, A.real_in, xoff + l), l);
+        }
+        return v;
+      },
+      [&](int e, C v) {
+        const int t = e / W, cc = e - t * W;
+        lds[cc * Sd + t] = v;
+      });
   const C* twl = A.twd;
   if constexpr (TWL) {
     C* t = lds + W * Sd;
@@ -454,10 +466,16 @@ __global__ void __launch_bounds__(kThreads) k_adj_cols(ColAdjArgs<C> A) {
     for (int e = threadIdx.x; e < W * p * Sd; e += kThreads) xb[e] = czero<C>();
   for (int n0 = 0; n0 < A.q; ++n0) {
     __syncthreads();
-    for (int e = threadIdx.x; e < WD; e += kThreads) {
-      const int cc = qdiv(e, rd), t = e - cc * d, r = r0 + cc;
-      yb[cc * Sd + t] = r < Mi ? A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t] : czero<C>();
-    }
+    batched_for<4, C>(
+        threadIdx.x, WD, kThreads,
+        [&](int e) {
+          const int cc = qdiv(e, rd), t = e - cc * d, r = r0 + cc;
+          return r < Mi ? A.H[bo * A.hs + ((long long)n0 * Mi + r) * d + t] : czero<C>();
+        },
+        [&](int e, C v) {
+          const int cc = qdiv(e, rd), t = e - cc * d;
+          yb[cc * Sd + t] = v;
+        });
     __syncthreads();
     fft_lds<C, false>(yb, Sd, A.fd, W, tw);
     int n0w;
@@ -714,21 +732,27 @@ __global__ void __launch_bounds__(kThreads) k_col_fft(ColFftArgs<C> A) {
   const long long bo = blockIdx.y;
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = A.list ? 0 : bo * A.xs;
-  for (int e = threadIdx.x; e < W * n; e += kThreads) {
-    const int j = e / W, cc = e - j * W, col = c0 + cc;
-    C v = czero<C>();
-    if (col < nc) {
-      const long long idx = (long long)j * nc + col;
-      v = apply_chirp(A.pre, load_sig<C>(xsrc, A.real_in, xoff + idx), idx);
-    }
-    buf[cc * Sn + j] = v;
-  }
+  batched_for<4, C>(
+      threadIdx.x, W * n, kThreads,
+      [&](int e) {
+        const int j = e / W, cc = e - j * W, col = c0 + cc;
+        C v = czero<C>();
+        if (col < nc) {
+          const long long idx = (long long)j * nc + col;
+          v = apply_chirp(A.pre, load_sig<C>(xsrc, A.real_in, xoff + idx), idx);
+        }
+        return v;
+      },
+      [&](int e, C v) {
+        const int j = e / W, cc = e - j * W;
+        buf[cc * Sn + j] = v;
+      });
   __syncthreads();
   fft_lds<C, INV>(buf, Sn, A.fs, W, tw);
   for (int e = threadIdx.x; e < W * n; e += kThreads) {
     const int k = e / W, cc = e - k * W, col = c0 + cc;
     if (col < nc) {
-      const long long ex = ((long long)k * col) % A.L;
+      const long long ex = (long long)k * col;   // k < n, col < ncols, n ncols = L: below L
       A.y[bo * A.ys + (long long)k * nc + col] = cmul(buf[cc * Sn + k], root_at(A.twL, ex, A.L, INV ? 1 : 0));
     }
   }
@@ -756,10 +780,17 @@ __global__ void __launch_bounds__(kThreads) k_row_fft(RowFftArgs<C> A) {
   for (int e = threadIdx.x; e < n; e += kThreads) tw[e] = A.tws[e];
   const int row0 = blockIdx.x * R;
   const long long bo = blockIdx.y;
-  for (int e = threadIdx.x; e < R * n; e += kThreads) {
-    const int rr = e / n, j = e - rr * n, row = row0 + rr;
-    buf[rr * Sn + j] = row < nr ? A.x[bo * A.xs + (long long)row * n + j] : czero<C>();
-  }
+  const float rn = 1.0f / float(n);   // R n < 2^15
+  batched_for<4, C>(
+      threadIdx.x, R * n, kThreads,
+      [&](int e) {
+        const int rr = qdiv(e, rn), j = e - rr * n, row = row0 + rr;
+        return row < nr ? A.x[bo * A.xs + (long long)row * n + j] : czero<C>();
+      },
+      [&](int e, C v) {
+        const int rr = qdiv(e, rn), j = e - rr * n;
+        buf[rr * Sn + j] = v;
+      });
   __syncthreads();
   fft_lds<C, INV>(buf, Sn, A.fs, R, tw);
   for (int e = threadIdx.x; e < R * n; e += kThreads) {

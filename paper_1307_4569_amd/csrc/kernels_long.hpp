@@ -66,20 +66,26 @@ __global__ void __launch_bounds__(kThreads) k_long_col(LongColArgs<C> A) {
   const long long bo = blockIdx.y, z = blockIdx.z;
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = (A.list ? 0 : bo * A.xs) + z * A.xz;
-  for (int e = threadIdx.x; e < W * n; e += kThreads) {
-    const int j = e / W, cc = e - j * W, col = c0 + cc;
-    C v = czero<C>();
-    if (col < nc) {
-      if (A.inmode == 0) {
-        const long long idx = (long long)j * nc + col;
-        v = apply_chirp(A.pre, load_sig<C>(xsrc, A.real_in, xoff + idx), idx);
-      } else {
-        const int r = col / d2, s2 = col - r * d2;
-        v = load_sig<C>(xsrc, 0, xoff + (long long)r * d + s2 + (long long)d2 * j);
-      }
-    }
-    buf[cc * Sn + j] = v;
-  }
+  batched_for<4, C>(
+      threadIdx.x, W * n, kThreads,
+      [&](int e) {
+        const int j = e / W, cc = e - j * W, col = c0 + cc;
+        C v = czero<C>();
+        if (col < nc) {
+          if (A.inmode == 0) {
+            const long long idx = (long long)j * nc + col;
+            v = apply_chirp(A.pre, load_sig<C>(xsrc, A.real_in, xoff + idx), idx);
+          } else {
+            const int r = col / d2, s2 = col - r * d2;
+            v = load_sig<C>(xsrc, 0, xoff + (long long)r * d + s2 + (long long)d2 * j);
+          }
+        }
+        return v;
+      },
+      [&](int e, C v) {
+        const int j = e / W, cc = e - j * W;
+        buf[cc * Sn + j] = v;
+      });
   __syncthreads();
   fft_lds<C, INV>(buf, Sn, A.fs, W, tw);
   const long long yoff = bo * A.ys + z * A.yz;
