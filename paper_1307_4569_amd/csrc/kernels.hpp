@@ -572,7 +572,7 @@ template <typename C> struct RowArgs {
 };
 
 // x mod m for any 64-bit x by Barrett reduction with mu = floor((2^64 - 1) /
-// m), m >= 2: q = floor(x mu / 2^64) is floor(x / m) or at most 2 below it,
+// m), m >= 1: q = floor(x mu / 2^64) is floor(x / m) or at most 2 below it,
 // so r = x - q m needs at most two corrections.  A few 32-bit products
 // instead of a 64-bit integer division.
 __device__ __forceinline__ unsigned long long mod_b(unsigned long long x, unsigned long long m,

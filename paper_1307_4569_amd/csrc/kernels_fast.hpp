@@ -574,8 +574,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
         v[k][e] = cmulc(coef_load(cb, int(A.M), col, cnt, ee, int(kt)), Ev);
       }
     }
-    wave_fft<C, MI, true>(v[k], ex, l, tw);
   }
+  // every row of the thread is loaded before the first transform
+#pragma unroll
+  for (int k = 0; k < K; ++k) wave_fft<C, MI, true>(v[k], ex, l, tw);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < K; ++k) {

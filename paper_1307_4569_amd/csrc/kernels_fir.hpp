@@ -38,6 +38,8 @@ template <typename C> struct FirArgs {
   FftSched fm;
   CoefLayout lay;  // coefficient layout (c, cs and cl follow it)
   int real_out;    // the adjoint writes real samples
+  // floor((2^64 - 1) / m) for m = M, lambda2 and lambda2 M (Barrett)
+  unsigned long long muM, muL2, muPM;
 };
 
 // Per-time-position constants of the folding: base = (n a + start) mod L
@@ -45,6 +47,10 @@ template <typename C> struct FirArgs {
 // and eb = (base kn) mod (lambda2 M), the phase index of sample 0.  Phase
 // indices then advance without divisions: lambda2 M divides L, so the
 // index (l kn) mod (lambda2 M) of sample l = base + j is eb + j kn reduced.
+// n a + start < 2 L (n a <= L - a, start < L): one conditional subtraction;
+// the other reductions are Barrett reductions with host reciprocals.  With n
+// the same on every lane (one transform per wavefront) all of it runs on the
+// scalar unit.
 struct FirPos {
   long long base;
   int bm, kn, eb;
@@ -52,12 +58,14 @@ struct FirPos {
 
 template <typename C>
 __device__ __forceinline__ FirPos fir_pos(const FirArgs<C>& A, int n) {
+  using U = unsigned long long;
   FirPos q;
-  q.base = ((long long)n * A.a + A.start) % A.L;
-  q.bm = int(q.base % A.M);
-  q.kn = int(((long long)n * A.lam1) % A.lam2);
-  const long long PM = (long long)A.lam2 * A.M;
-  q.eb = int(((q.base % PM) * q.kn) % PM);
+  q.base = (long long)n * A.a + A.start;
+  if (q.base >= A.L) q.base -= A.L;
+  q.bm = int(mod_b(U(q.base), U(A.M), A.muM));
+  q.kn = A.lam2 > 1 ? int(mod_b(U(n) * U(A.lam1), U(A.lam2), A.muL2)) : 0;
+  const U PM = U(A.lam2) * U(A.M);
+  q.eb = q.kn ? int(mod_b(mod_b(U(q.base), PM, A.muPM) * U(q.kn), PM, A.muPM)) : 0;
   return q;
 }
 
@@ -131,7 +139,8 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd_w(FirArgs<C> A) {
   const long long bo = blockIdx.y;
   const void* xsrc = A.list ? pick(A.xl, int(bo)) : A.x;
   const long long xoff = A.list ? 0 : bo * A.xs;
-  const int n = (blockIdx.x * 8 + wave) * TPW + tt;
+  // the same n on every lane of a wavefront when TPW = 1
+  const int n = (blockIdx.x * 8 + (TPW == 1 ? __builtin_amdgcn_readfirstlane(wave) : wave)) * TPW + tt;
   const FirPos q = fir_pos(A, n < A.N ? n : A.N - 1);
   C v[E];
 #pragma unroll
@@ -187,40 +196,61 @@ __global__ void __launch_bounds__(kThreads, 4) k_fir_fwd_ws(FirArgs<C> A) {
   // thread issues U loads before it waits for the first
   {
     constexpr int U = 4;
-    const long long base0 = ((long long)nf * A.a + A.start) % A.L;
+    using T = decltype(C::x);
+    long long base0 = (long long)nf * A.a + A.start;   // < 2 L
+    if (base0 >= A.L) base0 -= A.L;
     C* span = lds;
-    for (int i0 = tid; i0 < S; i0 += U * kThreads) {
-      C v[U];
+    // spans that do not wrap (all but the last few of a signal): one
+    // uniform base address and 32-bit lane offsets.  Indices beyond the span
+    // load its last sample (not stored), so the U loads carry no branch.
+    auto stage = [&](auto ld) {
+      for (unsigned i0 = tid; i0 < unsigned(S); i0 += U * kThreads) {
+        C v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * kThreads;
+        for (int u = 0; u < U; ++u) {
+          const unsigned i = i0 + u * kThreads;
+          v[u] = ld(i < unsigned(S) ? i : unsigned(S - 1));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (i0 + u * kThreads < unsigned(S)) span[i0 + u * kThreads] = v[u];
+      }
+    };
+    if (base0 + S <= A.L) {
+      if (A.real_in) {
+        const T* xp = reinterpret_cast<const T*>(xsrc) + xoff + base0;
+        stage([&](unsigned i) { return mk<C>(xp[i], T(0)); });
+      } else {
+        const C* xp = reinterpret_cast<const C*>(xsrc) + xoff + base0;
+        stage([&](unsigned i) { return xp[i]; });
+      }
+    } else {
+      stage([&](unsigned i) {
         long long idx = base0 + i;
         if (idx >= A.L) {
           idx -= A.L;
           if (idx >= A.L) idx %= A.L;   // spans longer than L (short signals)
         }
-        v[u] = i < S ? load_sig<C>(xsrc, A.real_in, xoff + idx) : czero<C>();
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (i0 + u * kThreads < S) span[i0 + u * kThreads] = v[u];
+        return load_sig<C>(xsrc, A.real_in, xoff + idx);
+      });
     }
     C* win = lds + S;
-    for (int j0 = tid; j0 < A.Lg; j0 += U * kThreads) {
+    for (unsigned j0 = tid; j0 < unsigned(A.Lg); j0 += U * kThreads) {
       C v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int j = j0 + u * kThreads;
-        v[u] = j < A.Lg ? A.gw[j] : czero<C>();
+        const unsigned j = j0 + u * kThreads;
+        v[u] = A.gw[j < unsigned(A.Lg) ? j : unsigned(A.Lg - 1)];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (j0 + u * kThreads < A.Lg) win[j0 + u * kThreads] = v[u];
+        if (j0 + u * kThreads < unsigned(A.Lg)) win[j0 + u * kThreads] = v[u];
     }
   }
   __syncthreads();
   // 2. fold: bin k = l + T e of position n
-  const int p = wave * TPW + tt, n = nf + p;
+  // the same p on every lane of a wavefront when TPW = 1
+  const int p = TPW == 1 ? __builtin_amdgcn_readfirstlane(wave) : wave * TPW + tt, n = nf + p;
   const FirPos q = fir_pos(A, n < A.N ? n : A.N - 1);
   const int M = A.M, PM = A.lam2 * A.M, tstep = M * q.kn;   // tap phase step, < PM
   const C* sp = lds + p * A.a;

@@ -783,6 +783,10 @@ FirArgs<C> fir_args(const Plan& P) {
   A.R = block_width(P.M | 1, sizeof(C)); A.Sm = int(P.M | 1);
   A.fm = sched(P.fm);
   A.lay = coef_layout(P);
+  const unsigned long long all = ~0ULL;
+  A.muM = all / (unsigned long long)P.M;
+  A.muL2 = all / (unsigned long long)P.lam2;
+  A.muPM = all / ((unsigned long long)P.lam2 * (unsigned long long)P.M);
   return A;
 }
 
