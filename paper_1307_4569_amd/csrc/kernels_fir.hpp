@@ -181,9 +181,21 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd_w(FirArgs<C> A) {
 // exchange areas: a barrier separates the fold from the transforms.
 // grid (ceil(N / (8 TPW)), B), 512 threads; LDS max(exchange, (S + L_g) C).
 // ----------------------------------------------------------------------------
+// FP32 with M = 1024: the half-size exchange (wave_fft_h), about 36 KB of LDS
+// per work-group and at most 80 VGPRs, so that three work-groups share a
+// compute unit and one's loads overlap another's transforms (forward and the
+// inverse DFTs of the adjoint).
+template <typename C, int MI> struct FirWs {
+  static constexpr bool HALF = MI == 1024 && sizeof(C) == 8;
+  static constexpr int EX = HALF ? WExH<C>::EX : WEx<C, MI>::EX;   // per transform
+  static constexpr int WAVES_PER_EU = HALF ? 6 : 4;
+  static constexpr int WAVES_PER_EU_ADJ = HALF ? 6 : 4;
+};
+
 template <typename C, int MI, bool HS, int NT>
-__global__ void __launch_bounds__(kThreads, 4) k_fir_fwd_ws(FirArgs<C> A) {
+__global__ void __launch_bounds__(kThreads, (FirWs<C, MI>::WAVES_PER_EU)) k_fir_fwd_ws(FirArgs<C> A) {
   using I = WInfo<MI>;
+  using F = FirWs<C, MI>;
   constexpr int E = I::E, T = I::T, TPW = I::TPW, P = 8 * TPW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
@@ -304,11 +316,16 @@ __global__ void __launch_bounds__(kThreads, 4) k_fir_fwd_ws(FirArgs<C> A) {
       v[e] = cmul(v[e], A.ph[be]);
     }
   }
-  WTw<C, MI> tw;
-  tw.load(A.twm, l);
-  __syncthreads();   // the exchange areas alias the span and the window
-  C* ex = lds + (wave * TPW + tt) * WEx<C, MI>::EX;
-  wave_fft<C, MI, false>(v, ex, l, tw);
+  C* ex = lds + (wave * TPW + tt) * F::EX;
+  if constexpr (F::HALF) {
+    __syncthreads();   // the exchange areas alias the span and the window
+    wave_fft_h<C, false>(v, ex, l, A.twm);
+  } else {
+    WTw<C, MI> tw;
+    tw.load(A.twm, l);
+    __syncthreads();
+    wave_fft<C, MI, false>(v, ex, l, tw);
+  }
   if (n < A.N) {
     int cnt, ee;
     C* row = (A.list ? pick(A.cl, int(bo)) : A.c + bo * A.cs) + coef_col(A.lay, n, &cnt, &ee);
@@ -363,8 +380,10 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd(FirArgs<C> A) {
 // grid (ceil(N / (8 TPW)), B), 512 threads.
 // ----------------------------------------------------------------------------
 template <typename C, int MI>
-__global__ void __launch_bounds__(kThreads) k_fir_adj_rows_w(FirArgs<C> A, C* Y, long long ys) {
+__global__ void __launch_bounds__(kThreads, (FirWs<C, MI>::WAVES_PER_EU_ADJ)) k_fir_adj_rows_w(FirArgs<C> A, C* Y,
+                                                                                long long ys) {
   using I = WInfo<MI>;
+  using F = FirWs<C, MI>;
   constexpr int E = I::E, T = I::T, TPW = I::TPW;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
@@ -378,10 +397,14 @@ __global__ void __launch_bounds__(kThreads) k_fir_adj_rows_w(FirArgs<C> A, C* Y,
   C v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = coef_load(cb, MI, col, cnt, ee, l + T * e);
-  WTw<C, MI> tw;
-  tw.load(A.twm, l);
-  C* ex = lds + (wave * TPW + tt) * WEx<C, MI>::EX;
-  wave_fft<C, MI, true>(v, ex, l, tw);
+  C* ex = lds + (wave * TPW + tt) * F::EX;
+  if constexpr (F::HALF) {
+    wave_fft_h<C, true>(v, ex, l, A.twm);
+  } else {
+    WTw<C, MI> tw;
+    tw.load(A.twm, l);
+    wave_fft<C, MI, true>(v, ex, l, tw);
+  }
   if (ok) {
     C* yr = Y + bo * ys + (long long)n * MI;
 #pragma unroll

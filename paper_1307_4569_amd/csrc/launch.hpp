@@ -800,7 +800,7 @@ int run_fir_fwd_w2(const FirArgs<C>& A, const Plan& P, long long B, hipStream_t 
   // span and window in LDS when they fit beside the exchange areas' size
   const size_t need = sizeof(C) * size_t((8 * I::TPW - 1) * P.a + 2 * P.fir_len);
   if (need <= std::max(lds, size_t(40960))) {
-    const size_t lw = std::max(lds, need);
+    const size_t lw = std::max(sizeof(C) * 8 * I::TPW * FirWs<C, MI>::EX, need);
     if (nt <= 1) return launch(k_fir_fwd_ws<C, MI, HS, 1>, grid, lw, st, A, "FIR DGT");
     if (nt <= 2) return launch(k_fir_fwd_ws<C, MI, HS, 2>, grid, lw, st, A, "FIR DGT");
     if (nt <= 4) return launch(k_fir_fwd_ws<C, MI, HS, 4>, grid, lw, st, A, "FIR DGT");
@@ -848,7 +848,7 @@ int run_fir_fwd(const Plan& P, const void* f, int real_in, C* c, long long B, hi
 template <typename C, int MI>
 int run_fir_adj_rows_w(const FirArgs<C>& A, const Plan& P, long long B, C* Y, long long ys, hipStream_t st) {
   using I = WInfo<MI>;
-  const size_t lds = sizeof(C) * 8 * I::TPW * WEx<C, MI>::EX;
+  const size_t lds = sizeof(C) * 8 * I::TPW * FirWs<C, MI>::EX;
   return launch_v(k_fir_adj_rows_w<C, MI>, dim3(cdiv(P.N, 8 * I::TPW), unsigned(B)), lds, st,
                        "FIR adjoint, inverse DFTs", A, Y, ys);
 }

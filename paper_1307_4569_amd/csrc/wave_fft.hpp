@@ -188,4 +188,69 @@ __device__ __forceinline__ void wave_fft(C (&v)[WInfo<N>::E], C* ex, int l, cons
   wave_pass<C, N, INV, 0>(v, ex, l, tw);
 }
 
+// Length-1024 transform with a half-size exchange region and the twiddles of
+// each pass read when the pass runs, for kernels that need the LDS and the
+// registers for more resident work-groups (one transform per wavefront).  In
+// the two exchanges of this schedule (radix 8, 8, 16; two butterflies per
+// lane) butterfly i of every lane fills exactly half i of the pass output
+// (positions [512 i, 512 i + 512)), and elements e < 8 of the next pass are
+// read from half 0, e >= 8 from half 1: the halves go through one region
+// of WExH elements in turn.
+template <typename C> struct WExH {
+  static constexpr int ES = sizeof(C);
+  using X0 = XPad<ES, 1024, 1>;
+  using X1 = XPad<ES, 1024, 8>;
+  static constexpr int n0 = 512 + X0::c * (511 >> X0::s);
+  static constexpr int n1 = 512 + X1::c * (511 >> X1::s);
+  static constexpr int EX = n0 > n1 ? n0 : n1;
+};
+
+template <typename C, bool INV, int P>
+__device__ __forceinline__ void wave_pass_h(C (&v)[16], C* ex, int l, const C* tab) {
+  constexpr int N = 1024, E = 16, T = 64;
+  using S = WSched<N>;
+  constexpr int R = S::rad(P), Ns = WInfo<N>::ns(P), NB = E / R, step = N / (Ns * R);
+  constexpr bool LAST = P == S::NP - 1;
+  static_assert(LAST || NB == 2, "two butterflies per lane before the last pass");
+  using XP = XPad<int(sizeof(C)), N, Ns>;
+  C u[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[i][r] = v[i + r * NB];
+    if constexpr (P > 0) {
+      const int k = (l + T * i) & (Ns - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const C w = tab[r * k * step];
+        u[i][r] = INV ? cmulc(u[i][r], w) : cmul(u[i][r], w);
+      }
+    }
+    Bfly<C, R, INV>::run(u[i]);
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = u[0][r];
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = l + T * h, k = j & (Ns - 1);
+      const int base = (j - k) * R + k - h * (N / 2);
+#pragma unroll
+      for (int r = 0; r < R; ++r) ex[XP::at(base + r * Ns)] = u[h][r];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int e = 0; e < E / 2; ++e) v[h * (E / 2) + e] = ex[XP::at(l + T * e)];
+      __builtin_amdgcn_wave_barrier();
+    }
+    wave_pass_h<C, INV, P + 1>(v, ex, l, tab);
+  }
+}
+
+// tab: the length-1024 table exp(-2 pi i e / 1024); ex: WExH<C>::EX elements
+template <typename C, bool INV>
+__device__ __forceinline__ void wave_fft_h(C (&v)[16], C* ex, int l, const C* tab) {
+  wave_pass_h<C, INV, 0>(v, ex, l, tab);
+}
+
 }  // namespace dgtns
