@@ -497,8 +497,9 @@ def test_float_reciprocal_quotient_is_exact():
 
 def test_barrett_reduction_of_the_index_maps():
     """The frequency-shear index map reduces 64-bit products modulo 2N, N
-    and L and divides by b through Barrett reduction with mu = floor((2^64 -
-    1) / m): the quotient estimate floor(x mu / 2^64) is at most 2 below
+    and L and divides by b, and the FIR positions reduce modulo M, lambda2
+    and lambda2 M, through Barrett reduction with mu = floor((2^64 - 1) /
+    m): the quotient estimate floor(x mu / 2^64) is at most 2 below
     floor(x / m), so two corrections give x mod m and x // m exactly.  The
     same steps in Python integers, on the edge cases and random dividends."""
     import random
