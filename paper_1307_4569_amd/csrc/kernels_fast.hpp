@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd_cols_w(ColArgs<C> A) {
 #pragma unroll
         for (int e = 0; e < E; ++e) Y[k][e] = cmul(X[k][e], Z[k][e]);
       }
-      if (SEP && n0 + 1 < n0_end) zload(n0 + 1);
+      if (SEP) zload(n0 + 1 < n0_end ? n0 + 1 : n0);   // unconditional: no register copies of Z
 #pragma unroll
       for (int k = 0; k < K; ++k) wave_fft<C, D, true>(Y[k], ex, l, tw);
       // SEP: every thread has read the previous offset's tile; otherwise the
