@@ -536,7 +536,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_rows_w(RowArgs<C> A) {
   constexpr int E = I::E, T = I::T, K = F::K, RB = F::RB, SR = F::SR;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, tt = lane / T, l = lane - tt * T;
+  // the wave index through readfirstlane: when one transform fills the
+  // wavefront, its row indices, phase and rotation loads and row addresses
+  // stay on the scalar unit
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, tt = lane / T, l = lane - tt * T;
   const int q = A.q, d = A.d;
   const int n0 = blockIdx.x % q, t0 = (blockIdx.x / q) * RB;
   const long long bo = blockIdx.y;
