@@ -676,7 +676,8 @@ def main():
         log("copied 3 x 1 GiB")
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU (batches and requests shard across "
+                                   "GPUs with no exchange, one process per GPU); use --gpus 1"}))
         sys.exit(2)
     if args.profile_serve > 0:
         import torch
