@@ -181,15 +181,15 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd_w(FirArgs<C> A) {
 // exchange areas: a barrier separates the fold from the transforms.
 // grid (ceil(N / (8 TPW)), B), 512 threads; LDS max(exchange, (S + L_g) C).
 // ----------------------------------------------------------------------------
-// FP32 with M = 1024: the half-size exchange (wave_fft_h), about 36 KB of LDS
-// per work-group and at most 80 VGPRs, so that three work-groups share a
-// compute unit and one's loads overlap another's transforms (forward and the
-// inverse DFTs of the adjoint).
+// FP32 with M = 1024: the half-size exchange (wave_fft_h, 36352 bytes of LDS
+// for the eight wavefronts instead of 73216) and at most 80 VGPRs, so that
+// three work-groups share a compute unit and one's loads overlap another's
+// transforms (forward, whose staged span and window may need a little more
+// LDS, and the inverse DFTs of the adjoint).
 template <typename C, int MI> struct FirWs {
   static constexpr bool HALF = MI == 1024 && sizeof(C) == 8;
   static constexpr int EX = HALF ? WExH<C>::EX : WEx<C, MI>::EX;   // per transform
   static constexpr int WAVES_PER_EU = HALF ? 6 : 4;
-  static constexpr int WAVES_PER_EU_ADJ = HALF ? 6 : 4;
 };
 
 template <typename C, int MI, bool HS, int NT>
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(kThreads) k_fir_fwd(FirArgs<C> A) {
 // grid (ceil(N / (8 TPW)), B), 512 threads.
 // ----------------------------------------------------------------------------
 template <typename C, int MI>
-__global__ void __launch_bounds__(kThreads, (FirWs<C, MI>::WAVES_PER_EU_ADJ)) k_fir_adj_rows_w(FirArgs<C> A, C* Y,
+__global__ void __launch_bounds__(kThreads, (FirWs<C, MI>::WAVES_PER_EU)) k_fir_adj_rows_w(FirArgs<C> A, C* Y,
                                                                                 long long ys) {
   using I = WInfo<MI>;
   using F = FirWs<C, MI>;
